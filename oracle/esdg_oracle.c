@@ -1,0 +1,668 @@
+/*
+ * esdg_oracle.c -- plain, slow, obviously-correct CPU oracle for the
+ * flux-differencing LGL-DGSEM semi-discretisation of the compressible Euler
+ * equations (Ranocha et al., "Efficient implementation of modern entropy
+ * stable and kinetic energy preserving discontinuous Galerkin methods for
+ * conservation laws").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
+ * call this file: only the test-suite, the smoke check and the CPU-baseline leg
+ * of the benchmark use it.  It shares no code with the HIP library.
+ *
+ * Everything is FP64 and written as the paper's definitions, without the
+ * optimisations the paper proposes:
+ *   - the volume term is the flux-differencing sum with 2*D over ALL k
+ *     (Sec. 2, flux-differencing form of the strong DG scheme), not the
+ *     skew-symmetric D~ form of Sec. 2.1, and no i<k halving (Sec. 2.2);
+ *   - the surface term is M^-1 R^T B (f_num - sum_j N_j R f^j) (same form),
+ *     evaluated per element side, not once per face;
+ *   - two-point fluxes take conservative variables and recompute primitive
+ *     variables on every call (no precomputed primitives or logarithms,
+ *     Sec. 7.1/7.2);
+ *   - time stepping is the textbook classical RK4 with k-vectors.
+ * OpenMP is used only across elements, which does not change any result.
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   R1  D from the closed-form Legendre expression with the textbook diagonal
+ *       D_00 = -p(p+1)/4, D_pp = p(p+1)/4, D_ii = 0 otherwise.
+ *   R2  entropy U = -rho*s/(gamma-1), s = ln p - gamma ln rho.
+ *   R3  log-mean cutoff: series iff u < 1e-4 (strict).
+ *   R7  LLF: 0.5(f(u-)+f(u+)).n - 0.5*lam*(u+ - u-),
+ *       lam = max(|v-.n|,|v+.n|) + max(c-,c+)*|n|.
+ *   R8  curvilinear surface term uses the contravariant (non-unit) normal Ja^n.
+ *   R9  one normal per face: the average of the two sides' Ja^n.
+ *   R10 3D metrics in the conservative curl form; J = det(dx/dxi) from
+ *       collocation derivatives.
+ *   R14 warp: x_m = xhat_m + warp*prod_j sin(pi*s_j), s_j in [-1,1] the
+ *       global box coordinate.
+ *   R17 CFL: dt = cfl*2/((p+1)*max_i sum_n (|v.Ja^n| + c|Ja^n|)/J_i).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAXN 16 /* at most degree 15 */
+
+enum { ORC_RANOCHA = 0, ORC_SHIMA = 1, ORC_LLF = 2, ORC_CENTRAL = 3 };
+
+typedef struct {
+  int32_t dim, p, n[3];
+  double lo[3], hi[3];
+  double warp, gamma;
+  int32_t vol_flux, surf_flux;
+} orc_desc;
+
+typedef struct {
+  orc_desc d;
+  int N;        /* nodes per line */
+  int nn;       /* nodes per element */
+  int64_t ne;   /* elements */
+  int nv;       /* conserved variables */
+  double xi[ORC_MAXN], w[ORC_MAXN], D[ORC_MAXN * ORC_MAXN];
+  double *x;    /* [ne][dim][nn] physical node coordinates */
+  double *Ja;   /* [ne][3][3][nn]: Ja[e][n][m][i] = (Ja)^n_m at node i */
+  double *J;    /* [ne][nn] */
+} orc_mesh;
+
+/* ------------------------------------------------------------------------ */
+/* 1D LGL operators (Sec. 2, LGL-DGSEM example; textbook closed forms)      */
+/* ------------------------------------------------------------------------ */
+
+/* Legendre P_p and its first two derivatives at x, by the three-term
+ * recurrence, in long double. */
+static void legendre(int p, long double x, long double *P, long double *dP,
+                     long double *d2P) {
+  long double p0 = 1.0L, p1 = x, dp0 = 0.0L, dp1 = 1.0L, d2p0 = 0.0L,
+              d2p1 = 0.0L;
+  if (p == 0) {
+    *P = 1.0L; *dP = 0.0L; *d2P = 0.0L;
+    return;
+  }
+  for (int k = 2; k <= p; ++k) {
+    long double pk = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+    long double dpk = dp0 + (2 * k - 1) * p1;           /* P'_k = P'_{k-2} + (2k-1)P_{k-1} */
+    long double d2pk = d2p0 + (2 * k - 1) * dp1;
+    p0 = p1; p1 = pk; dp0 = dp1; dp1 = dpk; d2p0 = d2p1; d2p1 = d2pk;
+  }
+  *P = p1; *dP = dp1; *d2P = d2p1;
+}
+
+/* LGL nodes xi (ascending), weights w and the nodal derivative matrix D
+ * (row-major D[i*N+j]) for degree p.  Interior nodes are the roots of P'_p,
+ * found by Newton's method from Chebyshev-Gauss-Lobatto guesses. */
+int orc_lgl(int p, double *xi, double *w, double *D) {
+  if (p < 1 || p >= ORC_MAXN) return -1;
+  int N = p + 1;
+  long double x[ORC_MAXN], Pp[ORC_MAXN];
+  x[0] = -1.0L; x[p] = 1.0L;
+  for (int i = 1; i < p; ++i) {
+    long double t = -cosl(3.14159265358979323846264338327950288L * i / p);
+    for (int it = 0; it < 100; ++it) {
+      long double P, dP, d2P;
+      legendre(p, t, &P, &dP, &d2P);
+      long double dt = dP / d2P;
+      t -= dt;
+      if (fabsl(dt) < 1e-19L) break;
+    }
+    x[i] = t;
+  }
+  /* symmetrise exactly: x_{p-i} = -x_i */
+  for (int i = 0; i < N / 2; ++i) {
+    long double s = 0.5L * (x[p - i] - x[i]);
+    x[i] = -s; x[p - i] = s;
+  }
+  if (N % 2 == 1) x[p / 2] = 0.0L;
+  for (int i = 0; i < N; ++i) {
+    long double P, dP, d2P;
+    legendre(p, x[i], &P, &dP, &d2P);
+    Pp[i] = P;
+    xi[i] = (double)x[i];
+    w[i] = (double)(2.0L / ((long double)p * (p + 1) * P * P));
+  }
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      long double v;
+      if (i != j) v = Pp[i] / (Pp[j] * (x[i] - x[j]));
+      else if (i == 0) v = -(long double)p * (p + 1) / 4.0L;
+      else if (i == p) v = (long double)p * (p + 1) / 4.0L;
+      else v = 0.0L;
+      D[i * N + j] = (double)v;
+    }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Logarithmic means (Sec. 3.1, Algorithms 2 and 3)                         */
+/* ------------------------------------------------------------------------ */
+
+double orc_logmean(double am, double ap) {
+  double u = (am * (am - 2.0 * ap) + ap * ap) / (am * (am + 2.0 * ap) + ap * ap);
+  double eps = 1.0e-4;
+  if (u < eps)
+    return (am + ap) / (2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0))));
+  return (ap - am) / log(ap / am);
+}
+
+double orc_inv_logmean(double am, double ap) {
+  double u = (am * (am - 2.0 * ap) + ap * ap) / (am * (am + 2.0 * ap) + ap * ap);
+  double eps = 1.0e-4;
+  if (u < eps)
+    return (2.0 + u * (2.0 / 3.0 + u * (2.0 / 5.0 + u * (2.0 / 7.0)))) / (am + ap);
+  return log(ap / am) / (ap - am);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Compressible Euler (Sec. 3, ideal gas)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* conservative u = (rho, rho v_1..rho v_d, rho e) -> rho, v[3], p */
+static void primitives(int dim, double g, const double *u, double *rho,
+                       double v[3], double *p) {
+  double r = u[0];
+  double kin = 0.0;
+  v[0] = v[1] = v[2] = 0.0;
+  for (int m = 0; m < dim; ++m) {
+    v[m] = u[1 + m] / r;
+    kin += u[1 + m] * v[m];
+  }
+  *rho = r;
+  *p = (g - 1.0) * (u[dim + 1] - 0.5 * kin);
+}
+
+/* physical flux in direction n (not necessarily unit): sum_j n_j f^j(u) */
+void orc_phys_flux(int dim, double g, const double *u, const double *n,
+                   double *f) {
+  double rho, v[3], p;
+  primitives(dim, g, u, &rho, v, &p);
+  double vn = 0.0;
+  for (int m = 0; m < dim; ++m) vn += v[m] * n[m];
+  f[0] = rho * vn;
+  for (int m = 0; m < dim; ++m) f[1 + m] = rho * v[m] * vn + p * n[m];
+  f[dim + 1] = (u[dim + 1] + p) * vn;
+}
+
+/* Directional two-point fluxes, arguments (u_-, u_+, n) in this order
+ * (Sec. 3.2; Def. of numerical fluxes in Sec. 2). */
+static void flux_shima(int dim, double g, const double *um, const double *up,
+                       const double *n, double *f) {
+  double rm, rp, vm[3], vp[3], pm, pp;
+  primitives(dim, g, um, &rm, vm, &pm);
+  primitives(dim, g, up, &rp, vp, &pp);
+  double vnm = 0.0, vnp = 0.0, vv = 0.0;
+  for (int m = 0; m < dim; ++m) {
+    vnm += vm[m] * n[m];
+    vnp += vp[m] * n[m];
+    vv += vm[m] * vp[m];
+  }
+  double rho_avg = 0.5 * (rm + rp);
+  double vn_avg = 0.5 * (vnm + vnp);
+  double p_avg = 0.5 * (pm + pp);
+  double frho = rho_avg * vn_avg;
+  f[0] = frho;
+  for (int m = 0; m < dim; ++m) f[1 + m] = frho * 0.5 * (vm[m] + vp[m]) + p_avg * n[m];
+  /* ((v;v)) = (v+ . v- + v- . v+)/2 = v- . v+ ; ((p; v.n)) = (p+ vn- + p- vn+)/2 */
+  f[dim + 1] = frho * vv / 2.0 + p_avg * vn_avg / (g - 1.0) +
+               0.5 * (pp * vnm + pm * vnp);
+}
+
+static void flux_ranocha(int dim, double g, const double *um, const double *up,
+                         const double *n, double *f) {
+  double rm, rp, vm[3], vp[3], pm, pp;
+  primitives(dim, g, um, &rm, vm, &pm);
+  primitives(dim, g, up, &rp, vp, &pp);
+  double vnm = 0.0, vnp = 0.0, vv = 0.0;
+  for (int m = 0; m < dim; ++m) {
+    vnm += vm[m] * n[m];
+    vnp += vp[m] * n[m];
+    vv += vm[m] * vp[m];
+  }
+  double rho_log = orc_logmean(rm, rp);
+  double vn_avg = 0.5 * (vnm + vnp);
+  double p_avg = 0.5 * (pm + pp);
+  double frho = rho_log * vn_avg;
+  /* 1/{{rho/p}}_log = p+ p- / {{rho- p+, rho+ p-}}_log  (Sec. 3.2) */
+  double inv_rho_p_log = pp * pm * orc_inv_logmean(rm * pp, rp * pm);
+  f[0] = frho;
+  for (int m = 0; m < dim; ++m) f[1 + m] = frho * 0.5 * (vm[m] + vp[m]) + p_avg * n[m];
+  f[dim + 1] = frho * vv / 2.0 + frho * inv_rho_p_log / (g - 1.0) +
+               0.5 * (pp * vnm + pm * vnp);
+}
+
+static void flux_central(int dim, double g, const double *um, const double *up,
+                         const double *n, double *f) {
+  double fm[5], fp[5];
+  orc_phys_flux(dim, g, um, n, fm);
+  orc_phys_flux(dim, g, up, n, fp);
+  for (int v = 0; v < dim + 2; ++v) f[v] = 0.5 * (fm[v] + fp[v]);
+}
+
+static void flux_llf(int dim, double g, const double *um, const double *up,
+                     const double *n, double *f) {
+  double rm, rp, vm[3], vp[3], pm, pp;
+  primitives(dim, g, um, &rm, vm, &pm);
+  primitives(dim, g, up, &rp, vp, &pp);
+  double vnm = 0.0, vnp = 0.0, nn = 0.0;
+  for (int m = 0; m < dim; ++m) {
+    vnm += vm[m] * n[m];
+    vnp += vp[m] * n[m];
+    nn += n[m] * n[m];
+  }
+  double cm = sqrt(g * pm / rm), cp = sqrt(g * pp / rp);
+  double lam = fmax(fabs(vnm), fabs(vnp)) + fmax(cm, cp) * sqrt(nn);
+  double fc[5];
+  flux_central(dim, g, um, up, n, fc);
+  for (int v = 0; v < dim + 2; ++v) f[v] = fc[v] - 0.5 * lam * (up[v] - um[v]);
+}
+
+void orc_two_point(int kind, int dim, double g, const double *um,
+                   const double *up, const double *n, double *f) {
+  switch (kind) {
+    case ORC_RANOCHA: flux_ranocha(dim, g, um, up, n, f); break;
+    case ORC_SHIMA: flux_shima(dim, g, um, up, n, f); break;
+    case ORC_LLF: flux_llf(dim, g, um, up, n, f); break;
+    default: flux_central(dim, g, um, up, n, f); break;
+  }
+}
+
+/* entropy variables for U = -rho s/(gamma-1), s = ln p - gamma ln rho (R2) */
+void orc_entropy_vars(int dim, double g, const double *u, double *w) {
+  double rho, v[3], p;
+  primitives(dim, g, u, &rho, v, &p);
+  double s = log(p) - g * log(rho);
+  double v2 = 0.0;
+  for (int m = 0; m < dim; ++m) v2 += v[m] * v[m];
+  w[0] = (g - s) / (g - 1.0) - 0.5 * rho * v2 / p;
+  for (int m = 0; m < dim; ++m) w[1 + m] = rho * v[m] / p;
+  w[dim + 1] = -rho / p;
+}
+
+/* entropy U and entropy flux in direction n: F.n = U (v.n) (R2) */
+void orc_entropy(int dim, double g, const double *u, const double *n,
+                 double *U, double *Fn) {
+  double rho, v[3], p;
+  primitives(dim, g, u, &rho, v, &p);
+  double s = log(p) - g * log(rho);
+  double vn = 0.0;
+  for (int m = 0; m < dim; ++m) vn += v[m] * n[m];
+  *U = -rho * s / (g - 1.0);
+  *Fn = *U * vn;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh: node coordinates and metric terms (Sec. 2.3)                        */
+/* ------------------------------------------------------------------------ */
+
+static int ipow(int b, int e) {
+  int r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
+
+/* multi-index of node i (x fastest) */
+static void node_index(int N, int dim, int i, int idx[3]) {
+  idx[0] = i % N;
+  idx[1] = dim > 1 ? (i / N) % N : 0;
+  idx[2] = dim > 2 ? i / (N * N) : 0;
+}
+
+static int node_of(int N, int dim, const int idx[3]) {
+  int i = idx[0];
+  if (dim > 1) i += N * idx[1];
+  if (dim > 2) i += N * N * idx[2];
+  return i;
+}
+
+static void elem_index(const orc_desc *d, int64_t e, int ie[3]) {
+  ie[0] = (int)(e % d->n[0]);
+  ie[1] = d->dim > 1 ? (int)((e / d->n[0]) % d->n[1]) : 0;
+  ie[2] = d->dim > 2 ? (int)(e / ((int64_t)d->n[0] * d->n[1])) : 0;
+}
+
+static int64_t elem_of(const orc_desc *d, const int ie[3]) {
+  int64_t e = ie[0];
+  if (d->dim > 1) e += (int64_t)d->n[0] * ie[1];
+  if (d->dim > 2) e += (int64_t)d->n[0] * d->n[1] * ie[2];
+  return e;
+}
+
+/* neighbour of element e in direction n, side s = +1 or -1 (periodic) */
+static int64_t neighbour(const orc_desc *d, int64_t e, int n, int s) {
+  int ie[3];
+  elem_index(d, e, ie);
+  ie[n] = (ie[n] + s + d->n[n]) % d->n[n];
+  return elem_of(d, ie);
+}
+
+/* apply the reference derivative in direction dir to nodal field a -> b */
+static void ref_deriv(const orc_mesh *m, int dir, const double *a, double *b) {
+  int N = m->N, dim = m->d.dim;
+  for (int i = 0; i < m->nn; ++i) {
+    int idx[3], jdx[3];
+    node_index(N, dim, i, idx);
+    double s = 0.0;
+    for (int k = 0; k < N; ++k) {
+      memcpy(jdx, idx, sizeof(idx));
+      jdx[dir] = k;
+      s += m->D[idx[dir] * N + k] * a[node_of(N, dim, jdx)];
+    }
+    b[i] = s;
+  }
+}
+
+/* metric terms of one element from its node coordinates X[m][i] */
+static void element_metrics(const orc_mesh *m, const double *X, double *Ja,
+                            double *J) {
+  int dim = m->d.dim, nn = m->nn;
+  /* covariant derivatives dX[j][mm][i] = (D_j X_mm)_i */
+  double *dX = (double *)malloc(sizeof(double) * 9 * nn);
+  for (int j = 0; j < dim; ++j)
+    for (int mm = 0; mm < dim; ++mm) ref_deriv(m, j, X + mm * nn, dX + (j * 3 + mm) * nn);
+  for (int q = 0; q < 9 * nn; ++q) Ja[q] = 0.0;
+  if (dim == 1) {
+    for (int i = 0; i < nn; ++i) Ja[i] = 1.0;
+  } else if (dim == 2) {
+    /* cross-product form (Sec. 2.3) */
+    for (int i = 0; i < nn; ++i) {
+      Ja[(0 * 3 + 0) * nn + i] = dX[(1 * 3 + 1) * nn + i];  /* (Ja)^1_1 =  D_2 x^2 */
+      Ja[(0 * 3 + 1) * nn + i] = -dX[(1 * 3 + 0) * nn + i]; /* (Ja)^1_2 = -D_2 x^1 */
+      Ja[(1 * 3 + 0) * nn + i] = -dX[(0 * 3 + 1) * nn + i]; /* (Ja)^2_1 = -D_1 x^2 */
+      Ja[(1 * 3 + 1) * nn + i] = dX[(0 * 3 + 0) * nn + i];  /* (Ja)^2_2 =  D_1 x^1 */
+    }
+  } else {
+    /* conservative curl form:
+     * (Ja)^i_n = D_{i+2}(X_l D_{i+1} X_m) - D_{i+1}(X_l D_{i+2} X_m),
+     * (n, m, l) cyclic, directions counted modulo 3. */
+    double *t1 = (double *)malloc(sizeof(double) * nn);
+    double *t2 = (double *)malloc(sizeof(double) * nn);
+    double *g1 = (double *)malloc(sizeof(double) * nn);
+    double *g2 = (double *)malloc(sizeof(double) * nn);
+    for (int i = 0; i < 3; ++i) {
+      int i1 = (i + 1) % 3, i2 = (i + 2) % 3;
+      for (int n = 0; n < 3; ++n) {
+        int mm = (n + 1) % 3, l = (n + 2) % 3;
+        for (int q = 0; q < nn; ++q) {
+          t1[q] = X[l * nn + q] * dX[(i1 * 3 + mm) * nn + q];
+          t2[q] = X[l * nn + q] * dX[(i2 * 3 + mm) * nn + q];
+        }
+        ref_deriv(m, i2, t1, g1);
+        ref_deriv(m, i1, t2, g2);
+        for (int q = 0; q < nn; ++q) Ja[(i * 3 + n) * nn + q] = g1[q] - g2[q];
+      }
+    }
+    free(t1); free(t2); free(g1); free(g2);
+  }
+  /* J = det(dx/dxi) with (dx/dxi)_{mm j} = D_j x^mm */
+  for (int q = 0; q < nn; ++q) {
+    double a[3][3];
+    for (int mm = 0; mm < 3; ++mm)
+      for (int j = 0; j < 3; ++j)
+        a[mm][j] = (mm < dim && j < dim) ? dX[(j * 3 + mm) * nn + q] : (mm == j ? 1.0 : 0.0);
+    J[q] = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+           a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+           a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+  }
+  free(dX);
+}
+
+/* Default node coordinates: uniform subdivision of the box; the reference
+ * point of node xi in element e is lo + (e + (xi+1)/2) h, optionally warped
+ * by x_m += warp * prod_j sin(pi s_j), s_j the coordinate scaled to [-1,1]. */
+static void default_coords(orc_mesh *m) {
+  const orc_desc *d = &m->d;
+  int dim = d->dim, N = m->N, nn = m->nn;
+  for (int64_t e = 0; e < m->ne; ++e) {
+    int ie[3];
+    elem_index(d, e, ie);
+    for (int i = 0; i < nn; ++i) {
+      int idx[3];
+      node_index(N, dim, i, idx);
+      double xh[3], s[3];
+      for (int j = 0; j < dim; ++j) {
+        double h = (d->hi[j] - d->lo[j]) / d->n[j];
+        xh[j] = d->lo[j] + (ie[j] + 0.5 * (m->xi[idx[j]] + 1.0)) * h;
+        s[j] = 2.0 * (xh[j] - d->lo[j]) / (d->hi[j] - d->lo[j]) - 1.0;
+      }
+      double bump = 1.0;
+      for (int j = 0; j < dim; ++j) bump *= sin(M_PI * s[j]);
+      for (int j = 0; j < dim; ++j)
+        m->x[(e * dim + j) * nn + i] = xh[j] + d->warp * bump;
+    }
+  }
+}
+
+/* Build the mesh; coords (layout [elem][dim][node]) may be NULL. */
+orc_mesh *orc_mesh_new(const orc_desc *desc, const double *coords) {
+  if (desc->dim < 1 || desc->dim > 3 || desc->p < 1 || desc->p >= ORC_MAXN) return NULL;
+  orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
+  m->d = *desc;
+  for (int j = desc->dim; j < 3; ++j) m->d.n[j] = 1;
+  m->N = desc->p + 1;
+  m->nn = ipow(m->N, desc->dim);
+  m->ne = (int64_t)m->d.n[0] * m->d.n[1] * m->d.n[2];
+  m->nv = desc->dim + 2;
+  orc_lgl(desc->p, m->xi, m->w, m->D);
+  m->x = (double *)malloc(sizeof(double) * m->ne * desc->dim * m->nn);
+  m->Ja = (double *)malloc(sizeof(double) * m->ne * 9 * m->nn);
+  m->J = (double *)malloc(sizeof(double) * m->ne * m->nn);
+  if (coords)
+    memcpy(m->x, coords, sizeof(double) * m->ne * desc->dim * m->nn);
+  else
+    default_coords(m);
+  double *X = (double *)malloc(sizeof(double) * 3 * m->nn);
+  for (int64_t e = 0; e < m->ne; ++e) {
+    /* Coordinates relative to the element's first node: the metric terms
+     * only involve derivatives of the coordinates and, in the curl form,
+     * D_a(c D_b X) - D_b(c D_a X) = 0 for a constant c, so the shift leaves
+     * them unchanged while keeping the products X_l D X_m at the element's
+     * own scale instead of the box's (their rounding would otherwise spoil
+     * free-stream preservation on small elements far from the origin). */
+    for (int j = 0; j < 3; ++j) {
+      double c = j < desc->dim ? m->x[(e * desc->dim + j) * m->nn] : 0.0;
+      for (int i = 0; i < m->nn; ++i)
+        X[j * m->nn + i] = j < desc->dim ? m->x[(e * desc->dim + j) * m->nn + i] - c : 0.0;
+    }
+    element_metrics(m, X, m->Ja + e * 9 * m->nn, m->J + e * m->nn);
+  }
+  free(X);
+  return m;
+}
+
+void orc_mesh_free(orc_mesh *m) {
+  if (!m) return;
+  free(m->x); free(m->Ja); free(m->J); free(m);
+}
+
+void orc_mesh_sizes(const orc_mesh *m, int64_t *ne, int32_t *nn, int32_t *nv) {
+  *ne = m->ne; *nn = m->nn; *nv = m->nv;
+}
+
+void orc_mesh_geometry(const orc_mesh *m, double *x, double *Ja, double *J) {
+  if (x) memcpy(x, m->x, sizeof(double) * m->ne * m->d.dim * m->nn);
+  if (Ja) memcpy(Ja, m->Ja, sizeof(double) * m->ne * 9 * m->nn);
+  if (J) memcpy(J, m->J, sizeof(double) * m->ne * m->nn);
+}
+
+void orc_mesh_operators(const orc_mesh *m, double *xi, double *w, double *D) {
+  memcpy(xi, m->xi, sizeof(double) * m->N);
+  memcpy(w, m->w, sizeof(double) * m->N);
+  memcpy(D, m->D, sizeof(double) * m->N * m->N);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Semi-discretisation du/dt = RHS(u)                                       */
+/* ------------------------------------------------------------------------ */
+
+static void gather(const orc_mesh *m, const double *u, int64_t e, int i, double *ui) {
+  for (int v = 0; v < m->nv; ++v) ui[v] = u[(e * m->nv + v) * m->nn + i];
+}
+
+static void ja_row(const orc_mesh *m, int64_t e, int n, int i, double *a) {
+  for (int mm = 0; mm < 3; ++mm) a[mm] = m->Ja[((e * 3 + n) * 3 + mm) * m->nn + i];
+}
+
+/* RHS_i = -(1/J_i) [ sum_n sum_k 2 D_{i_n k} f_vol(u_i, u_k, (Ja^n_i + Ja^n_k)/2)
+ *                    + sum_n (boundary terms of M^-1 R^T B (f* - N f)) ]         */
+void orc_rhs(const orc_mesh *m, const double *u, double *du) {
+  const int dim = m->d.dim, N = m->N, nn = m->nn, nv = m->nv, p = m->d.p;
+  const double g = m->d.gamma;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < m->ne; ++e) {
+    for (int i = 0; i < nn; ++i) {
+      int idx[3];
+      node_index(N, dim, i, idx);
+      double ui[5], acc[5] = {0, 0, 0, 0, 0};
+      gather(m, u, e, i, ui);
+      for (int n = 0; n < dim; ++n) {
+        double ai[3];
+        ja_row(m, e, n, i, ai);
+        /* volume: flux differencing along the line through i in direction n */
+        for (int k = 0; k < N; ++k) {
+          int jdx[3];
+          memcpy(jdx, idx, sizeof(idx));
+          jdx[n] = k;
+          int j = node_of(N, dim, jdx);
+          double uj[5], aj[3], nrm[3], f[5];
+          gather(m, u, e, j, uj);
+          ja_row(m, e, n, j, aj);
+          for (int mm = 0; mm < 3; ++mm) nrm[mm] = 0.5 * (ai[mm] + aj[mm]);
+          orc_two_point(m->d.vol_flux, dim, g, ui, uj, nrm, f);
+          for (int v = 0; v < nv; ++v) acc[v] += 2.0 * m->D[idx[n] * N + k] * f[v];
+        }
+        /* surface: i on the + face (i_n = p) or - face (i_n = 0) */
+        for (int side = 0; side < 2; ++side) {
+          int at = side ? p : 0;
+          if (idx[n] != at) continue;
+          int64_t eo = neighbour(&m->d, e, n, side ? +1 : -1);
+          int odx[3];
+          memcpy(odx, idx, sizeof(idx));
+          odx[n] = side ? 0 : p;
+          int io = node_of(N, dim, odx);
+          double uo[5], ao[3], nf[3], fstar[5], fphys[5];
+          gather(m, u, eo, io, uo);
+          ja_row(m, eo, n, io, ao);
+          for (int mm = 0; mm < 3; ++mm) nf[mm] = 0.5 * (ai[mm] + ao[mm]);
+          orc_phys_flux(dim, g, ui, ai, fphys);
+          if (side) {
+            /* outward reference normal +1: f* = f(u_L = u_i, u_R = u_o, n_f) */
+            orc_two_point(m->d.surf_flux, dim, g, ui, uo, nf, fstar);
+            for (int v = 0; v < nv; ++v) acc[v] += (fstar[v] - fphys[v]) / m->w[p];
+          } else {
+            /* outward reference normal -1: f* = f(u_L = u_o, u_R = u_i, n_f) */
+            orc_two_point(m->d.surf_flux, dim, g, uo, ui, nf, fstar);
+            for (int v = 0; v < nv; ++v) acc[v] += (-fstar[v] + fphys[v]) / m->w[0];
+          }
+        }
+      }
+      double Ji = m->J[e * nn + i];
+      for (int v = 0; v < nv; ++v) du[(e * nv + v) * nn + i] = -acc[v] / Ji;
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reductions (Sec. 2: conservation and entropy of the semi-discretisation)  */
+/* ------------------------------------------------------------------------ */
+
+static double weight(const orc_mesh *m, int i) {
+  int idx[3];
+  node_index(m->N, m->d.dim, i, idx);
+  double W = 1.0;
+  for (int j = 0; j < m->d.dim; ++j) W *= m->w[idx[j]];
+  return W;
+}
+
+/* totals_v = sum_e sum_i J_i W_i u_{i,v} */
+void orc_totals(const orc_mesh *m, const double *u, double *tot) {
+  for (int v = 0; v < m->nv; ++v) {
+    long double s = 0.0L;
+    for (int64_t e = 0; e < m->ne; ++e)
+      for (int i = 0; i < m->nn; ++i)
+        s += (long double)m->J[e * m->nn + i] * weight(m, i) * u[(e * m->nv + v) * m->nn + i];
+    tot[v] = (double)s;
+  }
+}
+
+/* dS/dt = sum J_i W_i w(u_i) . du_i  for a given du (e.g. RHS(u)) */
+double orc_entropy_rate(const orc_mesh *m, const double *u, const double *du) {
+  long double s = 0.0L;
+  for (int64_t e = 0; e < m->ne; ++e)
+    for (int i = 0; i < m->nn; ++i) {
+      double ui[5], w[5];
+      gather(m, u, e, i, ui);
+      orc_entropy_vars(m->d.dim, m->d.gamma, ui, w);
+      double JW = m->J[e * m->nn + i] * weight(m, i);
+      for (int v = 0; v < m->nv; ++v)
+        s += (long double)JW * w[v] * du[(e * m->nv + v) * m->nn + i];
+    }
+  return (double)s;
+}
+
+/* total entropy sum J_i W_i U(u_i) */
+double orc_total_entropy(const orc_mesh *m, const double *u) {
+  long double s = 0.0L;
+  double zero[3] = {0, 0, 0};
+  for (int64_t e = 0; e < m->ne; ++e)
+    for (int i = 0; i < m->nn; ++i) {
+      double ui[5], U, F;
+      gather(m, u, e, i, ui);
+      orc_entropy(m->d.dim, m->d.gamma, ui, zero, &U, &F);
+      s += (long double)m->J[e * m->nn + i] * weight(m, i) * U;
+    }
+  return (double)s;
+}
+
+/* R17: dt = cfl * 2 / ((p+1) max_i sum_n (|v.Ja^n_i| + c_i |Ja^n_i|) / J_i) */
+double orc_max_dt(const orc_mesh *m, const double *u, double cfl) {
+  double lmax = 0.0;
+  for (int64_t e = 0; e < m->ne; ++e)
+    for (int i = 0; i < m->nn; ++i) {
+      double ui[5], rho, v[3], p;
+      gather(m, u, e, i, ui);
+      primitives(m->d.dim, m->d.gamma, ui, &rho, v, &p);
+      double c = sqrt(m->d.gamma * p / rho);
+      double lam = 0.0;
+      for (int n = 0; n < m->d.dim; ++n) {
+        double a[3], vn = 0.0, an = 0.0;
+        ja_row(m, e, n, i, a);
+        for (int mm = 0; mm < m->d.dim; ++mm) {
+          vn += v[mm] * a[mm];
+          an += a[mm] * a[mm];
+        }
+        lam += fabs(vn) + c * sqrt(an);
+      }
+      lam /= m->J[e * m->nn + i];
+      if (lam > lmax) lmax = lam;
+    }
+  return cfl * 2.0 / (m->N * lmax);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Classical RK4 (textbook form with four stage derivatives)                 */
+/* ------------------------------------------------------------------------ */
+
+/* Advance u in place by nsteps steps of size dt (dt > 0), or of the CFL step
+ * size (dt <= 0, recomputed at the start of every step).  t is advanced. */
+void orc_rk4(const orc_mesh *m, double *u, double dt, int nsteps, double cfl,
+             double *t) {
+  size_t len = (size_t)m->ne * m->nv * m->nn;
+  double *k1 = (double *)malloc(sizeof(double) * len);
+  double *k2 = (double *)malloc(sizeof(double) * len);
+  double *k3 = (double *)malloc(sizeof(double) * len);
+  double *k4 = (double *)malloc(sizeof(double) * len);
+  double *y = (double *)malloc(sizeof(double) * len);
+  for (int s = 0; s < nsteps; ++s) {
+    double h = dt > 0.0 ? dt : orc_max_dt(m, u, cfl);
+    orc_rhs(m, u, k1);
+    for (size_t q = 0; q < len; ++q) y[q] = u[q] + 0.5 * h * k1[q];
+    orc_rhs(m, y, k2);
+    for (size_t q = 0; q < len; ++q) y[q] = u[q] + 0.5 * h * k2[q];
+    orc_rhs(m, y, k3);
+    for (size_t q = 0; q < len; ++q) y[q] = u[q] + h * k3[q];
+    orc_rhs(m, y, k4);
+    for (size_t q = 0; q < len; ++q)
+      u[q] = u[q] + h / 6.0 * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+    if (t) *t += h;
+  }
+  free(k1); free(k2); free(k3); free(k4); free(y);
+}

@@ -1,0 +1,277 @@
+"""Pins of the oracle's semi-discretisation du/dt = RHS(u) (Sec. 2: flux
+differencing form, conservation and entropy statements; Sec. 2.3: free-stream
+preservation on curved meshes; Sec. 3.2: pressure-equilibrium preservation).
+
+Each test checks a property the paper or the mathematics fixes:
+  * the central volume flux reduces flux differencing to the strong-form DG
+    scheme, computed here with independently constructed LGL operators;
+  * constant states are steady on warped meshes (free stream);
+  * sum_i J_i W_i RHS_i = 0 on periodic meshes (conservation);
+  * EC volume + EC surface fluxes give dS/dt = 0 to round-off, LLF < 0;
+  * pressure equilibria (constant v, p) stay in equilibrium;
+  * axis permutations and lower-dimensional embeddings commute with RHS;
+  * design-order convergence to the exact density wave; RK4 is 4th order.
+"""
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as L
+
+from paper_2112_10517_amd import inputs
+
+G = 1.4
+
+
+# ---------------------------------------------------------------------------
+# independent LGL operators (numpy roots, barycentric differentiation)
+# ---------------------------------------------------------------------------
+
+def lgl_numpy(p):
+    inner = np.sort(L.Legendre.basis(p).deriv().roots().real) if p > 1 else np.array([])
+    x = np.concatenate([[-1.0], inner, [1.0]])
+    Pp = L.legval(x, [0] * p + [1])
+    w = 2.0 / (p * (p + 1) * Pp ** 2)
+    lam = np.array([1.0 / np.prod([x[i] - x[j] for j in range(p + 1) if j != i]) for i in range(p + 1)])
+    D = np.zeros((p + 1, p + 1))
+    for i in range(p + 1):
+        for j in range(p + 1):
+            if i != j:
+                D[i, j] = lam[j] / lam[i] / (x[i] - x[j])
+        D[i, i] = -np.sum(D[i])
+    return x, w, D
+
+
+def euler_flux(u, axis, dim):
+    # f^axis(u) for u [..., var]
+    rho = u[..., 0]
+    v = u[..., 1:dim + 1] / rho[..., None]
+    p = (G - 1) * (u[..., dim + 1] - 0.5 * rho * np.sum(v * v, axis=-1))
+    f = np.empty_like(u)
+    f[..., 0] = rho * v[..., axis]
+    for m in range(dim):
+        f[..., 1 + m] = rho * v[..., m] * v[..., axis] + (p if m == axis else 0.0)
+    f[..., dim + 1] = (u[..., dim + 1] + p) * v[..., axis]
+    return f
+
+
+def strong_form_central_2d(u, n, p, h):
+    """Strong-form DGSEM with central volume and surface fluxes on a periodic
+    Cartesian 2D mesh: -sum_a (2/h_a) [D_a f^a + M^-1 B (f* - f^a)]."""
+    x, w, D = lgl_numpy(p)
+    N = p + 1
+    E = n[0] * n[1]
+    nv = 4
+    U = np.moveaxis(u.reshape(n[1], n[0], nv, N, N), 2, -1)  # [ey, ex, j, i, var]
+    out = np.zeros_like(U)
+    for a in range(2):
+        f = euler_flux(U, a, 2)
+        ax_node = 3 - a  # node axis of direction a in [ey, ex, j, i, var]
+        ax_elem = 1 - a  # element axis of direction a
+        df = np.moveaxis(np.tensordot(D, np.moveaxis(f, ax_node, 0), axes=(1, 0)), 0, ax_node)
+        fL = np.take(f, N - 1, axis=ax_node)  # trace on the + face of each element
+        fR = np.roll(np.take(f, 0, axis=ax_node), -1, axis=ax_elem)  # - face of + neighbour
+        fstar = 0.5 * (fL + fR)  # central flux on the + face
+        fstar_minus = np.roll(fstar, 1, axis=ax_elem)  # flux on the - face
+        surf = np.zeros_like(U)
+        sl_p = [slice(None)] * 5
+        sl_p[ax_node] = N - 1
+        sl_m = [slice(None)] * 5
+        sl_m[ax_node] = 0
+        surf[tuple(sl_p)] = (fstar - np.take(f, N - 1, axis=ax_node)) / w[-1]
+        surf[tuple(sl_m)] = -(fstar_minus - np.take(f, 0, axis=ax_node)) / w[0]
+        out -= (2.0 / h[a]) * (df + surf)
+    return np.moveaxis(out, -1, 2).reshape(E, nv, N * N)
+
+
+def test_central_flux_is_strong_form(orc):
+    n, p = (5, 3), 3
+    lo, hi = (-1.0, 0.0), (1.0, 1.5)
+    m = orc.Mesh(2, p, n, lo=lo, hi=hi, vol_flux="central", surf_flux="central")
+    rng = np.random.default_rng(0)
+    x = m.coords()
+    u = inputs.random_fourier(x, 11, lo=lo, hi=hi)
+    u *= 1 + 0.01 * rng.standard_normal(u.shape)  # jumps at faces
+    du = m.rhs(u)
+    h = [(hi[j] - lo[j]) / n[j] for j in range(2)]
+    ref = strong_form_central_2d(u, n, p, h)
+    assert np.abs(du - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_shima_density_row_is_linear_advection(orc):
+    # constant velocity: f_rho = {{rho}} v.n is the central flux of rho v,
+    # so the density row equals the strong-form DG derivative of rho v
+    n, p = (4, 6), 4
+    m_s = orc.Mesh(2, p, n, vol_flux="shima", surf_flux="central")
+    m_c = orc.Mesh(2, p, n, vol_flux="central", surf_flux="central")
+    u = inputs.density_wave(m_s.coords(), amp=0.5)
+    a = m_s.rhs(u)[:, 0]
+    b = m_c.rhs(u)[:, 0]
+    assert np.abs(a - b).max() < 1e-12 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("dim,p,n", [(2, 3, (6, 5)), (2, 5, (3, 4)), (3, 3, (4, 3, 5)), (3, 4, (3, 3, 3))])
+@pytest.mark.parametrize("vol", ["ranocha", "shima"])
+def test_free_stream_warped(orc, dim, p, n, vol):
+    m = orc.Mesh(dim, p, n, warp=0.1, vol_flux=vol, surf_flux="llf")
+    E = m.n_elem
+    v = np.array([0.3, -0.2, 0.1][:dim])
+    rho, pr = 1.3, 2.0
+    u = np.zeros(m.shape)
+    u[:, 0] = rho
+    u[:, 1:dim + 1] = rho * v[None, :, None]
+    u[:, dim + 1] = pr / (G - 1) + 0.5 * rho * v @ v
+    du = m.rhs(u)
+    Ja, J = m.metrics()
+    scale = (np.abs(Ja).max() / J.min()) * (pr / (G - 1) + pr + rho) * (p + 1) ** 2
+    assert np.abs(du).max() < 1e-13 * scale, np.abs(du).max() / scale
+
+
+def noisy_state(m, seed, rel=0.02):
+    x = m.coords()
+    u = inputs.random_fourier(x, seed)
+    rng = np.random.default_rng(seed)
+    return u * (1 + rel * rng.standard_normal(u.shape))
+
+
+@pytest.mark.parametrize("dim,warp", [(2, 0.0), (2, 0.1), (3, 0.0), (3, 0.1)])
+@pytest.mark.parametrize("vol,surf", [("ranocha", "llf"), ("shima", "llf"), ("ranocha", "ranocha"),
+                                      ("shima", "shima"), ("central", "central")])
+def test_conservation(orc, dim, warp, vol, surf):
+    n = (4, 3, 3)[:dim]
+    m = orc.Mesh(dim, 3, n, warp=warp, vol_flux=vol, surf_flux=surf)
+    u = noisy_state(m, 3)
+    du = m.rhs(u)
+    _, J = m.metrics()
+    JW = J * m.weights()[None, :]
+    tot = np.einsum("en,evn->v", JW, du)
+    scale = np.einsum("en,evn->v", JW, np.abs(du))
+    assert np.all(np.abs(tot) < 1e-13 * scale), tot / scale
+
+
+@pytest.mark.parametrize("dim,warp", [(2, 0.0), (2, 0.1), (3, 0.0), (3, 0.1)])
+def test_entropy_rate(orc, dim, warp):
+    n = (4, 3, 3)[:dim]
+    ec = orc.Mesh(dim, 3, n, warp=warp, vol_flux="ranocha", surf_flux="ranocha")
+    u = noisy_state(ec, 5)
+    du = ec.rhs(u)
+    _, J = ec.metrics()
+    JW = J * ec.weights()[None, :]
+    w = np.stack([orc.entropy_vars(dim, G, u[e, :, i]) for e in range(ec.n_elem) for i in range(ec.nodes)])
+    w = w.reshape(ec.n_elem, ec.nodes, dim + 2).transpose(0, 2, 1)
+    scale = np.sum(JW[:, None, :] * np.abs(w * du))
+    rate = ec.entropy_rate(u, du)
+    assert abs(rate - np.sum(JW[:, None, :] * w * du)) < 1e-13 * scale
+    assert abs(rate) < 1e-13 * scale, rate / scale
+    llf = orc.Mesh(dim, 3, n, warp=warp, vol_flux="ranocha", surf_flux="llf")
+    assert llf.entropy_rate(u) < -1e-6 * scale
+
+
+@pytest.mark.parametrize("dim,warp", [(2, 0.0), (2, 0.1), (3, 0.0), (3, 0.1)])
+@pytest.mark.parametrize("vol,surf", [("ranocha", "llf"), ("shima", "llf"), ("ranocha", "ranocha"), ("shima", "shima")])
+def test_pressure_equilibrium(orc, dim, warp, vol, surf):
+    m = orc.Mesh(dim, 3, (4, 3, 3)[:dim], warp=warp, vol_flux=vol, surf_flux=surf)
+    u = inputs.density_wave(m.coords())
+    rng = np.random.default_rng(1)
+    # break continuity: pressure equilibria must survive density jumps too
+    rho_noise = 1 + 0.05 * rng.standard_normal(u[:, 0].shape)
+    v = np.array(inputs.DENSITY_WAVE_V[:dim])
+    u[:, 0] *= rho_noise
+    u[:, 1:dim + 1] = u[:, 0][:, None, :] * v[None, :, None]
+    u[:, dim + 1] = 20.0 / (G - 1) + 0.5 * u[:, 0] * (v @ v)
+    du = m.rhs(u)
+    Ja, J = m.metrics()
+    # rounding scale of the energy row: (rho e + p)|v| |Ja|/J (p+1)
+    sc = (20.0 / (G - 1) + 20.0) * np.linalg.norm(v) * np.abs(Ja).max() / J.min() * 4
+    assert np.abs(du[:, 1:dim + 1] - v[None, :, None] * du[:, 0:1]).max() < 1e-13 * sc
+    assert np.abs(du[:, dim + 1] - 0.5 * (v @ v) * du[:, 0]).max() < 1e-13 * sc
+    assert np.abs(du[:, 0]).max() > 1e-3 * sc  # the density row itself is not trivial
+
+
+def test_axis_permutation_equivariance(orc):
+    n, p = (3, 4, 5), 3
+    lo, hi = (-1.0, -2.0, 0.0), (1.0, 2.0, 3.0)
+    m = orc.Mesh(3, p, n, lo=lo, hi=hi, vol_flux="ranocha", surf_flux="llf")
+    u = noisy_state(m, 9)
+    du = m.rhs(u)
+    N = p + 1
+    # swap x and z: element (ex,ey,ez) -> (ez,ey,ex); node (i,j,k) -> (k,j,i)
+    m2 = orc.Mesh(3, p, (n[2], n[1], n[0]), lo=(lo[2], lo[1], lo[0]), hi=(hi[2], hi[1], hi[0]),
+                  vol_flux="ranocha", surf_flux="llf")
+
+    def swap(a):
+        a = a.reshape(n[2], n[1], n[0], 5, N, N, N)  # [ez,ey,ex,var,k,j,i]
+        a = a.transpose(2, 1, 0, 3, 6, 5, 4)
+        a = a[:, :, :, [0, 3, 2, 1, 4]]
+        return a.reshape(-1, 5, N ** 3)
+
+    du2 = m2.rhs(swap(u))
+    assert np.abs(du2 - swap(du)).max() < 1e-13 * np.abs(du).max()
+
+
+def test_two_d_embedded_in_three_d(orc):
+    p, n = 3, (4, 3)
+    m2 = orc.Mesh(2, p, n, vol_flux="ranocha", surf_flux="llf")
+    m3 = orc.Mesh(3, p, (n[0], n[1], 2), vol_flux="ranocha", surf_flux="llf")
+    u2 = noisy_state(m2, 4)
+    du2 = m2.rhs(u2)
+    N = p + 1
+    # extend: constant in z, v_z = 0
+    U = u2.reshape(n[1], n[0], 4, N, N)
+    u3 = np.zeros((2, n[1], n[0], 5, N, N, N))
+    for ez in range(2):
+        for k in range(N):
+            u3[ez, :, :, [0, 1, 2, 4], k] = np.moveaxis(U, 2, 0)
+    du3 = m3.rhs(u3.reshape(-1, 5, N ** 3)).reshape(2, n[1], n[0], 5, N, N, N)
+    # the 3D box is [-1,1]^3 with 2 elements in z: J scales by h_z/2 = 0.5 on both sides
+    for ez in range(2):
+        for k in range(N):
+            got = du3[ez, :, :, [0, 1, 2, 4], k]
+            assert np.abs(got - np.moveaxis(du2.reshape(n[1], n[0], 4, N, N), 2, 0)).max() < 1e-12 * np.abs(du2).max()
+            assert np.abs(du3[ez, :, :, 3, k]).max() < 1e-12 * np.abs(du2).max()
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_convergence_density_wave(orc, p):
+    # smooth exact solution rho(x,t) = 1 + A sin(pi(x+y-2t)) for v = (1,1);
+    # integrated over one period of the domain so that the O(h^p) truncation
+    # error of the initial transient has given way to the O(h^(p+1)) DG error
+    amp, t_end, v, p0 = 0.5, 1.0, (1.0, 1.0), 1.0
+    errs = []
+    for n in (4, 8, 16):
+        m = orc.Mesh(2, p, (n, n), vol_flux="ranocha", surf_flux="llf")
+        x = m.coords()
+        u0 = inputs.density_wave(x, amp=amp, p0=p0, v=v)
+        dt0 = m.max_dt(u0, 0.5)
+        steps = int(np.ceil(t_end / dt0))
+        u, t = m.rk4(u0, t_end / steps, steps)
+        ex = inputs.density_wave(x, amp=amp, t=t, p0=p0, v=v)
+        _, J = m.metrics()
+        JW = J * m.weights()[None, :]
+        errs.append(np.sqrt(np.sum(JW * (u[:, 0] - ex[:, 0]) ** 2) / np.sum(JW)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert rates[-1] > p + 0.5, (errs, rates)
+
+
+def test_rk4_fourth_order_in_time(orc):
+    m = orc.Mesh(2, 3, (3, 3), vol_flux="ranocha", surf_flux="llf")
+    u0 = inputs.density_wave(m.coords(), amp=0.3)
+    T = 0.02
+    sols = [m.rk4(u0, T / s, s)[0] for s in (16, 32, 64, 128)]
+    d = [np.abs(sols[i] - sols[i + 1]).max() for i in range(3)]
+    ratios = [d[i] / d[i + 1] for i in range(2)]
+    assert all(14 < r < 18 for r in ratios), ratios
+    u1, t1 = m.rk4(u0, 0.0, 3, cfl=0.4)
+    assert abs(t1 - 3 * m.max_dt(u0, 0.4)) < 0.05 * t1  # CFL mode advances t
+
+
+def test_totals_and_max_dt(orc):
+    m = orc.Mesh(2, 3, (4, 4), vol_flux="ranocha", surf_flux="llf")
+    u = inputs.density_wave(m.coords(), amp=0.98)
+    tot = m.totals(u)
+    # integral over [-1,1]^2 of rho = 4 (sine integrates to zero), momentum 4*rho*v
+    assert abs(tot[0] - 4.0) < 1e-12 and abs(tot[1] - 0.4) < 1e-12 and abs(tot[2] - 0.8) < 1e-12
+    # CFL: affine 2D, lam = sum_a (|v_a| + c) * 2/h, max at rho_min
+    dt = m.max_dt(u, 1.0)
+    rho = u[:, 0]
+    c = np.sqrt(G * 20.0 / rho)
+    lam = ((0.1 + c) + (0.2 + c)) * 2 / 0.5
+    assert abs(dt - 2.0 / (4 * lam.max())) < 1e-12 * dt
