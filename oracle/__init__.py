@@ -72,6 +72,7 @@ def _load():
         lib.orc_mesh_geometry.argtypes = [C.c_void_p, dp, dp, dp]
         lib.orc_mesh_operators.argtypes = [C.c_void_p, dp, dp, dp]
         lib.orc_rhs.argtypes = [C.c_void_p, dp, dp]
+        lib.orc_rhs_scale.argtypes = [C.c_void_p, dp, dp]
         lib.orc_totals.argtypes = [C.c_void_p, dp, dp]
         lib.orc_entropy_rate.argtypes = [C.c_void_p, dp, dp]
         lib.orc_entropy_rate.restype = C.c_double
@@ -80,6 +81,8 @@ def _load():
         lib.orc_max_dt.argtypes = [C.c_void_p, dp, C.c_double]
         lib.orc_max_dt.restype = C.c_double
         lib.orc_rk4.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, C.c_double, dp]
+        lib.orc_num_threads.argtypes = []
+        lib.orc_num_threads.restype = C.c_int
         _lib = lib
         return lib
 
@@ -91,6 +94,11 @@ def _ptr(a: np.ndarray):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's element loops use."""
+    return _load().orc_num_threads()
 
 
 # --------------------------------------------------------------------------
@@ -226,6 +234,13 @@ class Mesh:
         du = np.empty_like(u)
         self._lib.orc_rhs(self._h, _ptr(u), _ptr(du))
         return du
+
+    def rhs_scale(self, u) -> np.ndarray:
+        """Per-node rounding scale of RHS: the same sums over term magnitudes."""
+        u = self._state(u)
+        sc = np.empty_like(u)
+        self._lib.orc_rhs_scale(self._h, _ptr(u), _ptr(sc))
+        return sc
 
     def totals(self, u) -> np.ndarray:
         u = self._state(u)

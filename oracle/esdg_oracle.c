@@ -38,6 +38,7 @@
  *   R17 CFL: dt = cfl*2/((p+1)*max_i sum_n (|v.Ja^n| + c|Ja^n|)/J_i).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -64,6 +65,9 @@ typedef struct {
   double *Ja;   /* [ne][3][3][nn]: Ja[e][n][m][i] = (Ja)^n_m at node i */
   double *J;    /* [ne][nn] */
 } orc_mesh;
+
+/* threads the element loops use (OpenMP) */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* 1D LGL operators (Sec. 2, LGL-DGSEM example; textbook closed forms)      */
@@ -556,6 +560,60 @@ void orc_rhs(const orc_mesh *m, const double *u, double *du) {
       }
       double Ji = m->J[e * nn + i];
       for (int v = 0; v < nv; ++v) du[(e * nv + v) * nn + i] = -acc[v] / Ji;
+    }
+  }
+}
+
+/* Rounding scale of RHS_i: the same sums as orc_rhs with every term replaced
+ * by its magnitude, sc_i = (1/J_i) [ sum_n sum_k |2 D_{i_n k} f_vol| +
+ * sum_n (|f*| + |f^n(u_i)|)/w_end ].  A floating-point evaluation of RHS_i in
+ * any order has an error of at most a few eps * sc_i; it is the natural
+ * denominator of a relative parity bound where RHS_i itself cancels. */
+void orc_rhs_scale(const orc_mesh *m, const double *u, double *sc) {
+  const int dim = m->d.dim, N = m->N, nn = m->nn, nv = m->nv, p = m->d.p;
+  const double g = m->d.gamma;
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < m->ne; ++e) {
+    for (int i = 0; i < nn; ++i) {
+      int idx[3];
+      node_index(N, dim, i, idx);
+      double ui[5], acc[5] = {0, 0, 0, 0, 0};
+      gather(m, u, e, i, ui);
+      for (int n = 0; n < dim; ++n) {
+        double ai[3];
+        ja_row(m, e, n, i, ai);
+        for (int k = 0; k < N; ++k) {
+          int jdx[3];
+          memcpy(jdx, idx, sizeof(idx));
+          jdx[n] = k;
+          int j = node_of(N, dim, jdx);
+          double uj[5], aj[3], nrm[3], f[5];
+          gather(m, u, e, j, uj);
+          ja_row(m, e, n, j, aj);
+          for (int mm = 0; mm < 3; ++mm) nrm[mm] = 0.5 * (ai[mm] + aj[mm]);
+          orc_two_point(m->d.vol_flux, dim, g, ui, uj, nrm, f);
+          for (int v = 0; v < nv; ++v) acc[v] += fabs(2.0 * m->D[idx[n] * N + k] * f[v]);
+        }
+        for (int side = 0; side < 2; ++side) {
+          int at = side ? p : 0;
+          if (idx[n] != at) continue;
+          int64_t eo = neighbour(&m->d, e, n, side ? +1 : -1);
+          int odx[3];
+          memcpy(odx, idx, sizeof(idx));
+          odx[n] = side ? 0 : p;
+          int io = node_of(N, dim, odx);
+          double uo[5], ao[3], nf[3], fstar[5], fphys[5];
+          gather(m, u, eo, io, uo);
+          ja_row(m, eo, n, io, ao);
+          for (int mm = 0; mm < 3; ++mm) nf[mm] = 0.5 * (ai[mm] + ao[mm]);
+          orc_phys_flux(dim, g, ui, ai, fphys);
+          if (side) orc_two_point(m->d.surf_flux, dim, g, ui, uo, nf, fstar);
+          else orc_two_point(m->d.surf_flux, dim, g, uo, ui, nf, fstar);
+          for (int v = 0; v < nv; ++v) acc[v] += (fabs(fstar[v]) + fabs(fphys[v])) / m->w[at];
+        }
+      }
+      double Ji = m->J[e * nn + i];
+      for (int v = 0; v < nv; ++v) sc[(e * nv + v) * nn + i] = acc[v] / fabs(Ji);
     }
   }
 }

@@ -1,0 +1,529 @@
+// C ABI of the library (include/esdg.h): problem handles, device buffers,
+// launch sequencing and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/esdg.h"
+#include "dispatch.hpp"
+#include "host_ops.hpp"
+#include "kernels.hpp"
+
+using namespace esdg;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+struct TimedLaunch {
+  int kind;
+  hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct esdg_problem {
+  MeshSpec spec;
+  Operators ops;
+  Geometry geo;
+  int dim = 3, p = 3, N = 4, nn = 64, nv = 5, nf = 16;
+  int64_t E = 0;
+  int vf = VF_RANOCHA, sf = SF_LLF, prec = PREC_FP64, mesh = MESH_AFFINE;
+  double gamma = 1.4;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  size_t rsize = 8;  // bytes per internal real
+
+  // device buffers (internal precision unless noted)
+  void* U = nullptr;       // state
+  void* Y = nullptr;       // RK stage state
+  void* R = nullptr;       // RK accumulator
+  void* DU = nullptr;      // right-hand side scratch
+  void* FSTAR = nullptr;   // surface fluxes
+  void* METRIC = nullptr;  // curved metrics
+  void* NFACE = nullptr;   // curved face normals
+  double* PARTIAL = nullptr;  // reduction partials (FP64)
+  double* SCAL = nullptr;     // FP64 scalars: [0] dt, [1] t, [2..] results
+  int* FLAG = nullptr;        // non-physical flag
+  int red_blocks = 1;
+  int64_t red_per_block = 256;
+
+  bool have_state = false;
+  bool timing = false;
+  std::vector<TimedLaunch> launches;
+  std::string err;
+};
+
+namespace {
+
+esdg_status fail(esdg_problem* P, esdg_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (P) P->err = buf;
+  g_thread_error = buf;
+  return st;
+}
+
+#define HIPCHECK(P, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return fail((P), ESDG_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t state_count(const esdg_problem* P) { return (size_t)P->E * P->nv * P->nn; }
+
+template <typename Real>
+LineOps<Real> line_ops(const esdg_problem* P) {
+  LineOps<Real> o{};
+  for (int i = 0; i < P->N * P->N; ++i) o.Dt[i] = (Real)P->ops.Dt[i];
+  o.inv_w0 = (Real)(1.0 / P->ops.w[0]);
+  o.inv_wp = (Real)(1.0 / P->ops.w[P->N - 1]);
+  for (int j = 0; j < 3; ++j) o.scale[j] = (Real)(P->mesh == MESH_AFFINE ? P->geo.inv_half_h[j] : 1.0);
+  o.gamma = (Real)P->gamma;
+  o.inv_gm1 = (Real)(1.0 / (P->gamma - 1.0));
+  return o;
+}
+
+// launch with optional event bracketing for per-kernel timing
+esdg_status launch(esdg_problem* P, int kind, const void* fn, dim3 grid, dim3 block, void** args) {
+  if (!fn) return fail(P, ESDG_EINVAL, "no kernel instantiated for this configuration");
+  TimedLaunch tl{kind, nullptr, nullptr};
+  if (P->timing) {
+    HIPCHECK(P, hipEventCreate(&tl.start));
+    HIPCHECK(P, hipEventCreate(&tl.stop));
+    HIPCHECK(P, hipEventRecord(tl.start, P->stream));
+  }
+  HIPCHECK(P, hipLaunchKernel(fn, grid, block, args, 0, P->stream));
+  if (P->timing) {
+    HIPCHECK(P, hipEventRecord(tl.stop, P->stream));
+    P->launches.push_back(tl);
+  }
+  return ESDG_OK;
+}
+
+#define TRY(x)                        \
+  do {                                \
+    esdg_status s_ = (x);             \
+    if (s_ != ESDG_OK) return s_;     \
+  } while (0)
+
+// surface fluxes of the state in `u` (device, internal precision)
+template <typename Real>
+esdg_status run_face(esdg_problem* P, const void* u) {
+  FaceArgs<Real> a{};
+  a.u = (const Real*)u;
+  a.nface = (const Real*)P->NFACE;
+  a.fstar = (Real*)P->FSTAR;
+  a.E = P->E;
+  a.n0 = P->spec.n[0];
+  a.n1 = P->spec.n[1];
+  a.n2 = P->dim == 3 ? P->spec.n[2] : 1;
+  a.N = P->N;
+  a.gamma = (Real)P->gamma;
+  a.inv_gm1 = (Real)(1.0 / (P->gamma - 1.0));
+  const int64_t total = (int64_t)P->dim * P->E * P->nf;
+  const int threads = 256;
+  dim3 grid((unsigned)((total + threads - 1) / threads));
+  void* args[] = {&a};
+  return launch(P, ESDG_KERNEL_FACE, face_kernel_for(P->prec, P->dim, P->sf, P->mesh), grid, dim3(threads), args);
+}
+
+template <typename Real>
+esdg_status run_volume(esdg_problem* P, const void* uin, void* out, int mode, double coef_b, double coef_a) {
+  VolArgs<Real> a{};
+  a.uin = (const Real*)uin;
+  a.metric = (const Real*)P->METRIC;
+  a.fstar = (const Real*)P->FSTAR;
+  a.out = (Real*)out;
+  a.acc = (Real*)P->R;
+  a.u0 = (const Real*)P->U;
+  a.dt = P->SCAL;
+  a.flag = P->FLAG;
+  a.E = P->E;
+  a.n0 = P->spec.n[0];
+  a.n1 = P->spec.n[1];
+  a.n2 = P->dim == 3 ? P->spec.n[2] : 1;
+  a.mode = mode;
+  a.coef_b = (Real)coef_b;
+  a.coef_a = (Real)coef_a;
+  a.ops = line_ops<Real>(P);
+  VolKernel k = P->dim == 2 ? volume_kernel_2d(P->prec, P->N, P->vf, P->mesh)
+                            : volume_kernel_3d(P->prec, P->N, P->vf, P->mesh);
+  if (!k.fn) return fail(P, ESDG_EINVAL, "no volume kernel for dim=%d p=%d flux=%d", P->dim, P->p, P->vf);
+  dim3 grid((unsigned)((P->E + k.epb - 1) / k.epb));
+  void* args[] = {&a};
+  return launch(P, ESDG_KERNEL_VOLUME, k.fn, grid, dim3(64), args);
+}
+
+esdg_status set_scalar(esdg_problem* P, int idx, double value) {
+  void* args[] = {&P->SCAL, &idx, &value};
+  return launch(P, -1, set_scalar_kernel(), dim3(1), dim3(1), args);
+}
+
+// FP64 reduction of op over the state (and DU for the entropy rate); the
+// result lands in SCAL[2..] (or SCAL[0] = dt for RED_MAXLAMBDA).
+template <typename Real>
+esdg_status run_reduce(esdg_problem* P, int op, double cfl, int advance_t) {
+  RedArgs<Real> a{};
+  a.u = (const Real*)P->U;
+  a.du = (const Real*)P->DU;
+  a.metric = (const Real*)P->METRIC;
+  a.partial = P->PARTIAL;
+  a.E = P->E;
+  a.N = P->N;
+  a.dim = P->dim;
+  a.nn = P->nn;
+  a.J_affine = P->geo.J_affine;
+  for (int j = 0; j < 3; ++j) a.inv_half_h[j] = P->geo.inv_half_h[j];
+  for (int i = 0; i < P->N; ++i) a.w[i] = P->ops.w[i];
+  a.gamma = P->gamma;
+  int64_t per_block = P->red_per_block;
+  void* args[] = {&a, &per_block};
+  TRY(launch(P, ESDG_KERNEL_REDUCE, reduce_partial_for(P->prec, P->dim, P->mesh, op), dim3(P->red_blocks),
+             dim3(kRedThreads), args));
+  int K = op == RED_TOTALS ? P->nv : 1;
+  double* out = P->SCAL + 2;
+  double* scal = op == RED_MAXLAMBDA ? P->SCAL : nullptr;
+  int blocks = P->red_blocks, N = P->N;
+  void* args2[] = {&P->PARTIAL, &blocks, &K, &out, &cfl, &N, &scal, &advance_t};
+  return launch(P, ESDG_KERNEL_REDUCE, reduce_final_for(op), dim3(1), dim3(kRedThreads), args2);
+}
+
+// dispatch on internal precision
+#define BY_PREC(P, call_double)                \
+  ((P)->prec == PREC_FP64 ? call_double : fail((P), ESDG_EINVAL, "precision not built"))
+
+esdg_status rhs_into(esdg_problem* P, void* out) {
+  TRY(BY_PREC(P, run_face<double>(P, P->U)));
+  return BY_PREC(P, run_volume<double>(P, P->U, out, MODE_RHS, 0.0, 0.0));
+}
+
+esdg_status check_handle(esdg_problem* P, bool need_state) {
+  if (!P) return fail(nullptr, ESDG_EINVAL, "NULL problem handle");
+  if (need_state && !P->have_state) return fail(P, ESDG_ESTATE, "no state set (call esdg_set_state first)");
+  HIPCHECK(P, hipSetDevice(P->device));
+  return ESDG_OK;
+}
+
+esdg_status read_scalars(esdg_problem* P, int first, int count, double* out) {
+  HIPCHECK(P, hipMemcpyAsync(out, P->SCAL + first, sizeof(double) * count, hipMemcpyDeviceToHost, P->stream));
+  HIPCHECK(P, hipStreamSynchronize(P->stream));
+  return ESDG_OK;
+}
+
+void free_buffers(esdg_problem* P) {
+  void* bufs[] = {P->U, P->Y, P->R, P->DU, P->FSTAR, P->METRIC, P->NFACE, P->PARTIAL, P->SCAL, P->FLAG};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  for (auto& t : P->launches) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  P->launches.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* esdg_version(void) { return "esdg-mi355x 0.1 (gfx950)"; }
+
+const char* esdg_last_error(const esdg_problem* prob) {
+  return prob ? prob->err.c_str() : g_thread_error.c_str();
+}
+
+esdg_status esdg_operators(int32_t p, double* x, double* w, double* D, double* Dt) {
+  Operators ops;
+  std::string err;
+  if (p > ESDG_PMAX || !make_operators(p, &ops, &err))
+    return fail(nullptr, ESDG_EINVAL, "%s", err.empty() ? "p out of range" : err.c_str());
+  const int N = p + 1;
+  for (int i = 0; i < N; ++i) {
+    if (x) x[i] = ops.x[i];
+    if (w) w[i] = ops.w[i];
+    for (int j = 0; j < N; ++j) {
+      if (D) D[i * N + j] = ops.D[i * N + j];
+      if (Dt) Dt[i * N + j] = ops.Dt[i * N + j];
+    }
+  }
+  return ESDG_OK;
+}
+
+esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
+  if (!d || !out) return fail(nullptr, ESDG_EINVAL, "NULL descriptor or output pointer");
+  *out = nullptr;
+  if (d->dim != 2 && d->dim != 3) return fail(nullptr, ESDG_EINVAL, "dim must be 2 or 3");
+  if (d->p < 1 || d->p > ESDG_PMAX) return fail(nullptr, ESDG_EINVAL, "p must be in [1, %d]", ESDG_PMAX);
+  if (!(d->gamma > 1.0)) return fail(nullptr, ESDG_EINVAL, "gamma must be > 1");
+  if (d->volume_flux != ESDG_FLUX_RANOCHA && d->volume_flux != ESDG_FLUX_SHIMA &&
+      d->volume_flux != ESDG_FLUX_CENTRAL)
+    return fail(nullptr, ESDG_EINVAL, "volume flux must be RANOCHA, SHIMA or CENTRAL");
+  if (d->surface_flux < 0 || d->surface_flux > 3) return fail(nullptr, ESDG_EINVAL, "unknown surface flux");
+  if (d->precision != ESDG_FP64 && d->precision != ESDG_FP32)
+    return fail(nullptr, ESDG_EINVAL, "unknown precision");
+  for (int j = 0; j < d->dim; ++j)
+    if (d->n[j] < 1) return fail(nullptr, ESDG_EINVAL, "element counts must be >= 1");
+  if (d->precision == ESDG_FP32) return fail(nullptr, ESDG_EINVAL, "FP32 precision is not built in this version");
+
+  esdg_problem* P = new esdg_problem();
+  P->spec.dim = d->dim;
+  P->spec.p = d->p;
+  for (int j = 0; j < 3; ++j) {
+    P->spec.n[j] = (j < d->dim) ? d->n[j] : 1;
+    P->spec.lo[j] = d->lo[j];
+    P->spec.hi[j] = d->hi[j];
+  }
+  P->spec.warp = d->warp;
+  P->spec.coords = d->coords;
+  P->dim = d->dim;
+  P->p = d->p;
+  P->N = d->p + 1;
+  P->nv = d->dim + 2;
+  P->vf = d->volume_flux;
+  P->sf = d->surface_flux;
+  P->prec = d->precision == ESDG_FP32 ? PREC_FP32 : PREC_FP64;
+  P->rsize = P->prec == PREC_FP32 ? 4 : 8;
+  P->gamma = d->gamma;
+  P->stream = (hipStream_t)d->stream;
+  std::string err;
+  if (!make_operators(d->p, &P->ops, &err) || !make_geometry(P->spec, P->ops, &P->geo, &err)) {
+    esdg_status st = fail(nullptr, ESDG_EINVAL, "%s", err.c_str());
+    delete P;
+    return st;
+  }
+  P->spec.coords = nullptr;  // never retained
+  P->E = P->geo.E;
+  P->nn = P->geo.nn;
+  P->nf = P->geo.nf;
+  P->mesh = P->geo.affine ? MESH_AFFINE : MESH_CURVED;
+
+  hipError_t he = hipGetDevice(&P->device);
+  if (he != hipSuccess) {
+    esdg_status st = fail(nullptr, ESDG_EDEVICE, "hipGetDevice: %s", hipGetErrorString(he));
+    delete P;
+    return st;
+  }
+  // reduction geometry: fixed per problem size, so results are reproducible
+  const int64_t total = P->E * P->nn;
+  int64_t blocks = (total + kRedThreads - 1) / kRedThreads;
+  if (blocks > 2048) blocks = 2048;
+  P->red_blocks = (int)blocks;
+  P->red_per_block = ((total + blocks - 1) / blocks + kRedThreads - 1) / kRedThreads * kRedThreads;
+
+  const size_t ns = state_count(P) * P->rsize;
+  const size_t nfs = (size_t)P->dim * P->E * P->nv * P->nf * P->rsize;
+  struct {
+    void** ptr;
+    size_t bytes;
+  } allocs[] = {{&P->U, ns},
+                {&P->Y, ns},
+                {&P->R, ns},
+                {&P->DU, ns},
+                {&P->FSTAR, nfs},
+                {(void**)&P->PARTIAL, sizeof(double) * 8 * (size_t)P->red_blocks},
+                {(void**)&P->SCAL, sizeof(double) * 16},
+                {(void**)&P->FLAG, sizeof(int)}};
+  for (auto& a : allocs) {
+    if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
+      free_buffers(P);
+      delete P;
+      return fail(nullptr, ESDG_ENOMEM, "device allocation of %zu bytes failed", a.bytes);
+    }
+  }
+  if (P->mesh == MESH_CURVED) {
+    const size_t mb = P->geo.metric.size() * P->rsize, fb = P->geo.nface.size() * P->rsize;
+    if (hipMalloc(&P->METRIC, mb) != hipSuccess || hipMalloc(&P->NFACE, fb) != hipSuccess) {
+      free_buffers(P);
+      delete P;
+      return fail(nullptr, ESDG_ENOMEM, "device allocation of metric terms failed");
+    }
+    hipError_t e1 = hipMemcpy(P->METRIC, P->geo.metric.data(), mb, hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy(P->NFACE, P->geo.nface.data(), fb, hipMemcpyHostToDevice);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      free_buffers(P);
+      delete P;
+      return fail(nullptr, ESDG_EDEVICE, "upload of metric terms failed");
+    }
+    // the device copy is authoritative; keep the host copy small
+    std::vector<double>().swap(P->geo.metric);
+    std::vector<double>().swap(P->geo.nface);
+  }
+  if (hipMemset(P->FLAG, 0, sizeof(int)) != hipSuccess || hipMemset(P->SCAL, 0, sizeof(double) * 16) != hipSuccess) {
+    free_buffers(P);
+    delete P;
+    return fail(nullptr, ESDG_EDEVICE, "device initialisation failed");
+  }
+  *out = P;
+  return ESDG_OK;
+}
+
+void esdg_destroy(esdg_problem* P) {
+  if (!P) return;
+  (void)hipSetDevice(P->device);
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  else (void)hipDeviceSynchronize();
+  free_buffers(P);
+  delete P;
+}
+
+esdg_status esdg_sizes(const esdg_problem* P, int64_t* n_elem, int32_t* nodes, int32_t* n_var) {
+  if (!P) return fail(nullptr, ESDG_EINVAL, "NULL problem handle");
+  if (n_elem) *n_elem = P->E;
+  if (nodes) *nodes = P->nn;
+  if (n_var) *n_var = P->nv;
+  return ESDG_OK;
+}
+
+esdg_status esdg_set_stream(esdg_problem* P, void* stream) {
+  if (!P) return fail(nullptr, ESDG_EINVAL, "NULL problem handle");
+  P->stream = (hipStream_t)stream;
+  return ESDG_OK;
+}
+
+esdg_status esdg_get_coords(const esdg_problem* P, double* x) {
+  if (!P || !x) return fail(const_cast<esdg_problem*>(P), ESDG_EINVAL, "NULL argument");
+  std::memcpy(x, P->geo.coords.data(), sizeof(double) * P->geo.coords.size());
+  return ESDG_OK;
+}
+
+esdg_status esdg_set_state(esdg_problem* P, const double* u, int32_t where) {
+  TRY(check_handle(P, false));
+  if (!u) return fail(P, ESDG_EINVAL, "NULL state");
+  const size_t bytes = state_count(P) * sizeof(double);
+  HIPCHECK(P, hipMemcpyAsync(P->U, u, bytes, where == ESDG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             P->stream));
+  if (where != ESDG_DEVICE) HIPCHECK(P, hipStreamSynchronize(P->stream));
+  P->have_state = true;
+  return ESDG_OK;
+}
+
+esdg_status esdg_get_state(esdg_problem* P, double* u, int32_t where) {
+  TRY(check_handle(P, true));
+  if (!u) return fail(P, ESDG_EINVAL, "NULL output");
+  const size_t bytes = state_count(P) * sizeof(double);
+  HIPCHECK(P, hipMemcpyAsync(u, P->U, bytes, where == ESDG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             P->stream));
+  if (where != ESDG_DEVICE) HIPCHECK(P, hipStreamSynchronize(P->stream));
+  return ESDG_OK;
+}
+
+esdg_status esdg_rhs(esdg_problem* P, double* du, int32_t where) {
+  TRY(check_handle(P, true));
+  if (!du) return fail(P, ESDG_EINVAL, "NULL output");
+  const bool direct = where == ESDG_DEVICE;
+  TRY(rhs_into(P, direct ? (void*)du : P->DU));
+  if (!direct) {
+    HIPCHECK(P, hipMemcpyAsync(du, P->DU, state_count(P) * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+    HIPCHECK(P, hipStreamSynchronize(P->stream));
+  }
+  return ESDG_OK;
+}
+
+esdg_status esdg_step(esdg_problem* P, double dt, int32_t nsteps, double cfl, double* t_inout) {
+  TRY(check_handle(P, true));
+  if (nsteps < 0) return fail(P, ESDG_EINVAL, "nsteps must be >= 0");
+  const bool use_cfl = !(dt > 0.0);
+  if (use_cfl && !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "dt <= 0 needs cfl > 0");
+  if (nsteps == 0) return ESDG_OK;
+  if (use_cfl) TRY(set_scalar(P, 1, 0.0));
+  else TRY(set_scalar(P, 0, dt));
+  // classical RK4 in three registers: U (state), Y (stage), R (accumulator)
+  for (int s = 0; s < nsteps; ++s) {
+    if (use_cfl) TRY(BY_PREC(P, run_reduce<double>(P, RED_MAXLAMBDA, cfl, 1)));
+    TRY(BY_PREC(P, run_face<double>(P, P->U)));
+    TRY(BY_PREC(P, run_volume<double>(P, P->U, P->Y, MODE_RK_FIRST, 1.0 / 6.0, 0.5)));
+    TRY(BY_PREC(P, run_face<double>(P, P->Y)));
+    TRY(BY_PREC(P, run_volume<double>(P, P->Y, P->Y, MODE_RK_MID, 1.0 / 3.0, 0.5)));
+    TRY(BY_PREC(P, run_face<double>(P, P->Y)));
+    TRY(BY_PREC(P, run_volume<double>(P, P->Y, P->Y, MODE_RK_MID, 1.0 / 3.0, 1.0)));
+    TRY(BY_PREC(P, run_face<double>(P, P->Y)));
+    TRY(BY_PREC(P, run_volume<double>(P, P->Y, P->U, MODE_RK_LAST, 1.0 / 6.0, 0.0)));
+  }
+  if (t_inout) {
+    if (use_cfl) {
+      double tsum = 0.0;
+      TRY(read_scalars(P, 1, 1, &tsum));
+      *t_inout += tsum;
+    } else {
+      *t_inout += dt * nsteps;
+    }
+  }
+  return ESDG_OK;
+}
+
+esdg_status esdg_entropy_rate(esdg_problem* P, double* dSdt) {
+  TRY(check_handle(P, true));
+  if (!dSdt) return fail(P, ESDG_EINVAL, "NULL output");
+  TRY(rhs_into(P, P->DU));
+  TRY(BY_PREC(P, run_reduce<double>(P, RED_ENTROPY, 0.0, 0)));
+  return read_scalars(P, 2, 1, dSdt);
+}
+
+esdg_status esdg_totals(esdg_problem* P, double* totals) {
+  TRY(check_handle(P, true));
+  if (!totals) return fail(P, ESDG_EINVAL, "NULL output");
+  TRY(BY_PREC(P, run_reduce<double>(P, RED_TOTALS, 0.0, 0)));
+  return read_scalars(P, 2, P->nv, totals);
+}
+
+esdg_status esdg_max_dt(esdg_problem* P, double cfl, double* dt) {
+  TRY(check_handle(P, true));
+  if (!dt || !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "need cfl > 0 and an output pointer");
+  TRY(BY_PREC(P, run_reduce<double>(P, RED_MAXLAMBDA, cfl, 0)));
+  return read_scalars(P, 2, 1, dt);
+}
+
+esdg_status esdg_sync(esdg_problem* P) {
+  TRY(check_handle(P, false));
+  HIPCHECK(P, hipStreamSynchronize(P->stream));
+  int flag = 0;
+  HIPCHECK(P, hipMemcpy(&flag, P->FLAG, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) {
+    HIPCHECK(P, hipMemset(P->FLAG, 0, sizeof(int)));
+    return fail(P, ESDG_ENONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or non-finite) met by a kernel");
+  }
+  return ESDG_OK;
+}
+
+esdg_status esdg_timing_enable(esdg_problem* P, int32_t enable) {
+  if (!P) return fail(nullptr, ESDG_EINVAL, "NULL problem handle");
+  P->timing = enable != 0;
+  return ESDG_OK;
+}
+
+esdg_status esdg_timing_read(esdg_problem* P, int32_t kernel, double* total_ms, int64_t* launches) {
+  TRY(check_handle(P, false));
+  double sum = 0.0;
+  int64_t cnt = 0;
+  for (auto& t : P->launches) {
+    if (t.kind != kernel) continue;
+    HIPCHECK(P, hipEventSynchronize(t.stop));
+    float ms = 0.0f;
+    HIPCHECK(P, hipEventElapsedTime(&ms, t.start, t.stop));
+    sum += ms;
+    ++cnt;
+  }
+  if (total_ms) *total_ms = sum;
+  if (launches) *launches = cnt;
+  return ESDG_OK;
+}
+
+esdg_status esdg_timing_reset(esdg_problem* P) {
+  TRY(check_handle(P, false));
+  HIPCHECK(P, hipStreamSynchronize(P->stream));
+  for (auto& t : P->launches) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  P->launches.clear();
+  return ESDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,11 @@
+// 3D volume-kernel instantiations.
+#include "dispatch_vol.hpp"
+
+namespace esdg {
+
+VolKernel volume_kernel_3d(int prec, int N, int vf, int mesh) {
+  if (prec == PREC_FP64) return vol_pick<3, double>(N, vf, mesh);
+  return VolKernel{};
+}
+
+}  // namespace esdg
