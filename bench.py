@@ -5,13 +5,13 @@ on [-1,1]^3 (x_m = xi_m + 0.1 sin(pi xi) sin(pi eta) sin(pi zeta)), p = 3
 (262,144 nodes, 1.31 M node-variables), FP64, seeded smooth random state
 (rho, p in [0.8,1.2], |v| <= 0.1, |k| <= 4, seed 2), Ranocha volume flux,
 local Lax-Friedrichs surface flux.  A step is one classical RK4 step in CFL
-mode: the FP64 CFL reduction, then four stages of (surface-flux kernel,
-fused volume + lifting + stage-update kernel).  The metric is the paper's
+mode: the FP64 CFL reduction, then four launches of the fused stage kernel
+(surface flux + volume term + lifting + stage update).  The metric is the paper's
 performance index PID = time per RHS evaluation / #DOF (Sec. 4, one DOF per
 volume node), here wall time per step / (4 x #nodes), lower is better.
 
-Prints one JSON line with the roofline of the dominant kernel (the volume
-kernel, HBM-bound; durations from hipEvents around its launches on the
+Prints one JSON line with the roofline of the dominant kernel (the fused
+stage kernel, HBM-bound; durations from hipEvents around its launches on the
 library's stream) and the CPU oracle timed on a bounded sample of the same
 workload.  Only one GPU: --gpus above 1 exits with a message.
 """
@@ -31,20 +31,23 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 FP64_VALU_PEAK_TF = 78.6    # MI355X FP64 vector
 
 
-def algorithmic_volume_bytes(dim: int, N: int, curved: bool, real_bytes: int = 8) -> float:
-    """Bytes per node one volume launch must move, averaged over the four RK4 stages.
+def algorithmic_stage_bytes(dim: int, N: int, curved: bool, real_bytes: int = 8) -> float:
+    """Bytes per node one fused stage launch must move, averaged over the RK4 stages.
 
     state registers: stage 1 reads U, writes R and Y (3 arrays); stages 2-3 read
     Y, U, R and write R, Y (5); stage 4 reads Y, R and writes U (3): mean 4
-    arrays of (dim+2) values.  Metrics: dim*dim contravariant components + 1/J
-    per node (curved only).  Surface fluxes: 2*dim faces of N^(dim-1) nodes and
-    (dim+2) values per element, i.e. 2*dim*(dim+2)/N per node.
+    arrays of (dim+2) values.  Metrics (curved): dim*dim contravariant
+    components + 1/J per node.  Surface: the neighbours' traces, 2*dim faces of
+    N^(dim-1) nodes and (dim+2) values per element, i.e. 2*dim*(dim+2)/N per
+    node, and one dim-vector normal per face node, dim*dim/N per node
+    (curved).
     """
     nv = dim + 2
     state = 4 * nv
     metric = (dim * dim + 1) if curved else 0
-    face = 2 * dim * nv / N
-    return (state + metric + face) * real_bytes
+    traces = 2 * dim * nv / N
+    normals = dim * dim / N if curved else 0
+    return (state + metric + traces + normals) * real_bytes
 
 
 def main(argv=None):
@@ -61,6 +64,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=10,
                     help="steps with per-kernel hipEvent timing (after the timed region)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one plain device-to-device copy of this many MiB (HBM "
+                         "counter calibration under a profiler)")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -108,13 +114,12 @@ def main(argv=None):
     g.timing(True)
     g.timing_reset()
     run(args.timing_steps)
-    vol_ms, vol_n = g.timing_read(esdg.KERNEL_VOLUME)
-    face_ms, face_n = g.timing_read(esdg.KERNEL_FACE)
+    vol_ms, vol_n = g.timing_read(esdg.KERNEL_STAGE)
     red_ms, red_n = g.timing_read(esdg.KERNEL_REDUCE)
     g.timing(False)
     g.timing_reset()
     vol_avg_s = vol_ms / vol_n * 1e-3
-    bytes_per_node = algorithmic_volume_bytes(dim, p + 1, curved=True)
+    bytes_per_node = algorithmic_stage_bytes(dim, p + 1, curved=True)
     traffic_bytes = bytes_per_node * nodes
     achieved_gbs = traffic_bytes / vol_avg_s / 1e9
 
@@ -134,7 +139,7 @@ def main(argv=None):
         "config": {
             "workload": "3D Euler, warped periodic %d^3 mesh on [-1,1]^3 (warp 0.1), p=%d, "
                         "smooth random Fourier state seed 2, %s volume flux + LLF surface flux, "
-                        "RK4 step (CFL %.2f) = CFL reduction + 4 x (surface + fused volume/lift/update)"
+                        "RK4 step (CFL %.2f) = CFL reduction + 4 fused stage launches (surface+volume+lift+update)"
                         % (n, p, args.flux, args.cfl),
             "elements": g.n_elem, "nodes": nodes, "node_vars": nodes * g.n_var,
             "rhs_per_step": 4,
@@ -143,12 +148,11 @@ def main(argv=None):
         "dof_per_s": 4 * nodes / (ms_per_step * 1e-3),
         "event_ms_per_step": round(ev_ms / args.steps, 6),
         "kernels_us": {
-            "volume": round(1e3 * vol_ms / vol_n, 3),
-            "face": round(1e3 * face_ms / face_n, 3),
+            "stage": round(1e3 * vol_ms / vol_n, 3),
             "reduce": round(1e3 * red_ms / max(red_n, 1), 3),
         },
         "roofline": {
-            "kernel": "volume_kernel<3,%d,%s,curved,double>" % (p + 1, args.flux),
+            "kernel": "stage_kernel<3,%d,%s,curved,double>" % (p + 1, args.flux),
             "bound": "hbm",
             "achieved": round(achieved_gbs, 2),
             "peak": HBM_PEAK_GBS,
@@ -161,6 +165,16 @@ def main(argv=None):
         },
         "cpu_baseline": None,
     }
+
+    if args.calibrate_copy_mib > 0:
+        nb = args.calibrate_copy_mib * (1 << 20)
+        src = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = {"read": nb, "write": nb}
+        del src, dst
 
     if not args.no_cpu_baseline:
         import oracle

@@ -115,9 +115,9 @@ esdg_status esdg_get_state(esdg_problem *prob, double *u, int32_t where);
 esdg_status esdg_rhs(esdg_problem *prob, double *du, int32_t where);
 
 /* step!: advance the state by nsteps steps of classical RK4 (Butcher
- * a = 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6) in three-register low-storage
- * form (state, stage, accumulator), each stage one surface-flux launch and
- * one fused volume+lifting+update launch.  dt > 0: fixed step; dt <= 0:
+ * a = 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6) in low-storage form (state,
+ * accumulator and two alternating stage buffers), each stage one fused
+ * launch (surface flux + volume term + lifting + stage update).  dt > 0: fixed step; dt <= 0:
  * dt = cfl*2/((p+1) max_i sum_n (|v.Ja^n|+c|Ja^n|)/J_i) recomputed at the start
  * of every step on the device.  *t_inout (may be NULL) is advanced by the
  * total time; in CFL mode this synchronises the stream. */
@@ -144,8 +144,9 @@ esdg_status esdg_sync(esdg_problem *prob);
 /* Per-kernel timing with hipEvents on the handle's stream: while enabled,
  * every launch of the listed kernels is bracketed by an event pair.
  * esdg_timing_read returns the summed duration (ms) and launch count since
- * the last reset, synchronising the stream. */
-typedef enum { ESDG_KERNEL_FACE = 0, ESDG_KERNEL_VOLUME = 1, ESDG_KERNEL_REDUCE = 2 } esdg_kernel;
+ * the last reset, synchronising the stream.  STAGE is the fused
+ * right-hand-side / RK-stage kernel, REDUCE the FP64 reductions. */
+typedef enum { ESDG_KERNEL_STAGE = 1, ESDG_KERNEL_REDUCE = 2 } esdg_kernel;
 esdg_status esdg_timing_enable(esdg_problem *prob, int32_t enable);
 esdg_status esdg_timing_read(esdg_problem *prob, int32_t kernel, double *total_ms,
                              int64_t *launches);

@@ -43,7 +43,7 @@ struct esdg_problem {
   void* Y = nullptr;       // RK stage state
   void* R = nullptr;       // RK accumulator
   void* DU = nullptr;      // right-hand side scratch
-  void* FSTAR = nullptr;   // surface fluxes
+  void* Y2 = nullptr;      // second RK stage state (stage inputs and outputs alternate)
   void* METRIC = nullptr;  // curved metrics
   void* NFACE = nullptr;   // curved face normals
   double* PARTIAL = nullptr;  // reduction partials (FP64)
@@ -80,8 +80,8 @@ esdg_status fail(esdg_problem* P, esdg_status st, const char* fmt, ...) {
 size_t state_count(const esdg_problem* P) { return (size_t)P->E * P->nv * P->nn; }
 
 template <typename Real>
-LineOps<Real> line_ops(const esdg_problem* P) {
-  LineOps<Real> o{};
+StageOps<Real> stage_ops(const esdg_problem* P) {
+  StageOps<Real> o{};
   for (int i = 0; i < P->N * P->N; ++i) o.Dt[i] = (Real)P->ops.Dt[i];
   o.inv_w0 = (Real)(1.0 / P->ops.w[0]);
   o.inv_wp = (Real)(1.0 / P->ops.w[P->N - 1]);
@@ -114,57 +114,36 @@ esdg_status launch(esdg_problem* P, int kind, const void* fn, dim3 grid, dim3 bl
     if (s_ != ESDG_OK) return s_;     \
   } while (0)
 
-// surface fluxes of the state in `u` (device, internal precision)
+// One fused stage launch: right-hand side of `uin` (surface and volume
+// terms) and, for the RK modes, the stage update into out / R.
 template <typename Real>
-esdg_status run_face(esdg_problem* P, const void* u) {
-  FaceArgs<Real> a{};
-  a.u = (const Real*)u;
-  a.nface = (const Real*)P->NFACE;
-  a.fstar = (Real*)P->FSTAR;
-  a.E = P->E;
-  a.n0 = P->spec.n[0];
-  a.n1 = P->spec.n[1];
-  a.n2 = P->dim == 3 ? P->spec.n[2] : 1;
-  a.N = P->N;
-  a.gamma = (Real)P->gamma;
-  a.inv_gm1 = (Real)(1.0 / (P->gamma - 1.0));
-  const int64_t total = (int64_t)P->dim * P->E * P->nf;
-  const int threads = 256;
-  dim3 grid((unsigned)((total + threads - 1) / threads));
-  void* args[] = {&a};
-  return launch(P, ESDG_KERNEL_FACE, face_kernel_for(P->prec, P->dim, P->sf, P->mesh), grid, dim3(threads), args);
-}
-
-template <typename Real>
-esdg_status run_volume(esdg_problem* P, const void* uin, void* out, int mode, double coef_b, double coef_a) {
-  VolArgs<Real> a{};
+esdg_status run_stage(esdg_problem* P, const void* uin, void* out, int mode, double coef_b, double coef_a,
+                      double dt_fixed = 0.0) {
+  StageArgs<Real> a{};
   a.uin = (const Real*)uin;
   a.metric = (const Real*)P->METRIC;
-  a.fstar = (const Real*)P->FSTAR;
+  a.nface = (const Real*)P->NFACE;
   a.out = (Real*)out;
   a.acc = (Real*)P->R;
   a.u0 = (const Real*)P->U;
-  a.dt = P->SCAL;
+  a.dt = dt_fixed > 0.0 ? nullptr : P->SCAL;
+  a.dt_fixed = dt_fixed;
   a.flag = P->FLAG;
-  a.E = P->E;
+  a.E = (int)P->E;
   a.n0 = P->spec.n[0];
   a.n1 = P->spec.n[1];
   a.n2 = P->dim == 3 ? P->spec.n[2] : 1;
   a.mode = mode;
+  a.surf = P->sf;
   a.coef_b = (Real)coef_b;
   a.coef_a = (Real)coef_a;
-  a.ops = line_ops<Real>(P);
-  VolKernel k = P->dim == 2 ? volume_kernel_2d(P->prec, P->N, P->vf, P->mesh)
-                            : volume_kernel_3d(P->prec, P->N, P->vf, P->mesh);
-  if (!k.fn) return fail(P, ESDG_EINVAL, "no volume kernel for dim=%d p=%d flux=%d", P->dim, P->p, P->vf);
+  a.ops = stage_ops<Real>(P);
+  VolKernel k = P->dim == 2 ? stage_kernel_2d(P->prec, P->N, P->vf, P->mesh)
+                            : stage_kernel_3d(P->prec, P->N, P->vf, P->mesh);
+  if (!k.fn) return fail(P, ESDG_EINVAL, "no stage kernel for dim=%d p=%d flux=%d", P->dim, P->p, P->vf);
   dim3 grid((unsigned)((P->E + k.epb - 1) / k.epb));
   void* args[] = {&a};
-  return launch(P, ESDG_KERNEL_VOLUME, k.fn, grid, dim3(64), args);
-}
-
-esdg_status set_scalar(esdg_problem* P, int idx, double value) {
-  void* args[] = {&P->SCAL, &idx, &value};
-  return launch(P, -1, set_scalar_kernel(), dim3(1), dim3(1), args);
+  return launch(P, ESDG_KERNEL_STAGE, k.fn, grid, dim3(k.threads), args);
 }
 
 // FP64 reduction of op over the state (and DU for the entropy rate); the
@@ -201,8 +180,7 @@ esdg_status run_reduce(esdg_problem* P, int op, double cfl, int advance_t) {
   ((P)->prec == PREC_FP64 ? call_double : fail((P), ESDG_EINVAL, "precision not built"))
 
 esdg_status rhs_into(esdg_problem* P, void* out) {
-  TRY(BY_PREC(P, run_face<double>(P, P->U)));
-  return BY_PREC(P, run_volume<double>(P, P->U, out, MODE_RHS, 0.0, 0.0));
+  return BY_PREC(P, run_stage<double>(P, P->U, out, MODE_RHS, 0.0, 0.0));
 }
 
 esdg_status check_handle(esdg_problem* P, bool need_state) {
@@ -219,7 +197,7 @@ esdg_status read_scalars(esdg_problem* P, int first, int count, double* out) {
 }
 
 void free_buffers(esdg_problem* P) {
-  void* bufs[] = {P->U, P->Y, P->R, P->DU, P->FSTAR, P->METRIC, P->NFACE, P->PARTIAL, P->SCAL, P->FLAG};
+  void* bufs[] = {P->U, P->Y, P->Y2, P->R, P->DU, P->METRIC, P->NFACE, P->PARTIAL, P->SCAL, P->FLAG};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& t : P->launches) {
@@ -268,8 +246,12 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
   if (d->surface_flux < 0 || d->surface_flux > 3) return fail(nullptr, ESDG_EINVAL, "unknown surface flux");
   if (d->precision != ESDG_FP64 && d->precision != ESDG_FP32)
     return fail(nullptr, ESDG_EINVAL, "unknown precision");
-  for (int j = 0; j < d->dim; ++j)
+  int64_t ne = 1;
+  for (int j = 0; j < d->dim; ++j) {
     if (d->n[j] < 1) return fail(nullptr, ESDG_EINVAL, "element counts must be >= 1");
+    ne *= d->n[j];
+  }
+  if (ne > (int64_t)1 << 30) return fail(nullptr, ESDG_EINVAL, "at most 2^30 elements");
   if (d->precision == ESDG_FP32) return fail(nullptr, ESDG_EINVAL, "FP32 precision is not built in this version");
 
   esdg_problem* P = new esdg_problem();
@@ -318,7 +300,6 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
   P->red_per_block = ((total + blocks - 1) / blocks + kRedThreads - 1) / kRedThreads * kRedThreads;
 
   const size_t ns = state_count(P) * P->rsize;
-  const size_t nfs = (size_t)P->dim * P->E * P->nv * P->nf * P->rsize;
   struct {
     void** ptr;
     size_t bytes;
@@ -326,7 +307,7 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
                 {&P->Y, ns},
                 {&P->R, ns},
                 {&P->DU, ns},
-                {&P->FSTAR, nfs},
+                {&P->Y2, ns},
                 {(void**)&P->PARTIAL, sizeof(double) * 8 * (size_t)P->red_blocks},
                 {(void**)&P->SCAL, sizeof(double) * 16},
                 {(void**)&P->FLAG, sizeof(int)}};
@@ -432,19 +413,16 @@ esdg_status esdg_step(esdg_problem* P, double dt, int32_t nsteps, double cfl, do
   const bool use_cfl = !(dt > 0.0);
   if (use_cfl && !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "dt <= 0 needs cfl > 0");
   if (nsteps == 0) return ESDG_OK;
-  if (use_cfl) TRY(set_scalar(P, 1, 0.0));
-  else TRY(set_scalar(P, 0, dt));
-  // classical RK4 in three registers: U (state), Y (stage), R (accumulator)
+  const double h = use_cfl ? 0.0 : dt;  // fixed step by value, CFL step from SCAL[0]
+  // classical RK4 in low-storage form: U (state), R (accumulator) and the
+  // stage state, alternating between Y and Y2
   for (int s = 0; s < nsteps; ++s) {
-    if (use_cfl) TRY(BY_PREC(P, run_reduce<double>(P, RED_MAXLAMBDA, cfl, 1)));
-    TRY(BY_PREC(P, run_face<double>(P, P->U)));
-    TRY(BY_PREC(P, run_volume<double>(P, P->U, P->Y, MODE_RK_FIRST, 1.0 / 6.0, 0.5)));
-    TRY(BY_PREC(P, run_face<double>(P, P->Y)));
-    TRY(BY_PREC(P, run_volume<double>(P, P->Y, P->Y, MODE_RK_MID, 1.0 / 3.0, 0.5)));
-    TRY(BY_PREC(P, run_face<double>(P, P->Y)));
-    TRY(BY_PREC(P, run_volume<double>(P, P->Y, P->Y, MODE_RK_MID, 1.0 / 3.0, 1.0)));
-    TRY(BY_PREC(P, run_face<double>(P, P->Y)));
-    TRY(BY_PREC(P, run_volume<double>(P, P->Y, P->U, MODE_RK_LAST, 1.0 / 6.0, 0.0)));
+    if (use_cfl) TRY(BY_PREC(P, run_reduce<double>(P, RED_MAXLAMBDA, cfl, s == 0 ? 2 : 1)));
+    // stage inputs are read across element faces, so inputs and outputs alternate
+    TRY(BY_PREC(P, run_stage<double>(P, P->U, P->Y, MODE_RK_FIRST, 1.0 / 6.0, 0.5, h)));
+    TRY(BY_PREC(P, run_stage<double>(P, P->Y, P->Y2, MODE_RK_MID, 1.0 / 3.0, 0.5, h)));
+    TRY(BY_PREC(P, run_stage<double>(P, P->Y2, P->Y, MODE_RK_MID, 1.0 / 3.0, 1.0, h)));
+    TRY(BY_PREC(P, run_stage<double>(P, P->Y, P->U, MODE_RK_LAST, 1.0 / 6.0, 0.0, h)));
   }
   if (t_inout) {
     if (use_cfl) {

@@ -1,30 +1,10 @@
-// Surface-flux, reduction and utility kernel instantiations.
+// Reduction and utility kernel instantiations.
 #include "dispatch.hpp"
 #include "kernels.hpp"
 
 namespace esdg {
 
 namespace {
-
-template <int DIM, typename Real>
-const void* face_pick(int sf, int mesh) {
-  if (mesh == MESH_AFFINE) {
-    switch (sf) {
-      case SF_RANOCHA: return (const void*)&face_kernel<DIM, SF_RANOCHA, MESH_AFFINE, Real>;
-      case SF_SHIMA: return (const void*)&face_kernel<DIM, SF_SHIMA, MESH_AFFINE, Real>;
-      case SF_LLF: return (const void*)&face_kernel<DIM, SF_LLF, MESH_AFFINE, Real>;
-      case SF_CENTRAL: return (const void*)&face_kernel<DIM, SF_CENTRAL, MESH_AFFINE, Real>;
-    }
-  } else {
-    switch (sf) {
-      case SF_RANOCHA: return (const void*)&face_kernel<DIM, SF_RANOCHA, MESH_CURVED, Real>;
-      case SF_SHIMA: return (const void*)&face_kernel<DIM, SF_SHIMA, MESH_CURVED, Real>;
-      case SF_LLF: return (const void*)&face_kernel<DIM, SF_LLF, MESH_CURVED, Real>;
-      case SF_CENTRAL: return (const void*)&face_kernel<DIM, SF_CENTRAL, MESH_CURVED, Real>;
-    }
-  }
-  return nullptr;
-}
 
 template <int DIM, typename Real>
 const void* reduce_pick(int mesh, int op) {
@@ -54,16 +34,7 @@ __global__ void __launch_bounds__(256) to_fp32_kernel(const double* src, float* 
   if (i < n) dst[i] = (float)src[i];
 }
 
-__global__ void set_scalar(double* scal, int idx, double value) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) scal[idx] = value;
-}
-
 }  // namespace
-
-const void* face_kernel_for(int prec, int dim, int sf, int mesh) {
-  if (prec != PREC_FP64) return nullptr;
-  return dim == 2 ? face_pick<2, double>(sf, mesh) : face_pick<3, double>(sf, mesh);
-}
 
 const void* reduce_partial_for(int prec, int dim, int mesh, int op) {
   if (prec != PREC_FP64) return nullptr;
@@ -82,7 +53,5 @@ const void* reduce_final_for(int op) {
 const void* convert_kernel_for(int to_fp64) {
   return to_fp64 ? (const void*)&to_fp64_kernel : (const void*)&to_fp32_kernel;
 }
-
-const void* set_scalar_kernel() { return (const void*)&set_scalar; }
 
 }  // namespace esdg

@@ -1,4 +1,4 @@
-// Volume-kernel instantiation table for one dimension (included by the
+// Stage-kernel instantiation table for one dimension (included by the
 // per-dimension translation units so that they compile in parallel).
 #pragma once
 
@@ -11,14 +11,15 @@ template <int DIM, typename Real, int N>
 VolKernel vol_pick_n(int vf, int mesh) {
   VolKernel k;
   k.epb = Tile<DIM, N>::EPB;
+  k.threads = Tile<DIM, N>::THREADS;
   if (mesh == MESH_AFFINE) {
-    if (vf == VF_RANOCHA) k.fn = (const void*)&volume_kernel<DIM, N, VF_RANOCHA, MESH_AFFINE, Real>;
-    else if (vf == VF_SHIMA) k.fn = (const void*)&volume_kernel<DIM, N, VF_SHIMA, MESH_AFFINE, Real>;
-    else if (vf == VF_CENTRAL) k.fn = (const void*)&volume_kernel<DIM, N, VF_CENTRAL, MESH_AFFINE, Real>;
+    if (vf == VF_RANOCHA) k.fn = (const void*)&stage_kernel<DIM, N, VF_RANOCHA, MESH_AFFINE, Real>;
+    else if (vf == VF_SHIMA) k.fn = (const void*)&stage_kernel<DIM, N, VF_SHIMA, MESH_AFFINE, Real>;
+    else if (vf == VF_CENTRAL) k.fn = (const void*)&stage_kernel<DIM, N, VF_CENTRAL, MESH_AFFINE, Real>;
   } else {
-    if (vf == VF_RANOCHA) k.fn = (const void*)&volume_kernel<DIM, N, VF_RANOCHA, MESH_CURVED, Real>;
-    else if (vf == VF_SHIMA) k.fn = (const void*)&volume_kernel<DIM, N, VF_SHIMA, MESH_CURVED, Real>;
-    else if (vf == VF_CENTRAL) k.fn = (const void*)&volume_kernel<DIM, N, VF_CENTRAL, MESH_CURVED, Real>;
+    if (vf == VF_RANOCHA) k.fn = (const void*)&stage_kernel<DIM, N, VF_RANOCHA, MESH_CURVED, Real>;
+    else if (vf == VF_SHIMA) k.fn = (const void*)&stage_kernel<DIM, N, VF_SHIMA, MESH_CURVED, Real>;
+    else if (vf == VF_CENTRAL) k.fn = (const void*)&stage_kernel<DIM, N, VF_CENTRAL, MESH_CURVED, Real>;
   }
   return k;
 }

@@ -1,9 +1,9 @@
-// 2D volume-kernel instantiations.
+// 2D stage-kernel instantiations.
 #include "dispatch_vol.hpp"
 
 namespace esdg {
 
-VolKernel volume_kernel_2d(int prec, int N, int vf, int mesh) {
+VolKernel stage_kernel_2d(int prec, int N, int vf, int mesh) {
   if (prec == PREC_FP64) return vol_pick<2, double>(N, vf, mesh);
   return VolKernel{};
 }

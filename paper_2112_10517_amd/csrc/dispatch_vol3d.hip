@@ -1,9 +1,9 @@
-// 3D volume-kernel instantiations.
+// 3D stage-kernel instantiations.
 #include "dispatch_vol.hpp"
 
 namespace esdg {
 
-VolKernel volume_kernel_3d(int prec, int N, int vf, int mesh) {
+VolKernel stage_kernel_3d(int prec, int N, int vf, int mesh) {
   if (prec == PREC_FP64) return vol_pick<3, double>(N, vf, mesh);
   return VolKernel{};
 }

@@ -1,21 +1,25 @@
 // Device kernels of the flux-differencing LGL-DGSEM (gfx950, wave64).
 //
-// Per right-hand side (or RK stage) two launches:
-//   face_kernel   one thread per face node: gathers the two traces and writes
-//                 the surface flux f* once per face (Sec. 2.4 remark on
-//                 computing surface fluxes once per surface);
-//   volume_kernel one 64-lane workgroup per tile of EPB elements:
-//                 prologue  coalesced load of u, primitive variables and
-//                           log(rho), log(p) once per node into LDS
-//                           (Sec. 7.1/7.2 precomputation);
-//                 sweeps    per direction, one lane per line, each lane
-//                           evaluating the i<k pairs of its line once and
-//                           scattering D~_ik F to node i and D~_ki F to node k
-//                           (skew-symmetric D~, Sec. 2.2; tensor-product
-//                           sparsity, Sec. 2.3), accumulated in LDS in a fixed
-//                           direction order (deterministic, no atomics);
-//                 epilogue  lifting of the face fluxes (+f*/w_p, -f*/w_0),
-//                           scaling by -1/J and the fused RK stage update.
+// One launch per right-hand side or RK stage, stage_kernel<DIM,N,VF,MESH>:
+// a workgroup owns EPB elements (Tile<DIM,N>) and
+//   prologue  loads u and the metric terms coalesced, computes the primitive
+//             variables and log(rho), log(p) once per node into LDS
+//             (Sec. 7.1/7.2 precomputation) and issues, without waiting, the
+//             loads of the face traces and of the RK registers needed later;
+//   per direction (tensor-product sparsity, Sec. 2.3):
+//     (1) one lane per pair i<k of every line evaluates the two-point volume
+//         flux in the direction of the averaged contravariant vectors once
+//         (skew-symmetric D~ with zero diagonal, Sec. 2.2) into LDS;
+//     (2) one lane per node sums D~_ab F(a,b) over its line in a fixed order
+//         (deterministic, no atomics);
+//   surface   one lane per face node evaluates f*(u_L, u_R, n_face) from the
+//             conservative traces of both elements; both elements of a face
+//             evaluate it with identical inputs, so f* is bitwise shared and
+//             the surface terms telescope exactly (Sec. 2.4: surface fluxes
+//             once per surface is the CPU choice; on the GPU recomputing
+//             avoids a launch and a round trip of f* through HBM);
+//   epilogue  lifting (+f*/w_p, -f*/w_0), scaling by -1/J and the fused RK
+//             stage update.
 // MFMA is not used: the volume term is an element-wise two-point flux
 // followed by a row-sum, not a dense contraction.
 #pragma once
@@ -35,7 +39,7 @@ enum RedOp { RED_TOTALS = 0, RED_ENTROPY = 1, RED_MAXLAMBDA = 2 };
 constexpr int kDevMaxN = 8;
 
 template <typename Real>
-struct LineOps {
+struct StageOps {
   Real Dt[kDevMaxN * kDevMaxN];  // D~ row-major
   Real inv_w0, inv_wp;           // 1/w_0, 1/w_p
   Real scale[3];                 // affine: 2/h_n ; curved: 1
@@ -43,31 +47,22 @@ struct LineOps {
 };
 
 template <typename Real>
-struct VolArgs {
+struct StageArgs {
   const Real* uin;     // stage input state [E][nv][nn]
   const Real* metric;  // curved: [E][dim*dim+1][nn] (Ja^n_m, then 1/J)
-  const Real* fstar;   // [dim][E][nv][nf] surface fluxes of + faces
+  const Real* nface;   // curved: [dim][E][dim][nf] normal of the + face of each element
   Real* out;           // MODE_RHS: du; RK: stage output y (FIRST, MID) or state (LAST)
   Real* acc;           // RK accumulator
   const Real* u0;      // RK state at the start of the step (MID)
-  const double* dt;    // device scalar time step
+  const double* dt;    // device scalar time step (CFL mode) or NULL
+  double dt_fixed;     // time step when dt is NULL
   int* flag;           // non-physical state flag
-  int64_t E;
+  int E;               // elements
   int n0, n1, n2;      // elements per direction
-  int mode;
+  int mode;            // StageMode
+  int surf;            // SurfFlux
   Real coef_b, coef_a; // RK: acc += b dt k ; y = u0 + a dt k
-  LineOps<Real> ops;
-};
-
-template <typename Real>
-struct FaceArgs {
-  const Real* u;       // [E][nv][nn]
-  const Real* nface;   // curved: [dim][E][dim][nf]
-  Real* fstar;         // [dim][E][nv][nf]
-  int64_t E;
-  int n0, n1, n2;
-  int N;
-  Real gamma, inv_gm1;
+  StageOps<Real> ops;
 };
 
 // ---------------------------------------------------------------------------
@@ -85,6 +80,20 @@ template <> struct LogMeanEps<float> { static constexpr float value = 2.0e-2f; }
 
 __device__ __forceinline__ double dev_log(double x) { return log(x); }
 __device__ __forceinline__ float dev_log(float x) { return __logf(x); }
+
+// Reciprocal: hardware estimate refined by Newton's iteration r <- r(2 - q r)
+// written as two fused multiply-adds (two steps in FP64, one in FP32).
+__device__ __forceinline__ double dev_rcp(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double e = fma(-q, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-q, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float dev_rcp(float q) {
+  const float r = __builtin_amdgcn_rcpf(q);
+  return fmaf(r, fmaf(-q, r, 1.0f), r);
+}
 
 // Primitive variables at one node, with log(rho) and log(p) when the volume
 // flux needs log means.
@@ -108,7 +117,7 @@ template <typename Real>
 __device__ __forceinline__ Real log_mean_pre(Real am, Real ap, Real lam, Real lap) {
   const Real s = am + ap, d = ap - am;
   const bool series = d * d < LogMeanEps<Real>::value * (s * s);
-  const Real r = Real(1) / (series ? s : (lap - lam));
+  const Real r = dev_rcp(series ? s : (lap - lam));
   const Real f = d * r;
   const Real u = f * f;
   const Real poly = Real(0.5) + u * (Real(-1.0 / 6.0) + u * (Real(-2.0 / 45.0) + u * Real(-22.0 / 945.0)));
@@ -119,7 +128,7 @@ template <typename Real>
 __device__ __forceinline__ Real inv_log_mean_pre(Real am, Real ap, Real lam, Real lap) {
   const Real s = am + ap, d = ap - am;
   const bool series = d * d < LogMeanEps<Real>::value * (s * s);
-  const Real r = Real(1) / (series ? s : d);
+  const Real r = dev_rcp(series ? s : d);
   const Real f = d * r;
   const Real u = f * f;
   const Real poly = Real(2) + u * (Real(2.0 / 3.0) + u * (Real(2.0 / 5.0) + u * Real(2.0 / 7.0)));
@@ -169,230 +178,13 @@ __device__ __forceinline__ void volume_flux(const Prim<Real>& a, const Prim<Real
 }
 
 // ---------------------------------------------------------------------------
-// volume kernel
-// ---------------------------------------------------------------------------
-
-template <int DIM, int N>
-struct Tile {
-  static constexpr int NN = Pow<N, DIM>::value;      // nodes per element
-  static constexpr int L = NN / N;                    // lines per direction
-  static constexpr int EPB = (64 / L) > 0 ? 64 / L : 1;  // elements per block
-  static constexpr int THREADS = 64;
-  static constexpr int NV = DIM + 2;
-};
-
-template <int VF, int DIM>
-struct PrimCount { static constexpr int value = (VF == VF_RANOCHA) ? DIM + 4 : DIM + 2; };
-
-// one direction of the flux-differencing sweep for one line
-template <int DIR, int DIM, int N, int VF, int MESH, typename Real>
-__device__ __forceinline__ void line_sweep(const Real* __restrict__ sp, Real* __restrict__ sa,
-                                           const Real* __restrict__ metric_e, int line, bool first,
-                                           const LineOps<Real>& ops) {
-  using T = Tile<DIM, N>;
-  constexpr int NN = T::NN;
-  constexpr int NV = T::NV;
-  constexpr int NP = PrimCount<VF, DIM>::value;
-  constexpr int stride = Pow<N, DIR>::value;
-  // base node of the line: remove the DIR digit
-  const int lo_part = line % stride;
-  const int hi_part = line / stride;
-  const int base = lo_part + hi_part * stride * N;
-
-  Prim<Real> P[N];
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const int q = base + k * stride;
-    P[k].rho = sp[0 * NN + q];
-    P[k].v0 = sp[1 * NN + q];
-    P[k].v1 = DIM > 1 ? sp[2 * NN + q] : Real(0);
-    P[k].v2 = DIM > 2 ? sp[3 * NN + q] : Real(0);
-    P[k].p = sp[(DIM + 1) * NN + q];
-    if (NP > DIM + 2) {
-      P[k].lr = sp[(DIM + 2) * NN + q];
-      P[k].lp = sp[(DIM + 3) * NN + q];
-    } else {
-      P[k].lr = P[k].lp = Real(0);
-    }
-  }
-  Real nrm[N][3];
-  if (MESH == MESH_CURVED) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      const int q = base + k * stride;
-#pragma unroll
-      for (int m = 0; m < 3; ++m) nrm[k][m] = m < DIM ? metric_e[(DIR * DIM + m) * NN + q] : Real(0);
-    }
-  }
-  Real A[N][NV];
-#pragma unroll
-  for (int k = 0; k < N; ++k)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) A[k][v] = Real(0);
-
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-#pragma unroll
-    for (int k = i + 1; k < N; ++k) {
-      Real F[NV];
-      if (MESH == MESH_CURVED) {
-        const Real nx = Real(0.5) * (nrm[i][0] + nrm[k][0]);
-        const Real ny = Real(0.5) * (nrm[i][1] + nrm[k][1]);
-        const Real nz = Real(0.5) * (nrm[i][2] + nrm[k][2]);
-        volume_flux<VF, DIM>(P[i], P[k], nx, ny, nz, ops.inv_gm1, F);
-      } else {
-        volume_flux<VF, DIM>(P[i], P[k], DIR == 0 ? Real(1) : Real(0), DIR == 1 ? Real(1) : Real(0),
-                             DIR == 2 ? Real(1) : Real(0), ops.inv_gm1, F);
-      }
-      const Real dik = ops.Dt[i * N + k], dki = ops.Dt[k * N + i];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        A[i][v] += dik * F[v];
-        A[k][v] += dki * F[v];
-      }
-    }
-  }
-  const Real sc = MESH == MESH_AFFINE ? ops.scale[DIR] : Real(1);
-#pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const int q = base + k * stride;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const Real val = MESH == MESH_AFFINE ? sc * A[k][v] : A[k][v];
-      if (first) sa[v * NN + q] = val;
-      else sa[v * NN + q] += val;
-    }
-  }
-}
-
-template <int DIM, int N, int VF, int MESH, typename Real>
-__global__ void __launch_bounds__(64) volume_kernel(VolArgs<Real> a) {
-  using T = Tile<DIM, N>;
-  constexpr int NN = T::NN, L = T::L, EPB = T::EPB, NV = T::NV;
-  constexpr int NP = PrimCount<VF, DIM>::value;
-  constexpr int NF = NN / N;
-  constexpr int NM = DIM * DIM + 1;
-  __shared__ Real s_prim[EPB][NP * NN];
-  __shared__ Real s_acc[EPB][NV * NN];
-
-  const int tid = threadIdx.x;
-  const int64_t e0 = (int64_t)blockIdx.x * EPB;
-  const Real gm1 = a.ops.gamma - Real(1);
-
-  // prologue: primitive variables (and logs) once per node
-  for (int q = tid; q < EPB * NN; q += T::THREADS) {
-    const int el = q / NN, i = q - el * NN;
-    const int64_t e = e0 + el;
-    if (e >= a.E) continue;
-    const Real* ue = a.uin + e * NV * NN;
-    const Real rho = ue[i];
-    const Real inv_rho = Real(1) / rho;
-    const Real m0 = ue[NN + i];
-    const Real m1 = DIM > 1 ? ue[2 * NN + i] : Real(0);
-    const Real m2 = DIM > 2 ? ue[3 * NN + i] : Real(0);
-    const Real E_ = ue[(DIM + 1) * NN + i];
-    const Real v0 = m0 * inv_rho, v1 = m1 * inv_rho, v2 = m2 * inv_rho;
-    const Real p = gm1 * (E_ - Real(0.5) * (m0 * v0 + m1 * v1 + m2 * v2));
-    if (!(rho > Real(0)) || !(p > Real(0)) || !isfinite(E_) || !isfinite(m0 + m1 + m2)) atomicOr(a.flag, 1);
-    Real* sp = s_prim[el];
-    sp[0 * NN + i] = rho;
-    sp[1 * NN + i] = v0;
-    if (DIM > 1) sp[2 * NN + i] = v1;
-    if (DIM > 2) sp[3 * NN + i] = v2;
-    sp[(DIM + 1) * NN + i] = p;
-    if (NP > DIM + 2) {
-      sp[(DIM + 2) * NN + i] = dev_log(rho);
-      sp[(DIM + 3) * NN + i] = dev_log(p);
-    }
-  }
-  __syncthreads();
-
-  // flux-differencing sweeps, one direction after the other
-  const int el = tid / L, line = tid - el * L;
-  const int64_t e = e0 + el;
-  const bool active = (tid < EPB * L) && (e < a.E);
-  const Real* me = MESH == MESH_CURVED && active ? a.metric + e * NM * NN : nullptr;
-  if (active) line_sweep<0, DIM, N, VF, MESH>(s_prim[el], s_acc[el], me, line, true, a.ops);
-  __syncthreads();
-  if (DIM > 1) {
-    if (active) line_sweep<(DIM > 1 ? 1 : 0), DIM, N, VF, MESH>(s_prim[el], s_acc[el], me, line, false, a.ops);
-    __syncthreads();
-  }
-  if (DIM > 2) {
-    if (active) line_sweep<(DIM > 2 ? 2 : 0), DIM, N, VF, MESH>(s_prim[el], s_acc[el], me, line, false, a.ops);
-    __syncthreads();
-  }
-
-  // epilogue: lifting, -1/J, stage update
-  const double dt = (a.mode == MODE_RHS) ? 0.0 : *a.dt;
-  for (int q = tid; q < EPB * NN; q += T::THREADS) {
-    const int el2 = q / NN, i = q - el2 * NN;
-    const int64_t ee = e0 + el2;
-    if (ee >= a.E) continue;
-    const int ix = i % N;
-    const int iy = DIM > 1 ? (i / N) % N : 0;
-    const int iz = DIM > 2 ? i / (N * N) : 0;
-    const int64_t ex = ee % a.n0;
-    const int64_t ey = (ee / a.n0) % a.n1;
-    const int64_t ez = ee / ((int64_t)a.n0 * a.n1);
-    Real S[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) S[v] = s_acc[el2][v * NN + i];
-#pragma unroll
-    for (int dir = 0; dir < DIM; ++dir) {
-      const int id = dir == 0 ? ix : (dir == 1 ? iy : iz);
-      if (id != 0 && id != N - 1) continue;
-      // face node index: the other node indices, lowest direction first
-      const int f = dir == 0 ? (iy + N * iz) : (dir == 1 ? (ix + N * iz) : (ix + N * iy));
-      const Real sc = MESH == MESH_AFFINE ? a.ops.scale[dir] : Real(1);
-      if (id == N - 1) {
-        const Real* fs = a.fstar + ((int64_t)dir * a.E + ee) * NV * NF;
-        const Real w = sc * a.ops.inv_wp;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) S[v] += w * fs[v * NF + f];
-      }
-      if (id == 0) {
-        int64_t mx = ex, my = ey, mz = ez;
-        if (dir == 0) mx = (ex + a.n0 - 1) % a.n0;
-        if (dir == 1) my = (ey + a.n1 - 1) % a.n1;
-        if (dir == 2) mz = (ez + a.n2 - 1) % a.n2;
-        const int64_t em = mx + (int64_t)a.n0 * (my + (int64_t)a.n1 * mz);
-        const Real* fs = a.fstar + ((int64_t)dir * a.E + em) * NV * NF;
-        const Real w = sc * a.ops.inv_w0;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) S[v] -= w * fs[v * NF + f];
-      }
-    }
-    const Real mul = MESH == MESH_CURVED ? -a.metric[(ee * NM + DIM * DIM) * NN + i] : Real(-1);
-    const int64_t base = ee * NV * NN + i;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const Real k = mul * S[v];
-      const int64_t o = base + (int64_t)v * NN;
-      if (a.mode == MODE_RHS) {
-        a.out[o] = k;
-      } else if (a.mode == MODE_RK_FIRST) {
-        const Real u0 = a.uin[o];
-        a.acc[o] = u0 + a.coef_b * (Real)dt * k;
-        a.out[o] = u0 + a.coef_a * (Real)dt * k;
-      } else if (a.mode == MODE_RK_MID) {
-        a.acc[o] = a.acc[o] + a.coef_b * (Real)dt * k;
-        a.out[o] = a.u0[o] + a.coef_a * (Real)dt * k;
-      } else {
-        a.out[o] = a.acc[o] + a.coef_b * (Real)dt * k;
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// surface flux kernel (one thread per face node)
+// surface flux from conservative traces
 // ---------------------------------------------------------------------------
 
 template <int DIM, typename Real>
 __device__ __forceinline__ void cons_to_prim(const Real* u, Real gm1, Prim<Real>& P) {
   P.rho = u[0];
-  const Real ir = Real(1) / P.rho;
+  const Real ir = dev_rcp(P.rho);
   P.v0 = u[1] * ir;
   P.v1 = DIM > 1 ? u[2] * ir : Real(0);
   P.v2 = DIM > 2 ? u[3] * ir : Real(0);
@@ -401,74 +193,378 @@ __device__ __forceinline__ void cons_to_prim(const Real* u, Real gm1, Prim<Real>
   P.lr = P.lp = Real(0);
 }
 
-template <int DIM, int SF, int MESH, typename Real>
-__global__ void __launch_bounds__(256) face_kernel(FaceArgs<Real> a) {
-  constexpr int NV = DIM + 2;
-  const int N = a.N;
-  const int NF = DIM == 3 ? N * N : N;
-  const int NN = NF * N;
-  const int64_t total = (int64_t)DIM * a.E * NF;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= total) return;
-  const int dir = (int)(gid / (a.E * NF));
-  const int64_t rem = gid - (int64_t)dir * a.E * NF;
-  const int64_t e = rem / NF;
-  const int f = (int)(rem - e * NF);
-  // node indices of face node f on the + face (L) and - face (R)
-  const int sa = dir == 0 ? 1 : (dir == 1 ? N : N * N);
-  const int lo_part = f % sa, hi_part = f / sa;
-  const int qL = lo_part + (N - 1) * sa + hi_part * sa * N;
-  const int qR = lo_part + hi_part * sa * N;
-  int64_t ex = e % a.n0, ey = (e / a.n0) % a.n1, ez = e / ((int64_t)a.n0 * a.n1);
-  if (dir == 0) ex = (ex + 1) % a.n0;
-  if (dir == 1) ey = (ey + 1) % a.n1;
-  if (dir == 2) ez = (ez + 1) % a.n2;
-  const int64_t eR = ex + (int64_t)a.n0 * (ey + (int64_t)a.n1 * ez);
-  Real uL[NV], uR[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    uL[v] = a.u[(e * NV + v) * NN + qL];
-    uR[v] = a.u[(eR * NV + v) * NN + qR];
-  }
-  Real nx, ny, nz;
-  if (MESH == MESH_CURVED) {
-    const Real* nf = a.nface + ((int64_t)dir * a.E + e) * DIM * NF + f;
-    nx = nf[0];
-    ny = DIM > 1 ? nf[NF] : Real(0);
-    nz = DIM > 2 ? nf[2 * NF] : Real(0);
-  } else {
-    nx = dir == 0 ? Real(1) : Real(0);
-    ny = dir == 1 ? Real(1) : Real(0);
-    nz = dir == 2 ? Real(1) : Real(0);
-  }
-  const Real gm1 = a.gamma - Real(1);
+// f*(u_L, u_R, n) of kind sf (runtime, uniform across the launch)
+template <int DIM, typename Real>
+__device__ __forceinline__ void surface_flux(int sf, const Real* uL, const Real* uR, Real nx, Real ny, Real nz,
+                                             Real gamma, Real inv_gm1, Real* F) {
+  const Real gm1 = gamma - Real(1);
   Prim<Real> PL, PR;
   cons_to_prim<DIM>(uL, gm1, PL);
   cons_to_prim<DIM>(uR, gm1, PR);
-  Real F[NV];
-  if (SF == SF_RANOCHA) {
+  if (sf == SF_RANOCHA) {
     PL.lr = dev_log(PL.rho);
     PL.lp = dev_log(PL.p);
     PR.lr = dev_log(PR.rho);
     PR.lp = dev_log(PR.p);
-    volume_flux<VF_RANOCHA, DIM>(PL, PR, nx, ny, nz, a.inv_gm1, F);
-  } else if (SF == SF_SHIMA) {
-    volume_flux<VF_SHIMA, DIM>(PL, PR, nx, ny, nz, a.inv_gm1, F);
+    volume_flux<VF_RANOCHA, DIM>(PL, PR, nx, ny, nz, inv_gm1, F);
+  } else if (sf == SF_SHIMA) {
+    volume_flux<VF_SHIMA, DIM>(PL, PR, nx, ny, nz, inv_gm1, F);
   } else {
-    volume_flux<VF_CENTRAL, DIM>(PL, PR, nx, ny, nz, a.inv_gm1, F);
-    if (SF == SF_LLF) {
+    volume_flux<VF_CENTRAL, DIM>(PL, PR, nx, ny, nz, inv_gm1, F);
+    if (sf == SF_LLF) {
       const Real vnL = PL.v0 * nx + PL.v1 * ny + PL.v2 * nz;
       const Real vnR = PR.v0 * nx + PR.v1 * ny + PR.v2 * nz;
-      const Real cL = sqrt(a.gamma * PL.p / PL.rho), cR = sqrt(a.gamma * PR.p / PR.rho);
+      const Real cL = sqrt(gamma * PL.p * dev_rcp(PL.rho)), cR = sqrt(gamma * PR.p * dev_rcp(PR.rho));
       const Real nn = sqrt(nx * nx + ny * ny + nz * nz);
       const Real lam = fmax(fabs(vnL), fabs(vnR)) + fmax(cL, cR) * nn;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) F[v] -= Real(0.5) * lam * (uR[v] - uL[v]);
+      for (int v = 0; v < DIM + 2; ++v) F[v] -= Real(0.5) * lam * (uR[v] - uL[v]);
     }
   }
-  Real* out = a.fstar + ((int64_t)dir * a.E + e) * NV * NF + f;
+}
+
+// ---------------------------------------------------------------------------
+// fused stage kernel
+// ---------------------------------------------------------------------------
+
+// Tile of one workgroup: EPB elements, THREADS lanes.  Per direction there are
+// TDIR = (lines per element) x (pairs i<k per line) two-point fluxes and
+// NFACE = 2 DIM N^(DIM-1) face nodes per element; the workgroup is sized so
+// that the pairs of one direction, the face nodes and the nodes of all its
+// elements each get a lane (up to 1024 lanes).
+template <int DIM, int N>
+struct Tile {
+  static constexpr int NN = Pow<N, DIM>::value;   // nodes per element
+  static constexpr int NF = NN / N;               // nodes per face
+  static constexpr int L = NN / N;                // lines per direction
+  static constexpr int NPAIR = N * (N - 1) / 2;   // pairs i<k per line
+  static constexpr int TDIR = L * NPAIR;          // pair fluxes per direction
+  static constexpr int NFACE = 2 * DIM * NF;      // face nodes per element
+  static constexpr int W1 = TDIR > NN ? TDIR : NN;
+  static constexpr int WORK = W1 > NFACE ? W1 : NFACE;
+  static constexpr int EPB = (192 / WORK) > 0 ? 192 / WORK : 1;  // elements per block
+  static constexpr int T0 = ((EPB * WORK + 63) / 64) * 64;
+  static constexpr int THREADS = T0 > 1024 ? 1024 : T0;
+  static constexpr int NPT = (EPB * NN + THREADS - 1) / THREADS;     // nodes per lane
+  static constexpr int FPT = (EPB * NFACE + THREADS - 1) / THREADS;  // face nodes per lane
+  static constexpr int NSLOT = TDIR > NFACE ? TDIR : NFACE;          // LDS flux slots
+  static constexpr int NV = DIM + 2;
+};
+
+template <int VF, int DIM>
+struct PrimCount { static constexpr int value = (VF == VF_RANOCHA) ? DIM + 4 : DIM + 2; };
+
+// triangular enumeration of the pairs (i, k), i < k, of one line
+template <int N>
+__device__ __forceinline__ void pair_nodes(int p, int& i, int& k) {
+  int ii = 0, rem = p;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) out[v * NF] = F[v];
+  for (int s = 0; s < N - 1; ++s) {
+    if (rem >= N - 1 - ii) {
+      rem -= N - 1 - ii;
+      ++ii;
+    }
+  }
+  i = ii;
+  k = ii + 1 + rem;
+}
+
+template <int N>
+__device__ __forceinline__ int pair_index(int a, int b) {  // a < b
+  return a * (2 * N - a - 1) / 2 + (b - a - 1);
+}
+
+template <int N>
+__device__ __forceinline__ int node_digit(int q, int dir) {
+  return dir == 0 ? q % N : (dir == 1 ? (q / N) % N : q / (N * N));
+}
+
+// node of face node f (other digits, lowest direction first) with digit `pos` in direction dir
+template <int N>
+__device__ __forceinline__ int face_node(int dir, int f, int pos) {
+  const int sa = dir == 0 ? 1 : (dir == 1 ? N : N * N);
+  return (f % sa) + pos * sa + (f / sa) * sa * N;
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of tiles so that neighbouring elements (whose traces a
+// tile reads) are processed by the same XCD and hit its L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+  const int q = G >> 3;
+  return b < (q << 3) ? (b & 7) * q + (b >> 3) : b;
+}
+
+template <int DIM, int N, int VF, int MESH, typename Real>
+__global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) stage_kernel(StageArgs<Real> a) {
+  using T = Tile<DIM, N>;
+  constexpr int NN = T::NN, NF = T::NF, EPB = T::EPB, NV = T::NV, NPAIR = T::NPAIR, TDIR = T::TDIR;
+  constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, NFACE = T::NFACE, NSLOT = T::NSLOT;
+  constexpr int NP = PrimCount<VF, DIM>::value;
+  constexpr int NM = DIM * DIM + 1;
+  constexpr int NJ = MESH == MESH_CURVED ? DIM * DIM : 1;
+  __shared__ Real s_prim[EPB][NP][NN];     // rho, v, p (, log rho, log p)
+  __shared__ Real s_ja[EPB][NJ][NN];       // contravariant vectors (curved)
+  __shared__ Real s_flux[EPB][NV][NSLOT];  // pair fluxes of one direction, then face fluxes
+  __shared__ Real s_dt[N * N];             // D~
+  __shared__ int s_nbr[EPB][2 * DIM];      // neighbour across face (2 dir + side), side 1 = +
+
+  const int tid = threadIdx.x;
+  const int e0 = xcd_tile(blockIdx.x, gridDim.x) * EPB;
+  const Real gm1 = a.ops.gamma - Real(1);
+  if (tid < N * N) s_dt[tid] = a.ops.Dt[tid];
+  if (tid < EPB) {
+    const int e = e0 + tid;
+    const int ex = e % a.n0, ey = (e / a.n0) % a.n1, ez = e / (a.n0 * a.n1);
+    const int exm = ex == 0 ? a.n0 - 1 : ex - 1, exp_ = ex == a.n0 - 1 ? 0 : ex + 1;
+    s_nbr[tid][0] = exm + a.n0 * (ey + a.n1 * ez);
+    s_nbr[tid][1] = exp_ + a.n0 * (ey + a.n1 * ez);
+    if (DIM > 1) {
+      const int eym = ey == 0 ? a.n1 - 1 : ey - 1, eyp = ey == a.n1 - 1 ? 0 : ey + 1;
+      s_nbr[tid][DIM > 1 ? 2 : 0] = ex + a.n0 * (eym + a.n1 * ez);
+      s_nbr[tid][DIM > 1 ? 3 : 0] = ex + a.n0 * (eyp + a.n1 * ez);
+    }
+    if (DIM > 2) {
+      const int ezm = ez == 0 ? a.n2 - 1 : ez - 1, ezp = ez == a.n2 - 1 ? 0 : ez + 1;
+      s_nbr[tid][DIM > 2 ? 4 : 0] = ex + a.n0 * (ey + a.n1 * ezm);
+      s_nbr[tid][DIM > 2 ? 5 : 0] = ex + a.n0 * (ey + a.n1 * ezp);
+    }
+  }
+  __syncthreads();
+
+  // ---- loads: own state and metrics (needed first), then traces and RK
+  // registers, all issued before any is consumed.  Indices of lanes without
+  // work are clamped to element 0 so that every address stays in bounds.
+  Real uo[NPT][NV], mo[NPT][NM];
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int q = tid + r * THREADS;
+    const int el = q / NN, i = q - el * NN;
+    const bool ok = q < EPB * NN && e0 + el < a.E;
+    const size_t o = ok ? (size_t)(e0 + el) * (NV * NN) + i : 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) uo[r][v] = a.uin[o + (size_t)v * NN];
+    if (MESH == MESH_CURVED) {
+      const size_t om = ok ? (size_t)(e0 + el) * (NM * NN) + i : 0;
+#pragma unroll
+      for (int c = 0; c < NM; ++c) mo[r][c] = a.metric[om + (size_t)c * NN];
+    }
+  }
+  Real tL[FPT][NV], tR[FPT][NV], tn[FPT][3];
+#pragma unroll
+  for (int r = 0; r < FPT; ++r) {
+    const int t = tid + r * THREADS;
+    const int el = t / NFACE, rr = t - el * NFACE;
+    const bool ok = t < EPB * NFACE && e0 + el < a.E;
+    const int fc = rr / NF, f = rr - fc * NF, dir = fc >> 1, side = fc & 1;
+    const int e = ok ? e0 + el : 0;
+    const int en = ok ? s_nbr[el][fc] : 0;
+    const int eL = side ? e : en, eR = side ? en : e;
+    const int qL = face_node<N>(dir, f, N - 1), qR = face_node<N>(dir, f, 0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      tL[r][v] = a.uin[(size_t)eL * (NV * NN) + v * NN + qL];
+      tR[r][v] = a.uin[(size_t)eR * (NV * NN) + v * NN + qR];
+    }
+    if (MESH == MESH_CURVED) {
+      const Real* nf = a.nface + ((size_t)dir * a.E + eL) * (DIM * NF) + f;
+      tn[r][0] = nf[0];
+      tn[r][1] = DIM > 1 ? nf[NF] : Real(0);
+      tn[r][2] = DIM > 2 ? nf[2 * NF] : Real(0);
+    } else {
+      tn[r][0] = dir == 0 ? Real(1) : Real(0);
+      tn[r][1] = dir == 1 ? Real(1) : Real(0);
+      tn[r][2] = dir == 2 ? Real(1) : Real(0);
+    }
+  }
+  Real ru0[NPT][NV], racc[NPT][NV];
+  const bool need_u0 = a.mode == MODE_RK_MID;
+  const bool need_acc = a.mode == MODE_RK_MID || a.mode == MODE_RK_LAST;
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int q = tid + r * THREADS;
+    const int el = q / NN, i = q - el * NN;
+    const bool ok = q < EPB * NN && e0 + el < a.E;
+    const size_t o = ok ? (size_t)(e0 + el) * (NV * NN) + i : 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      ru0[r][v] = need_u0 ? a.u0[o + (size_t)v * NN] : Real(0);
+      racc[r][v] = need_acc ? a.acc[o + (size_t)v * NN] : Real(0);
+    }
+  }
+
+  // ---- prologue: primitive variables (and logs) once per node
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int q = tid + r * THREADS;
+    const int el = q / NN, i = q - el * NN;
+    if (!(q < EPB * NN && e0 + el < a.E)) continue;
+    const Real rho = uo[r][0];
+    const Real inv_rho = dev_rcp(rho);
+    const Real m0 = uo[r][1];
+    const Real m1 = DIM > 1 ? uo[r][DIM > 1 ? 2 : 1] : Real(0);
+    const Real m2 = DIM > 2 ? uo[r][DIM > 2 ? 3 : 1] : Real(0);
+    const Real E_ = uo[r][DIM + 1];
+    const Real v0 = m0 * inv_rho, v1 = m1 * inv_rho, v2 = m2 * inv_rho;
+    const Real p = gm1 * (E_ - Real(0.5) * (m0 * v0 + m1 * v1 + m2 * v2));
+    if (!(rho > Real(0)) || !(p > Real(0)) || !isfinite(E_) || !isfinite(m0 + m1 + m2)) atomicOr(a.flag, 1);
+    s_prim[el][0][i] = rho;
+    s_prim[el][1][i] = v0;
+    if (DIM > 1) s_prim[el][DIM > 1 ? 2 : 0][i] = v1;
+    if (DIM > 2) s_prim[el][DIM > 2 ? 3 : 0][i] = v2;
+    s_prim[el][DIM + 1][i] = p;
+    if (NP > DIM + 2) {
+      s_prim[el][(NP > DIM + 2) ? DIM + 2 : 0][i] = dev_log(rho);
+      s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][i] = dev_log(p);
+    }
+    if (MESH == MESH_CURVED) {
+#pragma unroll
+      for (int c = 0; c < NJ; ++c) s_ja[el][c][i] = mo[r][c];
+    }
+  }
+  __syncthreads();
+
+  Real acc[NPT][NV];
+#pragma unroll
+  for (int r = 0; r < NPT; ++r)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[r][v] = Real(0);
+
+  // ---- volume: per direction, pair fluxes then line sums
+#pragma unroll
+  for (int dir = 0; dir < DIM; ++dir) {
+    const int stride = dir == 0 ? 1 : (dir == 1 ? N : N * N);
+    for (int t = tid; t < EPB * TDIR; t += THREADS) {
+      const int el = t / TDIR;
+      const int r = t - el * TDIR;
+      const int line = r / NPAIR;
+      const int pr = r - line * NPAIR;
+      if (e0 + el >= a.E) continue;
+      int i, k;
+      pair_nodes<N>(pr, i, k);
+      const int base = (line % stride) + (line / stride) * stride * N;
+      const int qi = base + i * stride, qk = base + k * stride;
+      Prim<Real> Pi, Pk;
+      Pi.rho = s_prim[el][0][qi];
+      Pk.rho = s_prim[el][0][qk];
+      Pi.v0 = s_prim[el][1][qi];
+      Pk.v0 = s_prim[el][1][qk];
+      Pi.v1 = DIM > 1 ? s_prim[el][DIM > 1 ? 2 : 0][qi] : Real(0);
+      Pk.v1 = DIM > 1 ? s_prim[el][DIM > 1 ? 2 : 0][qk] : Real(0);
+      Pi.v2 = DIM > 2 ? s_prim[el][DIM > 2 ? 3 : 0][qi] : Real(0);
+      Pk.v2 = DIM > 2 ? s_prim[el][DIM > 2 ? 3 : 0][qk] : Real(0);
+      Pi.p = s_prim[el][DIM + 1][qi];
+      Pk.p = s_prim[el][DIM + 1][qk];
+      if (NP > DIM + 2) {
+        Pi.lr = s_prim[el][(NP > DIM + 2) ? DIM + 2 : 0][qi];
+        Pk.lr = s_prim[el][(NP > DIM + 2) ? DIM + 2 : 0][qk];
+        Pi.lp = s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][qi];
+        Pk.lp = s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][qk];
+      } else {
+        Pi.lr = Pk.lr = Pi.lp = Pk.lp = Real(0);
+      }
+      Real F[NV];
+      if (MESH == MESH_CURVED) {
+        const int c0 = dir * DIM;
+        const Real nx = Real(0.5) * (s_ja[el][(c0) % NJ][qi] + s_ja[el][(c0) % NJ][qk]);
+        const Real ny = DIM > 1 ? Real(0.5) * (s_ja[el][(c0 + 1) % NJ][qi] + s_ja[el][(c0 + 1) % NJ][qk]) : Real(0);
+        const Real nz = DIM > 2 ? Real(0.5) * (s_ja[el][(c0 + 2) % NJ][qi] + s_ja[el][(c0 + 2) % NJ][qk]) : Real(0);
+        volume_flux<VF, DIM>(Pi, Pk, nx, ny, nz, a.ops.inv_gm1, F);
+      } else {
+        volume_flux<VF, DIM>(Pi, Pk, dir == 0 ? Real(1) : Real(0), dir == 1 ? Real(1) : Real(0),
+                             dir == 2 ? Real(1) : Real(0), a.ops.inv_gm1, F);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_flux[el][v][r] = F[v];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+      const int q = tid + r * THREADS;
+      if (q >= EPB * NN) continue;
+      const int el = q / NN, i = q - el * NN;
+      const int pos = node_digit<N>(i, dir);
+      const int line = (i % stride) + (i / (stride * N)) * stride;
+      Real sum[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sum[v] = Real(0);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        if (b == pos) continue;
+        const int pr = line * NPAIR + (b > pos ? pair_index<N>(pos, b) : pair_index<N>(b, pos));
+        const Real d = s_dt[pos * N + b];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sum[v] += d * s_flux[el][v][pr];
+      }
+      const Real sc = MESH == MESH_AFFINE ? a.ops.scale[dir] : Real(1);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[r][v] += MESH == MESH_AFFINE ? sc * sum[v] : sum[v];
+    }
+    __syncthreads();
+  }
+
+  // ---- surface fluxes of the element's faces into the (now free) flux slots
+#pragma unroll
+  for (int r = 0; r < FPT; ++r) {
+    const int t = tid + r * THREADS;
+    const int el = t / NFACE, rr = t - el * NFACE;
+    if (!(t < EPB * NFACE && e0 + el < a.E)) continue;
+    Real F[NV];
+    surface_flux<DIM>(a.surf, tL[r], tR[r], tn[r][0], tn[r][1], tn[r][2], a.ops.gamma, a.ops.inv_gm1, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s_flux[el][v][rr] = F[v];
+  }
+  __syncthreads();
+
+  // ---- epilogue: lifting, -1/J, stage update
+  const double dt = (a.mode == MODE_RHS) ? 0.0 : (a.dt ? *a.dt : a.dt_fixed);
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int q = tid + r * THREADS;
+    const int el = q / NN, i = q - el * NN;
+    if (!(q < EPB * NN && e0 + el < a.E)) continue;
+    const int ee = e0 + el;
+    const int ix = i % N;
+    const int iy = DIM > 1 ? (i / N) % N : 0;
+    const int iz = DIM > 2 ? i / (N * N) : 0;
+    Real S[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) S[v] = acc[r][v];
+#pragma unroll
+    for (int dir = 0; dir < DIM; ++dir) {
+      const int id = dir == 0 ? ix : (dir == 1 ? iy : iz);
+      if (id != 0 && id != N - 1) continue;
+      const int f = dir == 0 ? (iy + N * iz) : (dir == 1 ? (ix + N * iz) : (ix + N * iy));
+      const Real sc = MESH == MESH_AFFINE ? a.ops.scale[dir] : Real(1);
+      if (id == N - 1) {
+        const Real w = sc * a.ops.inv_wp;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[v] += w * s_flux[el][v][(2 * dir + 1) * NF + f];
+      }
+      if (id == 0) {
+        const Real w = sc * a.ops.inv_w0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S[v] -= w * s_flux[el][v][(2 * dir) * NF + f];
+      }
+    }
+    const Real mul = MESH == MESH_CURVED ? -mo[r][NM - 1] : Real(-1);
+    const size_t base = (size_t)ee * (NV * NN) + i;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const Real k = mul * S[v];
+      const size_t o = base + (size_t)v * NN;
+      if (a.mode == MODE_RHS) {
+        a.out[o] = k;
+      } else if (a.mode == MODE_RK_FIRST) {
+        a.acc[o] = uo[r][v] + a.coef_b * (Real)dt * k;
+        a.out[o] = uo[r][v] + a.coef_a * (Real)dt * k;
+      } else if (a.mode == MODE_RK_MID) {
+        a.acc[o] = racc[r][v] + a.coef_b * (Real)dt * k;
+        a.out[o] = ru0[r][v] + a.coef_a * (Real)dt * k;
+      } else {
+        a.out[o] = racc[r][v] + a.coef_b * (Real)dt * k;
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -582,7 +678,7 @@ __global__ void __launch_bounds__(kRedThreads) reduce_partial_kernel(RedArgs<Rea
 
 // Final pass: one block folds the partials in index order.  For
 // RED_MAXLAMBDA it also turns lam_max into dt = cfl*2/(N lam_max), stores it
-// in scal[0] and, if advance_t, adds it to scal[1].
+// in scal[0] and adds it to (advance_t == 1) or stores it in (== 2) scal[1].
 template <int OP>
 __global__ void __launch_bounds__(kRedThreads) reduce_final_kernel(const double* partial, int blocks, int K,
                                                                      double* out, double cfl, int N,
@@ -618,7 +714,8 @@ __global__ void __launch_bounds__(kRedThreads) reduce_final_kernel(const double*
         out[k] = dt;
         if (scal) {
           scal[0] = dt;
-          if (advance_t) scal[1] += dt;
+          if (advance_t == 1) scal[1] += dt;  // accumulate the time
+          if (advance_t == 2) scal[1] = dt;   // first step of a call
         }
       } else {
         out[k] = sh[0];

@@ -21,7 +21,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONPHYSICAL, ESTATE = 0, -1, -2, -3, -4, -5
 FLUX = {"ranocha": 0, "shima": 1, "llf": 2, "central": 3}
 PRECISION = {"fp64": 0, "fp32": 1}
 HOST, DEVICE = 0, 1
-KERNEL_FACE, KERNEL_VOLUME, KERNEL_REDUCE = 0, 1, 2
+KERNEL_STAGE, KERNEL_REDUCE = 1, 2
 PMAX = 7
 
 
