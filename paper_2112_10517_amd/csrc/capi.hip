@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/esdg.h"
+#include "esdg.h"
 #include "dispatch.hpp"
 #include "host_ops.hpp"
 #include "kernels.hpp"

@@ -2,21 +2,20 @@
 //
 // One launch per right-hand side or RK stage, stage_kernel<DIM,N,VF,MESH>:
 // a workgroup owns EPB elements (Tile<DIM,N>) and
-//   prologue  loads u and the metric terms coalesced, computes the primitive
-//             variables and log(rho), log(p) once per node into LDS
-//             (Sec. 7.1/7.2 precomputation) and issues, without waiting, the
-//             loads of the face traces and of the RK registers needed later;
-//   per direction (tensor-product sparsity, Sec. 2.3):
-//     (1) one lane per pair i<k of every line evaluates the two-point volume
-//         flux in the direction of the averaged contravariant vectors once
-//         (skew-symmetric D~ with zero diagonal, Sec. 2.2) into LDS;
-//     (2) one lane per node sums D~_ab F(a,b) over its line in a fixed order
-//         (deterministic, no atomics);
+//   prologue  loads u coalesced and computes the primitive variables and
+//             log(rho), log(p) once per node into LDS (Sec. 7.1/7.2
+//             precomputation);
+//   lines     one lane per (direction, element, line): the lane evaluates the
+//             N(N-1)/2 pairs i<k of its line once each, with the two-point
+//             volume flux in the direction of the averaged contravariant
+//             vectors (Sec. 2.3 rearranged form; skew-symmetric D~ with zero
+//             diagonal, Sec. 2.2), accumulating D~_ik F and D~_ki F in
+//             registers; all directions run concurrently and are summed per
+//             node in a fixed order (deterministic, no atomics);
 //   surface   one lane per face node evaluates f*(u_L, u_R, n_face) from the
 //             conservative traces of both elements; both elements of a face
 //             evaluate it with identical inputs, so f* is bitwise shared and
-//             the surface terms telescope exactly (Sec. 2.4: surface fluxes
-//             once per surface is the CPU choice; on the GPU recomputing
+//             the surface terms telescope exactly (computing it on each side
 //             avoids a launch and a round trip of f* through HBM);
 //   epilogue  lifting (+f*/w_p, -f*/w_0), scaling by -1/J and the fused RK
 //             stage update.
@@ -227,57 +226,29 @@ __device__ __forceinline__ void surface_flux(int sf, const Real* uL, const Real*
 // fused stage kernel
 // ---------------------------------------------------------------------------
 
-// Tile of one workgroup: EPB elements, THREADS lanes.  Per direction there are
-// TDIR = (lines per element) x (pairs i<k per line) two-point fluxes and
-// NFACE = 2 DIM N^(DIM-1) face nodes per element; the workgroup is sized so
-// that the pairs of one direction, the face nodes and the nodes of all its
-// elements each get a lane (up to 1024 lanes).
+// Tile of one workgroup: EPB elements.  The line phase gives one lane to each
+// (direction, element, line); the lanes of one direction fill whole waves, so
+// a wave never diverges on the direction.  Node and face-node work is spread
+// over all lanes of the workgroup.
 template <int DIM, int N>
 struct Tile {
   static constexpr int NN = Pow<N, DIM>::value;   // nodes per element
   static constexpr int NF = NN / N;               // nodes per face
   static constexpr int L = NN / N;                // lines per direction
-  static constexpr int NPAIR = N * (N - 1) / 2;   // pairs i<k per line
-  static constexpr int TDIR = L * NPAIR;          // pair fluxes per direction
   static constexpr int NFACE = 2 * DIM * NF;      // face nodes per element
-  static constexpr int W1 = TDIR > NN ? TDIR : NN;
-  static constexpr int WORK = W1 > NFACE ? W1 : NFACE;
-  static constexpr int EPB = (192 / WORK) > 0 ? 192 / WORK : 1;  // elements per block
-  static constexpr int T0 = ((EPB * WORK + 63) / 64) * 64;
-  static constexpr int THREADS = T0 > 1024 ? 1024 : T0;
+  static constexpr int EPB = (64 / L) > 0 ? 64 / L : 1;  // elements per block
+  static constexpr int LANES_DIR = ((EPB * L + 63) / 64) * 64;  // lanes per direction
+  static constexpr int THREADS = DIM * LANES_DIR;
   static constexpr int NPT = (EPB * NN + THREADS - 1) / THREADS;     // nodes per lane
   static constexpr int FPT = (EPB * NFACE + THREADS - 1) / THREADS;  // face nodes per lane
-  static constexpr int NSLOT = TDIR > NFACE ? TDIR : NFACE;          // LDS flux slots
   static constexpr int NV = DIM + 2;
+  // waves per SIMD the register allocation must allow: every workgroup of a
+  // typical launch resident at once (3 x 64-lane waves per SIMD for N <= 4)
+  static constexpr int WPE = N <= 4 ? 3 : (N <= 6 ? 2 : 1);
 };
 
 template <int VF, int DIM>
 struct PrimCount { static constexpr int value = (VF == VF_RANOCHA) ? DIM + 4 : DIM + 2; };
-
-// triangular enumeration of the pairs (i, k), i < k, of one line
-template <int N>
-__device__ __forceinline__ void pair_nodes(int p, int& i, int& k) {
-  int ii = 0, rem = p;
-#pragma unroll
-  for (int s = 0; s < N - 1; ++s) {
-    if (rem >= N - 1 - ii) {
-      rem -= N - 1 - ii;
-      ++ii;
-    }
-  }
-  i = ii;
-  k = ii + 1 + rem;
-}
-
-template <int N>
-__device__ __forceinline__ int pair_index(int a, int b) {  // a < b
-  return a * (2 * N - a - 1) / 2 + (b - a - 1);
-}
-
-template <int N>
-__device__ __forceinline__ int node_digit(int q, int dir) {
-  return dir == 0 ? q % N : (dir == 1 ? (q / N) % N : q / (N * N));
-}
 
 // node of face node f (other digits, lowest direction first) with digit `pos` in direction dir
 template <int N>
@@ -294,24 +265,77 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
   return b < (q << 3) ? (b & 7) * q + (b >> 3) : b;
 }
 
+// The i<k pairs of one line in direction DIR: the lane loads the line's
+// primitive variables (LDS) and averaged contravariant vectors, evaluates each
+// two-point flux once and scatters D~_ik F to node i and D~_ki F to node k in
+// registers (skew-symmetric D~ with zero diagonal, Sec. 2.2; all indices are
+// compile-time constants).
+template <int DIR, int DIM, int N, int VF, int MESH, typename Real>
+__device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value], const Real (&nrm)[N][3], int base,
+                                            const StageOps<Real>& ops, Real (&A)[N][DIM + 2]) {
+  constexpr int NV = DIM + 2;
+  constexpr int NP = PrimCount<VF, DIM>::value;
+  constexpr int stride = Pow<N, DIR>::value;
+  Prim<Real> P[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int q = base + k * stride;
+    P[k].rho = sp[0][q];
+    P[k].v0 = sp[1][q];
+    P[k].v1 = DIM > 1 ? sp[DIM > 1 ? 2 : 0][q] : Real(0);
+    P[k].v2 = DIM > 2 ? sp[DIM > 2 ? 3 : 0][q] : Real(0);
+    P[k].p = sp[DIM + 1][q];
+    P[k].lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][q] : Real(0);
+    P[k].lp = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][q] : Real(0);
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) A[k][v] = Real(0);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int k = i + 1; k < N; ++k) {
+      Real F[NV];
+      if (MESH == MESH_CURVED) {
+        volume_flux<VF, DIM>(P[i], P[k], Real(0.5) * (nrm[i][0] + nrm[k][0]), Real(0.5) * (nrm[i][1] + nrm[k][1]),
+                             Real(0.5) * (nrm[i][2] + nrm[k][2]), ops.inv_gm1, F);
+      } else {
+        volume_flux<VF, DIM>(P[i], P[k], DIR == 0 ? Real(1) : Real(0), DIR == 1 ? Real(1) : Real(0),
+                             DIR == 2 ? Real(1) : Real(0), ops.inv_gm1, F);
+      }
+      const Real dik = ops.Dt[i * N + k], dki = ops.Dt[k * N + i];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        A[i][v] += dik * F[v];
+        A[k][v] += dki * F[v];
+      }
+    }
+  }
+  if (MESH == MESH_AFFINE) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) A[k][v] *= ops.scale[DIR];
+  }
+}
+
 template <int DIM, int N, int VF, int MESH, typename Real>
-__global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) stage_kernel(StageArgs<Real> a) {
+__global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(Tile<DIM, N>::WPE)))
+stage_kernel(StageArgs<Real> a) {
   using T = Tile<DIM, N>;
-  constexpr int NN = T::NN, NF = T::NF, EPB = T::EPB, NV = T::NV, NPAIR = T::NPAIR, TDIR = T::TDIR;
-  constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, NFACE = T::NFACE, NSLOT = T::NSLOT;
+  constexpr int NN = T::NN, NF = T::NF, L = T::L, EPB = T::EPB, NV = T::NV, NFACE = T::NFACE;
+  constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, LANES_DIR = T::LANES_DIR;
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int NM = DIM * DIM + 1;
-  constexpr int NJ = MESH == MESH_CURVED ? DIM * DIM : 1;
-  __shared__ Real s_prim[EPB][NP][NN];     // rho, v, p (, log rho, log p)
-  __shared__ Real s_ja[EPB][NJ][NN];       // contravariant vectors (curved)
-  __shared__ Real s_flux[EPB][NV][NSLOT];  // pair fluxes of one direction, then face fluxes
-  __shared__ Real s_dt[N * N];             // D~
+  __shared__ Real s_prim[EPB][NP][NN];     // primitive variables (and logs)
+  __shared__ Real s_face[EPB][NV][NFACE];  // surface fluxes of the element's faces
+  __shared__ Real s_acc[EPB][NV][NN];      // volume term, summed over directions in order
   __shared__ int s_nbr[EPB][2 * DIM];      // neighbour across face (2 dir + side), side 1 = +
 
   const int tid = threadIdx.x;
   const int e0 = xcd_tile(blockIdx.x, gridDim.x) * EPB;
   const Real gm1 = a.ops.gamma - Real(1);
-  if (tid < N * N) s_dt[tid] = a.ops.Dt[tid];
   if (tid < EPB) {
     const int e = e0 + tid;
     const int ex = e % a.n0, ey = (e / a.n0) % a.n1, ez = e / (a.n0 * a.n1);
@@ -329,12 +353,21 @@ __global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) stage_kernel(StageArg
       s_nbr[tid][DIM > 2 ? 5 : 0] = ex + a.n0 * (ey + a.n1 * ezp);
     }
   }
-  __syncthreads();
 
-  // ---- loads: own state and metrics (needed first), then traces and RK
-  // registers, all issued before any is consumed.  Indices of lanes without
-  // work are clamped to element 0 so that every address stays in bounds.
-  Real uo[NPT][NV], mo[NPT][NM];
+  // the lane's line: direction (wave-uniform), element and line index
+  const int ldir = tid / LANES_DIR;
+  const int lrem = tid - ldir * LANES_DIR;
+  const int lel = lrem / L;
+  const int lline = lrem - lel * L;
+  const bool lactive = lel < EPB && e0 + lel < a.E;
+  const int stride = ldir == 0 ? 1 : (ldir == 1 ? N : N * N);
+  const int lbase = (lline % stride) + (lline / stride) * stride * N;
+
+  // ---- every global load the block needs before its stores is issued here:
+  // own state and 1/J per node, the line's contravariant vectors, the face
+  // traces and normals.  Indices of lanes without work are clamped to
+  // element 0 so that every address stays in bounds.
+  Real uo[NPT][NV], rinvj[NPT];
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
@@ -343,12 +376,18 @@ __global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) stage_kernel(StageArg
     const size_t o = ok ? (size_t)(e0 + el) * (NV * NN) + i : 0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) uo[r][v] = a.uin[o + (size_t)v * NN];
-    if (MESH == MESH_CURVED) {
-      const size_t om = ok ? (size_t)(e0 + el) * (NM * NN) + i : 0;
-#pragma unroll
-      for (int c = 0; c < NM; ++c) mo[r][c] = a.metric[om + (size_t)c * NN];
-    }
+    rinvj[r] = MESH == MESH_CURVED ? a.metric[(ok ? (size_t)(e0 + el) * (NM * NN) + i : 0) + (size_t)(NM - 1) * NN]
+                                   : Real(1);
   }
+  Real nrm[N][3];
+  if (MESH == MESH_CURVED) {
+    const Real* me = a.metric + (size_t)(lactive ? e0 + lel : 0) * (NM * NN);
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) nrm[k][m] = m < DIM ? me[(ldir * DIM + m) * NN + lbase + k * stride] : Real(0);
+  }
+  __syncthreads();  // s_nbr
   Real tL[FPT][NV], tR[FPT][NV], tn[FPT][3];
 #pragma unroll
   for (int r = 0; r < FPT; ++r) {
@@ -376,23 +415,8 @@ __global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) stage_kernel(StageArg
       tn[r][2] = dir == 2 ? Real(1) : Real(0);
     }
   }
-  Real ru0[NPT][NV], racc[NPT][NV];
-  const bool need_u0 = a.mode == MODE_RK_MID;
-  const bool need_acc = a.mode == MODE_RK_MID || a.mode == MODE_RK_LAST;
-#pragma unroll
-  for (int r = 0; r < NPT; ++r) {
-    const int q = tid + r * THREADS;
-    const int el = q / NN, i = q - el * NN;
-    const bool ok = q < EPB * NN && e0 + el < a.E;
-    const size_t o = ok ? (size_t)(e0 + el) * (NV * NN) + i : 0;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      ru0[r][v] = need_u0 ? a.u0[o + (size_t)v * NN] : Real(0);
-      racc[r][v] = need_acc ? a.acc[o + (size_t)v * NN] : Real(0);
-    }
-  }
 
-  // ---- prologue: primitive variables (and logs) once per node
+  // ---- prologue: primitive variables and logs once per node into LDS
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
@@ -416,93 +440,9 @@ __global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) stage_kernel(StageArg
       s_prim[el][(NP > DIM + 2) ? DIM + 2 : 0][i] = dev_log(rho);
       s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][i] = dev_log(p);
     }
-    if (MESH == MESH_CURVED) {
-#pragma unroll
-      for (int c = 0; c < NJ; ++c) s_ja[el][c][i] = mo[r][c];
-    }
-  }
-  __syncthreads();
-
-  Real acc[NPT][NV];
-#pragma unroll
-  for (int r = 0; r < NPT; ++r)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) acc[r][v] = Real(0);
-
-  // ---- volume: per direction, pair fluxes then line sums
-#pragma unroll
-  for (int dir = 0; dir < DIM; ++dir) {
-    const int stride = dir == 0 ? 1 : (dir == 1 ? N : N * N);
-    for (int t = tid; t < EPB * TDIR; t += THREADS) {
-      const int el = t / TDIR;
-      const int r = t - el * TDIR;
-      const int line = r / NPAIR;
-      const int pr = r - line * NPAIR;
-      if (e0 + el >= a.E) continue;
-      int i, k;
-      pair_nodes<N>(pr, i, k);
-      const int base = (line % stride) + (line / stride) * stride * N;
-      const int qi = base + i * stride, qk = base + k * stride;
-      Prim<Real> Pi, Pk;
-      Pi.rho = s_prim[el][0][qi];
-      Pk.rho = s_prim[el][0][qk];
-      Pi.v0 = s_prim[el][1][qi];
-      Pk.v0 = s_prim[el][1][qk];
-      Pi.v1 = DIM > 1 ? s_prim[el][DIM > 1 ? 2 : 0][qi] : Real(0);
-      Pk.v1 = DIM > 1 ? s_prim[el][DIM > 1 ? 2 : 0][qk] : Real(0);
-      Pi.v2 = DIM > 2 ? s_prim[el][DIM > 2 ? 3 : 0][qi] : Real(0);
-      Pk.v2 = DIM > 2 ? s_prim[el][DIM > 2 ? 3 : 0][qk] : Real(0);
-      Pi.p = s_prim[el][DIM + 1][qi];
-      Pk.p = s_prim[el][DIM + 1][qk];
-      if (NP > DIM + 2) {
-        Pi.lr = s_prim[el][(NP > DIM + 2) ? DIM + 2 : 0][qi];
-        Pk.lr = s_prim[el][(NP > DIM + 2) ? DIM + 2 : 0][qk];
-        Pi.lp = s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][qi];
-        Pk.lp = s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][qk];
-      } else {
-        Pi.lr = Pk.lr = Pi.lp = Pk.lp = Real(0);
-      }
-      Real F[NV];
-      if (MESH == MESH_CURVED) {
-        const int c0 = dir * DIM;
-        const Real nx = Real(0.5) * (s_ja[el][(c0) % NJ][qi] + s_ja[el][(c0) % NJ][qk]);
-        const Real ny = DIM > 1 ? Real(0.5) * (s_ja[el][(c0 + 1) % NJ][qi] + s_ja[el][(c0 + 1) % NJ][qk]) : Real(0);
-        const Real nz = DIM > 2 ? Real(0.5) * (s_ja[el][(c0 + 2) % NJ][qi] + s_ja[el][(c0 + 2) % NJ][qk]) : Real(0);
-        volume_flux<VF, DIM>(Pi, Pk, nx, ny, nz, a.ops.inv_gm1, F);
-      } else {
-        volume_flux<VF, DIM>(Pi, Pk, dir == 0 ? Real(1) : Real(0), dir == 1 ? Real(1) : Real(0),
-                             dir == 2 ? Real(1) : Real(0), a.ops.inv_gm1, F);
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) s_flux[el][v][r] = F[v];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-      const int q = tid + r * THREADS;
-      if (q >= EPB * NN) continue;
-      const int el = q / NN, i = q - el * NN;
-      const int pos = node_digit<N>(i, dir);
-      const int line = (i % stride) + (i / (stride * N)) * stride;
-      Real sum[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sum[v] = Real(0);
-#pragma unroll
-      for (int b = 0; b < N; ++b) {
-        if (b == pos) continue;
-        const int pr = line * NPAIR + (b > pos ? pair_index<N>(pos, b) : pair_index<N>(b, pos));
-        const Real d = s_dt[pos * N + b];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sum[v] += d * s_flux[el][v][pr];
-      }
-      const Real sc = MESH == MESH_AFFINE ? a.ops.scale[dir] : Real(1);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) acc[r][v] += MESH == MESH_AFFINE ? sc * sum[v] : sum[v];
-    }
-    __syncthreads();
   }
 
-  // ---- surface fluxes of the element's faces into the (now free) flux slots
+  // ---- surface fluxes of the element's faces
 #pragma unroll
   for (int r = 0; r < FPT; ++r) {
     const int t = tid + r * THREADS;
@@ -511,9 +451,50 @@ __global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) stage_kernel(StageArg
     Real F[NV];
     surface_flux<DIM>(a.surf, tL[r], tR[r], tn[r][0], tn[r][1], tn[r][2], a.ops.gamma, a.ops.inv_gm1, F);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) s_flux[el][v][rr] = F[v];
+    for (int v = 0; v < NV; ++v) s_face[el][v][rr] = F[v];
   }
   __syncthreads();
+
+  // ---- volume term: each lane sweeps the pairs of its line
+  Real A[N][NV];
+  {
+    const Real(*sp)[NN] = s_prim[lactive ? lel : 0];
+    if (ldir == 0) line_fluxes<0, DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, A);
+    else if (DIM > 1 && ldir == 1) line_fluxes<(DIM > 1 ? 1 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, A);
+    else if (DIM > 2) line_fluxes<(DIM > 2 ? 2 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, A);
+  }
+  // RK registers of the owned nodes, in flight while the line sums are merged
+  Real ru0[NPT][NV], racc[NPT][NV];
+  const bool need_u0 = a.mode == MODE_RK_MID;
+  const bool need_acc = a.mode == MODE_RK_MID || a.mode == MODE_RK_LAST;
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int q = tid + r * THREADS;
+    const int el = q / NN, i = q - el * NN;
+    const bool ok = q < EPB * NN && e0 + el < a.E;
+    const size_t o = ok ? (size_t)(e0 + el) * (NV * NN) + i : 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      ru0[r][v] = need_u0 ? a.u0[o + (size_t)v * NN] : Real(0);
+      racc[r][v] = need_acc ? a.acc[o + (size_t)v * NN] : Real(0);
+    }
+  }
+  // fixed summation order over directions: dir 0 writes, then dir 1, dir 2 add
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    if (ldir == d && lactive) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const int q = lbase + k * stride;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          if (d == 0) s_acc[lel][v][q] = A[k][v];
+          else s_acc[lel][v][q] += A[k][v];
+        }
+      }
+    }
+    __syncthreads();
+  }
 
   // ---- epilogue: lifting, -1/J, stage update
   const double dt = (a.mode == MODE_RHS) ? 0.0 : (a.dt ? *a.dt : a.dt_fixed);
@@ -528,7 +509,7 @@ __global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) stage_kernel(StageArg
     const int iz = DIM > 2 ? i / (N * N) : 0;
     Real S[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) S[v] = acc[r][v];
+    for (int v = 0; v < NV; ++v) S[v] = s_acc[el][v][i];
 #pragma unroll
     for (int dir = 0; dir < DIM; ++dir) {
       const int id = dir == 0 ? ix : (dir == 1 ? iy : iz);
@@ -538,15 +519,15 @@ __global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) stage_kernel(StageArg
       if (id == N - 1) {
         const Real w = sc * a.ops.inv_wp;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) S[v] += w * s_flux[el][v][(2 * dir + 1) * NF + f];
+        for (int v = 0; v < NV; ++v) S[v] += w * s_face[el][v][(2 * dir + 1) * NF + f];
       }
       if (id == 0) {
         const Real w = sc * a.ops.inv_w0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) S[v] -= w * s_flux[el][v][(2 * dir) * NF + f];
+        for (int v = 0; v < NV; ++v) S[v] -= w * s_face[el][v][(2 * dir) * NF + f];
       }
     }
-    const Real mul = MESH == MESH_CURVED ? -mo[r][NM - 1] : Real(-1);
+    const Real mul = -rinvj[r];
     const size_t base = (size_t)ee * (NV * NN) + i;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
