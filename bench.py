@@ -50,6 +50,54 @@ def algorithmic_stage_bytes(dim: int, N: int, curved: bool, real_bytes: int = 8)
     return (state + metric + traces + normals) * real_bytes
 
 
+def time_steps(g, steps, warmup, cfl, torch):
+    """ms per CFL-mode RK4 step of problem g (state already set)."""
+    for _ in range(warmup):
+        g.step(dt=0.0, nsteps=1, cfl=cfl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.step(dt=0.0, nsteps=1, cfl=cfl)
+    torch.cuda.synchronize()
+    g.sync()
+    return 1e3 * (time.perf_counter() - t0) / steps
+
+
+def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
+    """Same workload in FP32 bulk precision and with the Shima volume flux."""
+    import numpy as np
+    import torch
+    out = {}
+    steps = max(10, args.steps // 2)
+    # FP32 bulk (state, metrics, fluxes in FP32; FP64 reductions) against FP64
+    res = {}
+    for prec in ("fp64", "fp32"):
+        g = esdg.Problem(dim, p, (n, n, n), warp=0.1, volume_flux=args.flux, surface_flux="llf", precision=prec)
+        g.set_state(u0_dev)
+        dt = 0.5 * g.max_dt(args.cfl)
+        g.step(dt=dt, nsteps=10)
+        res[prec] = g.get_state()
+        g.set_state(u0_dev)
+        ms = time_steps(g, steps, 3, args.cfl, torch)
+        res[prec + "_ms"] = ms
+        g.close()
+    err = max(np.abs(res["fp32"][:, v] - res["fp64"][:, v]).max() / np.abs(res["fp64"][:, v]).max()
+              for v in range(dim + 2))
+    out["fp32_bulk"] = {
+        "pid_ns": round(res["fp32_ms"] * 1e6 / (4 * nodes), 6),
+        "ms_per_step": round(res["fp32_ms"], 6),
+        "speedup_vs_fp64": round(res["fp64_ms"] / res["fp32_ms"], 3),
+        "state_max_rel_err_vs_fp64_after_10_steps": float("%.3e" % err),
+    }
+    # Shima (KEP, no log means) volume flux, FP64
+    g = esdg.Problem(dim, p, (n, n, n), warp=0.1, volume_flux="shima", surface_flux="llf")
+    g.set_state(u0_dev)
+    ms = time_steps(g, steps, 3, args.cfl, torch)
+    g.close()
+    out["shima_fp64"] = {"pid_ns": round(ms * 1e6 / (4 * nodes), 6), "ms_per_step": round(ms, 6)}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +112,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=10,
                     help="steps with per-kernel hipEvent timing (after the timed region)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP32-bulk and Shima variants of the workload")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (HBM "
                          "counter calibration under a profiler)")
@@ -165,6 +215,9 @@ def main(argv=None):
         },
         "cpu_baseline": None,
     }
+
+    if not args.no_variants:
+        line["variants"] = variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n)
 
     if args.calibrate_copy_mib > 0:
         nb = args.calibrate_copy_mib * (1 << 20)

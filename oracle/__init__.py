@@ -73,6 +73,8 @@ def _load():
         lib.orc_mesh_operators.argtypes = [C.c_void_p, dp, dp, dp]
         lib.orc_rhs.argtypes = [C.c_void_p, dp, dp]
         lib.orc_rhs_scale.argtypes = [C.c_void_p, dp, dp]
+        lib.orc_rhs_elements.argtypes = [C.c_void_p, dp, dp, C.POINTER(C.c_int64), C.c_int64]
+        lib.orc_rhs_scale_elements.argtypes = [C.c_void_p, dp, dp, C.POINTER(C.c_int64), C.c_int64]
         lib.orc_totals.argtypes = [C.c_void_p, dp, dp]
         lib.orc_entropy_rate.argtypes = [C.c_void_p, dp, dp]
         lib.orc_entropy_rate.restype = C.c_double
@@ -241,6 +243,17 @@ class Mesh:
         sc = np.empty_like(u)
         self._lib.orc_rhs_scale(self._h, _ptr(u), _ptr(sc))
         return sc
+
+    def rhs_elements(self, u, elems):
+        """(RHS, rounding scale) of the listed elements only: arrays [len(elems), var, node]."""
+        u = self._state(u)
+        el = np.ascontiguousarray(np.asarray(elems, dtype=np.int64))
+        du = np.zeros_like(u)
+        sc = np.zeros_like(u)
+        ep = el.ctypes.data_as(C.POINTER(C.c_int64))
+        self._lib.orc_rhs_elements(self._h, _ptr(u), _ptr(du), ep, len(el))
+        self._lib.orc_rhs_scale_elements(self._h, _ptr(u), _ptr(sc), ep, len(el))
+        return du[el], sc[el]
 
     def totals(self, u) -> np.ndarray:
         u = self._state(u)

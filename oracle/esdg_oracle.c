@@ -453,7 +453,10 @@ orc_mesh *orc_mesh_new(const orc_desc *desc, const double *coords) {
     memcpy(m->x, coords, sizeof(double) * m->ne * desc->dim * m->nn);
   else
     default_coords(m);
+#pragma omp parallel
+  {
   double *X = (double *)malloc(sizeof(double) * 3 * m->nn);
+#pragma omp for schedule(static)
   for (int64_t e = 0; e < m->ne; ++e) {
     /* Coordinates relative to the element's first node: the metric terms
      * only involve derivatives of the coordinates and, in the curl form,
@@ -469,6 +472,7 @@ orc_mesh *orc_mesh_new(const orc_desc *desc, const double *coords) {
     element_metrics(m, X, m->Ja + e * 9 * m->nn, m->J + e * m->nn);
   }
   free(X);
+  }
   return m;
 }
 
@@ -507,61 +511,71 @@ static void ja_row(const orc_mesh *m, int64_t e, int n, int i, double *a) {
 
 /* RHS_i = -(1/J_i) [ sum_n sum_k 2 D_{i_n k} f_vol(u_i, u_k, (Ja^n_i + Ja^n_k)/2)
  *                    + sum_n (boundary terms of M^-1 R^T B (f* - N f)) ]         */
-void orc_rhs(const orc_mesh *m, const double *u, double *du) {
+/* RHS of one element (all its nodes) */
+static void rhs_element(const orc_mesh *m, const double *u, double *du, int64_t e) {
   const int dim = m->d.dim, N = m->N, nn = m->nn, nv = m->nv, p = m->d.p;
   const double g = m->d.gamma;
-#pragma omp parallel for schedule(static)
-  for (int64_t e = 0; e < m->ne; ++e) {
-    for (int i = 0; i < nn; ++i) {
-      int idx[3];
-      node_index(N, dim, i, idx);
-      double ui[5], acc[5] = {0, 0, 0, 0, 0};
-      gather(m, u, e, i, ui);
-      for (int n = 0; n < dim; ++n) {
-        double ai[3];
-        ja_row(m, e, n, i, ai);
-        /* volume: flux differencing along the line through i in direction n */
-        for (int k = 0; k < N; ++k) {
-          int jdx[3];
-          memcpy(jdx, idx, sizeof(idx));
-          jdx[n] = k;
-          int j = node_of(N, dim, jdx);
-          double uj[5], aj[3], nrm[3], f[5];
-          gather(m, u, e, j, uj);
-          ja_row(m, e, n, j, aj);
-          for (int mm = 0; mm < 3; ++mm) nrm[mm] = 0.5 * (ai[mm] + aj[mm]);
-          orc_two_point(m->d.vol_flux, dim, g, ui, uj, nrm, f);
-          for (int v = 0; v < nv; ++v) acc[v] += 2.0 * m->D[idx[n] * N + k] * f[v];
-        }
-        /* surface: i on the + face (i_n = p) or - face (i_n = 0) */
-        for (int side = 0; side < 2; ++side) {
-          int at = side ? p : 0;
-          if (idx[n] != at) continue;
-          int64_t eo = neighbour(&m->d, e, n, side ? +1 : -1);
-          int odx[3];
-          memcpy(odx, idx, sizeof(idx));
-          odx[n] = side ? 0 : p;
-          int io = node_of(N, dim, odx);
-          double uo[5], ao[3], nf[3], fstar[5], fphys[5];
-          gather(m, u, eo, io, uo);
-          ja_row(m, eo, n, io, ao);
-          for (int mm = 0; mm < 3; ++mm) nf[mm] = 0.5 * (ai[mm] + ao[mm]);
-          orc_phys_flux(dim, g, ui, ai, fphys);
-          if (side) {
-            /* outward reference normal +1: f* = f(u_L = u_i, u_R = u_o, n_f) */
-            orc_two_point(m->d.surf_flux, dim, g, ui, uo, nf, fstar);
-            for (int v = 0; v < nv; ++v) acc[v] += (fstar[v] - fphys[v]) / m->w[p];
-          } else {
-            /* outward reference normal -1: f* = f(u_L = u_o, u_R = u_i, n_f) */
-            orc_two_point(m->d.surf_flux, dim, g, uo, ui, nf, fstar);
-            for (int v = 0; v < nv; ++v) acc[v] += (-fstar[v] + fphys[v]) / m->w[0];
-          }
+  for (int i = 0; i < nn; ++i) {
+    int idx[3];
+    node_index(N, dim, i, idx);
+    double ui[5], acc[5] = {0, 0, 0, 0, 0};
+    gather(m, u, e, i, ui);
+    for (int n = 0; n < dim; ++n) {
+      double ai[3];
+      ja_row(m, e, n, i, ai);
+      /* volume: flux differencing along the line through i in direction n */
+      for (int k = 0; k < N; ++k) {
+        int jdx[3];
+        memcpy(jdx, idx, sizeof(idx));
+        jdx[n] = k;
+        int j = node_of(N, dim, jdx);
+        double uj[5], aj[3], nrm[3], f[5];
+        gather(m, u, e, j, uj);
+        ja_row(m, e, n, j, aj);
+        for (int mm = 0; mm < 3; ++mm) nrm[mm] = 0.5 * (ai[mm] + aj[mm]);
+        orc_two_point(m->d.vol_flux, dim, g, ui, uj, nrm, f);
+        for (int v = 0; v < nv; ++v) acc[v] += 2.0 * m->D[idx[n] * N + k] * f[v];
+      }
+      /* surface: i on the + face (i_n = p) or - face (i_n = 0) */
+      for (int side = 0; side < 2; ++side) {
+        int at = side ? p : 0;
+        if (idx[n] != at) continue;
+        int64_t eo = neighbour(&m->d, e, n, side ? +1 : -1);
+        int odx[3];
+        memcpy(odx, idx, sizeof(idx));
+        odx[n] = side ? 0 : p;
+        int io = node_of(N, dim, odx);
+        double uo[5], ao[3], nf[3], fstar[5], fphys[5];
+        gather(m, u, eo, io, uo);
+        ja_row(m, eo, n, io, ao);
+        for (int mm = 0; mm < 3; ++mm) nf[mm] = 0.5 * (ai[mm] + ao[mm]);
+        orc_phys_flux(dim, g, ui, ai, fphys);
+        if (side) {
+          /* outward reference normal +1: f* = f(u_L = u_i, u_R = u_o, n_f) */
+          orc_two_point(m->d.surf_flux, dim, g, ui, uo, nf, fstar);
+          for (int v = 0; v < nv; ++v) acc[v] += (fstar[v] - fphys[v]) / m->w[p];
+        } else {
+          /* outward reference normal -1: f* = f(u_L = u_o, u_R = u_i, n_f) */
+          orc_two_point(m->d.surf_flux, dim, g, uo, ui, nf, fstar);
+          for (int v = 0; v < nv; ++v) acc[v] += (-fstar[v] + fphys[v]) / m->w[0];
         }
       }
-      double Ji = m->J[e * nn + i];
-      for (int v = 0; v < nv; ++v) du[(e * nv + v) * nn + i] = -acc[v] / Ji;
     }
+    double Ji = m->J[e * nn + i];
+    for (int v = 0; v < nv; ++v) du[(e * nv + v) * nn + i] = -acc[v] / Ji;
   }
+}
+
+void orc_rhs(const orc_mesh *m, const double *u, double *du) {
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < m->ne; ++e) rhs_element(m, u, du, e);
+}
+
+/* RHS of the listed elements only (du has the full layout; other elements
+ * are left untouched) -- for sampled checks of large meshes */
+void orc_rhs_elements(const orc_mesh *m, const double *u, double *du, const int64_t *elems, int64_t count) {
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t q = 0; q < count; ++q) rhs_element(m, u, du, elems[q]);
 }
 
 /* Rounding scale of RHS_i: the same sums as orc_rhs with every term replaced
@@ -569,53 +583,60 @@ void orc_rhs(const orc_mesh *m, const double *u, double *du) {
  * sum_n (|f*| + |f^n(u_i)|)/w_end ].  A floating-point evaluation of RHS_i in
  * any order has an error of at most a few eps * sc_i; it is the natural
  * denominator of a relative parity bound where RHS_i itself cancels. */
-void orc_rhs_scale(const orc_mesh *m, const double *u, double *sc) {
+static void scale_element(const orc_mesh *m, const double *u, double *sc, int64_t e) {
   const int dim = m->d.dim, N = m->N, nn = m->nn, nv = m->nv, p = m->d.p;
   const double g = m->d.gamma;
-#pragma omp parallel for schedule(static)
-  for (int64_t e = 0; e < m->ne; ++e) {
-    for (int i = 0; i < nn; ++i) {
-      int idx[3];
-      node_index(N, dim, i, idx);
-      double ui[5], acc[5] = {0, 0, 0, 0, 0};
-      gather(m, u, e, i, ui);
-      for (int n = 0; n < dim; ++n) {
-        double ai[3];
-        ja_row(m, e, n, i, ai);
-        for (int k = 0; k < N; ++k) {
-          int jdx[3];
-          memcpy(jdx, idx, sizeof(idx));
-          jdx[n] = k;
-          int j = node_of(N, dim, jdx);
-          double uj[5], aj[3], nrm[3], f[5];
-          gather(m, u, e, j, uj);
-          ja_row(m, e, n, j, aj);
-          for (int mm = 0; mm < 3; ++mm) nrm[mm] = 0.5 * (ai[mm] + aj[mm]);
-          orc_two_point(m->d.vol_flux, dim, g, ui, uj, nrm, f);
-          for (int v = 0; v < nv; ++v) acc[v] += fabs(2.0 * m->D[idx[n] * N + k] * f[v]);
-        }
-        for (int side = 0; side < 2; ++side) {
-          int at = side ? p : 0;
-          if (idx[n] != at) continue;
-          int64_t eo = neighbour(&m->d, e, n, side ? +1 : -1);
-          int odx[3];
-          memcpy(odx, idx, sizeof(idx));
-          odx[n] = side ? 0 : p;
-          int io = node_of(N, dim, odx);
-          double uo[5], ao[3], nf[3], fstar[5], fphys[5];
-          gather(m, u, eo, io, uo);
-          ja_row(m, eo, n, io, ao);
-          for (int mm = 0; mm < 3; ++mm) nf[mm] = 0.5 * (ai[mm] + ao[mm]);
-          orc_phys_flux(dim, g, ui, ai, fphys);
-          if (side) orc_two_point(m->d.surf_flux, dim, g, ui, uo, nf, fstar);
-          else orc_two_point(m->d.surf_flux, dim, g, uo, ui, nf, fstar);
-          for (int v = 0; v < nv; ++v) acc[v] += (fabs(fstar[v]) + fabs(fphys[v])) / m->w[at];
-        }
+  for (int i = 0; i < nn; ++i) {
+    int idx[3];
+    node_index(N, dim, i, idx);
+    double ui[5], acc[5] = {0, 0, 0, 0, 0};
+    gather(m, u, e, i, ui);
+    for (int n = 0; n < dim; ++n) {
+      double ai[3];
+      ja_row(m, e, n, i, ai);
+      for (int k = 0; k < N; ++k) {
+        int jdx[3];
+        memcpy(jdx, idx, sizeof(idx));
+        jdx[n] = k;
+        int j = node_of(N, dim, jdx);
+        double uj[5], aj[3], nrm[3], f[5];
+        gather(m, u, e, j, uj);
+        ja_row(m, e, n, j, aj);
+        for (int mm = 0; mm < 3; ++mm) nrm[mm] = 0.5 * (ai[mm] + aj[mm]);
+        orc_two_point(m->d.vol_flux, dim, g, ui, uj, nrm, f);
+        for (int v = 0; v < nv; ++v) acc[v] += fabs(2.0 * m->D[idx[n] * N + k] * f[v]);
       }
-      double Ji = m->J[e * nn + i];
-      for (int v = 0; v < nv; ++v) sc[(e * nv + v) * nn + i] = acc[v] / fabs(Ji);
+      for (int side = 0; side < 2; ++side) {
+        int at = side ? p : 0;
+        if (idx[n] != at) continue;
+        int64_t eo = neighbour(&m->d, e, n, side ? +1 : -1);
+        int odx[3];
+        memcpy(odx, idx, sizeof(idx));
+        odx[n] = side ? 0 : p;
+        int io = node_of(N, dim, odx);
+        double uo[5], ao[3], nf[3], fstar[5], fphys[5];
+        gather(m, u, eo, io, uo);
+        ja_row(m, eo, n, io, ao);
+        for (int mm = 0; mm < 3; ++mm) nf[mm] = 0.5 * (ai[mm] + ao[mm]);
+        orc_phys_flux(dim, g, ui, ai, fphys);
+        if (side) orc_two_point(m->d.surf_flux, dim, g, ui, uo, nf, fstar);
+        else orc_two_point(m->d.surf_flux, dim, g, uo, ui, nf, fstar);
+        for (int v = 0; v < nv; ++v) acc[v] += (fabs(fstar[v]) + fabs(fphys[v])) / m->w[at];
+      }
     }
+    double Ji = m->J[e * nn + i];
+    for (int v = 0; v < nv; ++v) sc[(e * nv + v) * nn + i] = acc[v] / fabs(Ji);
   }
+}
+
+void orc_rhs_scale(const orc_mesh *m, const double *u, double *sc) {
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < m->ne; ++e) scale_element(m, u, sc, e);
+}
+
+void orc_rhs_scale_elements(const orc_mesh *m, const double *u, double *sc, const int64_t *elems, int64_t count) {
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t q = 0; q < count; ++q) scale_element(m, u, sc, elems[q]);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -43,16 +43,23 @@ struct esdg_problem {
   void* Y = nullptr;       // RK stage state
   void* R = nullptr;       // RK accumulator
   void* DU = nullptr;      // right-hand side scratch
+  double* STAGE64 = nullptr;  // FP32 mode: FP64 staging of states crossing the ABI
   void* Y2 = nullptr;      // second RK stage state (stage inputs and outputs alternate)
   void* METRIC = nullptr;  // curved metrics
   void* NFACE = nullptr;   // curved face normals
   double* PARTIAL = nullptr;  // reduction partials (FP64)
-  double* SCAL = nullptr;     // FP64 scalars: [0] dt, [1] t, [2..] results
+  double* SCAL = nullptr;     // FP64 scalars: [1] t, [2..7] results
+  unsigned long long* LAM = nullptr;  // CFL slots: 2 x kLamSlots (bit patterns of doubles)
   int* FLAG = nullptr;        // non-physical flag
   int red_blocks = 1;
   int64_t red_per_block = 256;
 
   bool have_state = false;
+  // CFL: the largest wave-speed sum of the current state lives in one of two
+  // device slots (bit pattern of a double); valid until the state changes
+  // other than through esdg_step in CFL mode
+  bool lam_valid = false;
+  int lam_cur = 0;
   bool timing = false;
   std::vector<TimedLaunch> launches;
   std::string err;
@@ -116,9 +123,22 @@ esdg_status launch(esdg_problem* P, int kind, const void* fn, dim3 grid, dim3 bl
 
 // One fused stage launch: right-hand side of `uin` (surface and volume
 // terms) and, for the RK modes, the stage update into out / R.
+unsigned long long* lam_slot(esdg_problem* P, int k) { return P->LAM + k * kLamSlots; }
+
+// Time stepping of one stage launch: fixed dt, or CFL from a lam slot.
+struct StepCtl {
+  double dt_fixed = 0.0, cfl = 0.0;
+  const unsigned long long* lam_in = nullptr;
+  unsigned long long* lam_out = nullptr;
+  unsigned long long* lam_clear = nullptr;
+  int t_mode = 0;
+};
+
+// One fused stage launch: right-hand side of `uin` (surface and volume
+// terms) and, for the RK modes, the stage update into out / R.
 template <typename Real>
 esdg_status run_stage(esdg_problem* P, const void* uin, void* out, int mode, double coef_b, double coef_a,
-                      double dt_fixed = 0.0) {
+                      const StepCtl& ctl = StepCtl()) {
   StageArgs<Real> a{};
   a.uin = (const Real*)uin;
   a.metric = (const Real*)P->METRIC;
@@ -126,8 +146,13 @@ esdg_status run_stage(esdg_problem* P, const void* uin, void* out, int mode, dou
   a.out = (Real*)out;
   a.acc = (Real*)P->R;
   a.u0 = (const Real*)P->U;
-  a.dt = dt_fixed > 0.0 ? nullptr : P->SCAL;
-  a.dt_fixed = dt_fixed;
+  a.lam_in = ctl.lam_in;
+  a.dt_fixed = ctl.dt_fixed;
+  a.cfl = ctl.cfl;
+  a.lam_out = ctl.lam_out;
+  a.lam_clear = ctl.lam_clear;
+  a.t_acc = P->SCAL + 1;
+  a.t_mode = ctl.t_mode;
   a.flag = P->FLAG;
   a.E = (int)P->E;
   a.n0 = P->spec.n[0];
@@ -147,9 +172,10 @@ esdg_status run_stage(esdg_problem* P, const void* uin, void* out, int mode, dou
 }
 
 // FP64 reduction of op over the state (and DU for the entropy rate); the
-// result lands in SCAL[2..] (or SCAL[0] = dt for RED_MAXLAMBDA).
+// result lands in SCAL[2..] (dt for RED_MAXLAMBDA, whose lam_max also goes
+// to `slot` if given).
 template <typename Real>
-esdg_status run_reduce(esdg_problem* P, int op, double cfl, int advance_t) {
+esdg_status run_reduce(esdg_problem* P, int op, double cfl, unsigned long long* slot = nullptr) {
   RedArgs<Real> a{};
   a.u = (const Real*)P->U;
   a.du = (const Real*)P->DU;
@@ -169,18 +195,23 @@ esdg_status run_reduce(esdg_problem* P, int op, double cfl, int advance_t) {
              dim3(kRedThreads), args));
   int K = op == RED_TOTALS ? P->nv : 1;
   double* out = P->SCAL + 2;
-  double* scal = op == RED_MAXLAMBDA ? P->SCAL : nullptr;
   int blocks = P->red_blocks, N = P->N;
-  void* args2[] = {&P->PARTIAL, &blocks, &K, &out, &cfl, &N, &scal, &advance_t};
+  void* args2[] = {&P->PARTIAL, &blocks, &K, &out, &cfl, &N, &slot};
   return launch(P, ESDG_KERNEL_REDUCE, reduce_final_for(op), dim3(1), dim3(kRedThreads), args2);
 }
 
 // dispatch on internal precision
-#define BY_PREC(P, call_double)                \
-  ((P)->prec == PREC_FP64 ? call_double : fail((P), ESDG_EINVAL, "precision not built"))
+#define BY_PREC(P, fn, ...) ((P)->prec == PREC_FP32 ? fn<float>(__VA_ARGS__) : fn<double>(__VA_ARGS__))
 
 esdg_status rhs_into(esdg_problem* P, void* out) {
-  return BY_PREC(P, run_stage<double>(P, P->U, out, MODE_RHS, 0.0, 0.0));
+  return BY_PREC(P, run_stage, P, P->U, out, MODE_RHS, 0.0, 0.0);
+}
+
+// elementwise precision conversion of n values on the handle's stream
+esdg_status convert(esdg_problem* P, const void* src, void* dst, int to_fp64) {
+  int64_t n = (int64_t)state_count(P);
+  void* args[] = {(void*)&src, &dst, &n};
+  return launch(P, -1, convert_kernel_for(to_fp64), dim3((unsigned)((n + 255) / 256)), dim3(256), args);
 }
 
 esdg_status check_handle(esdg_problem* P, bool need_state) {
@@ -197,7 +228,7 @@ esdg_status read_scalars(esdg_problem* P, int first, int count, double* out) {
 }
 
 void free_buffers(esdg_problem* P) {
-  void* bufs[] = {P->U, P->Y, P->Y2, P->R, P->DU, P->METRIC, P->NFACE, P->PARTIAL, P->SCAL, P->FLAG};
+  void* bufs[] = {P->U, P->Y, P->Y2, P->R, P->DU, P->STAGE64, P->METRIC, P->NFACE, P->PARTIAL, P->SCAL, P->LAM, P->FLAG};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& t : P->launches) {
@@ -252,7 +283,6 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
     ne *= d->n[j];
   }
   if (ne > (int64_t)1 << 30) return fail(nullptr, ESDG_EINVAL, "at most 2^30 elements");
-  if (d->precision == ESDG_FP32) return fail(nullptr, ESDG_EINVAL, "FP32 precision is not built in this version");
 
   esdg_problem* P = new esdg_problem();
   P->spec.dim = d->dim;
@@ -310,6 +340,7 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
                 {&P->Y2, ns},
                 {(void**)&P->PARTIAL, sizeof(double) * 8 * (size_t)P->red_blocks},
                 {(void**)&P->SCAL, sizeof(double) * 16},
+                {(void**)&P->LAM, sizeof(unsigned long long) * 2 * kLamSlots},
                 {(void**)&P->FLAG, sizeof(int)}};
   for (auto& a : allocs) {
     if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
@@ -318,7 +349,29 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
       return fail(nullptr, ESDG_ENOMEM, "device allocation of %zu bytes failed", a.bytes);
     }
   }
-  if (P->mesh == MESH_CURVED) {
+  if (P->prec == PREC_FP32 && hipMalloc((void**)&P->STAGE64, state_count(P) * sizeof(double)) != hipSuccess) {
+    free_buffers(P);
+    delete P;
+    return fail(nullptr, ESDG_ENOMEM, "device allocation of the FP64 staging buffer failed");
+  }
+  if (P->mesh == MESH_CURVED && P->prec == PREC_FP32) {
+    // FP32 bulk: the metric terms are rounded once, on the host
+    std::vector<float> mf(P->geo.metric.begin(), P->geo.metric.end());
+    std::vector<float> nf(P->geo.nface.begin(), P->geo.nface.end());
+    if (hipMalloc(&P->METRIC, mf.size() * 4) != hipSuccess || hipMalloc(&P->NFACE, nf.size() * 4) != hipSuccess) {
+      free_buffers(P);
+      delete P;
+      return fail(nullptr, ESDG_ENOMEM, "device allocation of metric terms failed");
+    }
+    if (hipMemcpy(P->METRIC, mf.data(), mf.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(P->NFACE, nf.data(), nf.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      free_buffers(P);
+      delete P;
+      return fail(nullptr, ESDG_EDEVICE, "upload of metric terms failed");
+    }
+    std::vector<double>().swap(P->geo.metric);
+    std::vector<double>().swap(P->geo.nface);
+  } else if (P->mesh == MESH_CURVED) {
     const size_t mb = P->geo.metric.size() * P->rsize, fb = P->geo.nface.size() * P->rsize;
     if (hipMalloc(&P->METRIC, mb) != hipSuccess || hipMalloc(&P->NFACE, fb) != hipSuccess) {
       free_buffers(P);
@@ -378,10 +431,20 @@ esdg_status esdg_set_state(esdg_problem* P, const double* u, int32_t where) {
   TRY(check_handle(P, false));
   if (!u) return fail(P, ESDG_EINVAL, "NULL state");
   const size_t bytes = state_count(P) * sizeof(double);
-  HIPCHECK(P, hipMemcpyAsync(P->U, u, bytes, where == ESDG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                             P->stream));
+  if (P->prec == PREC_FP32) {
+    const void* src = u;
+    if (where != ESDG_DEVICE) {
+      HIPCHECK(P, hipMemcpyAsync(P->STAGE64, u, bytes, hipMemcpyHostToDevice, P->stream));
+      src = P->STAGE64;
+    }
+    TRY(convert(P, src, P->U, 0));
+  } else {
+    HIPCHECK(P, hipMemcpyAsync(P->U, u, bytes, where == ESDG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                               P->stream));
+  }
   if (where != ESDG_DEVICE) HIPCHECK(P, hipStreamSynchronize(P->stream));
   P->have_state = true;
+  P->lam_valid = false;
   return ESDG_OK;
 }
 
@@ -389,8 +452,13 @@ esdg_status esdg_get_state(esdg_problem* P, double* u, int32_t where) {
   TRY(check_handle(P, true));
   if (!u) return fail(P, ESDG_EINVAL, "NULL output");
   const size_t bytes = state_count(P) * sizeof(double);
-  HIPCHECK(P, hipMemcpyAsync(u, P->U, bytes, where == ESDG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                             P->stream));
+  if (P->prec == PREC_FP32) {
+    TRY(convert(P, P->U, where == ESDG_DEVICE ? (void*)u : (void*)P->STAGE64, 1));
+    if (where != ESDG_DEVICE) HIPCHECK(P, hipMemcpyAsync(u, P->STAGE64, bytes, hipMemcpyDeviceToHost, P->stream));
+  } else {
+    HIPCHECK(P, hipMemcpyAsync(u, P->U, bytes, where == ESDG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                               P->stream));
+  }
   if (where != ESDG_DEVICE) HIPCHECK(P, hipStreamSynchronize(P->stream));
   return ESDG_OK;
 }
@@ -399,11 +467,16 @@ esdg_status esdg_rhs(esdg_problem* P, double* du, int32_t where) {
   TRY(check_handle(P, true));
   if (!du) return fail(P, ESDG_EINVAL, "NULL output");
   const bool direct = where == ESDG_DEVICE;
-  TRY(rhs_into(P, direct ? (void*)du : P->DU));
-  if (!direct) {
-    HIPCHECK(P, hipMemcpyAsync(du, P->DU, state_count(P) * sizeof(double), hipMemcpyDeviceToHost, P->stream));
-    HIPCHECK(P, hipStreamSynchronize(P->stream));
+  const size_t bytes = state_count(P) * sizeof(double);
+  if (P->prec == PREC_FP32) {
+    TRY(rhs_into(P, P->DU));
+    TRY(convert(P, P->DU, direct ? (void*)du : (void*)P->STAGE64, 1));
+    if (!direct) HIPCHECK(P, hipMemcpyAsync(du, P->STAGE64, bytes, hipMemcpyDeviceToHost, P->stream));
+  } else {
+    TRY(rhs_into(P, direct ? (void*)du : P->DU));
+    if (!direct) HIPCHECK(P, hipMemcpyAsync(du, P->DU, bytes, hipMemcpyDeviceToHost, P->stream));
   }
+  if (!direct) HIPCHECK(P, hipStreamSynchronize(P->stream));
   return ESDG_OK;
 }
 
@@ -413,16 +486,38 @@ esdg_status esdg_step(esdg_problem* P, double dt, int32_t nsteps, double cfl, do
   const bool use_cfl = !(dt > 0.0);
   if (use_cfl && !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "dt <= 0 needs cfl > 0");
   if (nsteps == 0) return ESDG_OK;
-  const double h = use_cfl ? 0.0 : dt;  // fixed step by value, CFL step from SCAL[0]
-  // classical RK4 in low-storage form: U (state), R (accumulator) and the
-  // stage state, alternating between Y and Y2
-  for (int s = 0; s < nsteps; ++s) {
-    if (use_cfl) TRY(BY_PREC(P, run_reduce<double>(P, RED_MAXLAMBDA, cfl, s == 0 ? 2 : 1)));
-    // stage inputs are read across element faces, so inputs and outputs alternate
-    TRY(BY_PREC(P, run_stage<double>(P, P->U, P->Y, MODE_RK_FIRST, 1.0 / 6.0, 0.5, h)));
-    TRY(BY_PREC(P, run_stage<double>(P, P->Y, P->Y2, MODE_RK_MID, 1.0 / 3.0, 0.5, h)));
-    TRY(BY_PREC(P, run_stage<double>(P, P->Y2, P->Y, MODE_RK_MID, 1.0 / 3.0, 1.0, h)));
-    TRY(BY_PREC(P, run_stage<double>(P, P->Y, P->U, MODE_RK_LAST, 1.0 / 6.0, 0.0, h)));
+  if (!use_cfl) {
+    StepCtl ctl;
+    ctl.dt_fixed = dt;
+    for (int s = 0; s < nsteps; ++s) {
+      // stage inputs are read across element faces, so inputs and outputs alternate
+      TRY(BY_PREC(P, run_stage, P, P->U, P->Y, MODE_RK_FIRST, 1.0 / 6.0, 0.5, ctl));
+      TRY(BY_PREC(P, run_stage, P, P->Y, P->Y2, MODE_RK_MID, 1.0 / 3.0, 0.5, ctl));
+      TRY(BY_PREC(P, run_stage, P, P->Y2, P->Y, MODE_RK_MID, 1.0 / 3.0, 1.0, ctl));
+      TRY(BY_PREC(P, run_stage, P, P->Y, P->U, MODE_RK_LAST, 1.0 / 6.0, 0.0, ctl));
+    }
+    P->lam_valid = false;
+  } else {
+    // the CFL wave-speed sum of the start state comes from the previous CFL
+    // step's last stage; otherwise from one reduction
+    if (!P->lam_valid) TRY(BY_PREC(P, run_reduce, P, RED_MAXLAMBDA, cfl, lam_slot(P, P->lam_cur)));
+    for (int s = 0; s < nsteps; ++s) {
+      const int cur = P->lam_cur, nxt = 1 - cur;
+      StepCtl ctl;
+      ctl.cfl = cfl;
+      ctl.lam_in = lam_slot(P, cur);
+      StepCtl first = ctl;
+      first.lam_clear = lam_slot(P, nxt);
+      first.t_mode = s == 0 ? 2 : 1;
+      StepCtl last = ctl;
+      last.lam_out = lam_slot(P, nxt);
+      TRY(BY_PREC(P, run_stage, P, P->U, P->Y, MODE_RK_FIRST, 1.0 / 6.0, 0.5, first));
+      TRY(BY_PREC(P, run_stage, P, P->Y, P->Y2, MODE_RK_MID, 1.0 / 3.0, 0.5, ctl));
+      TRY(BY_PREC(P, run_stage, P, P->Y2, P->Y, MODE_RK_MID, 1.0 / 3.0, 1.0, ctl));
+      TRY(BY_PREC(P, run_stage, P, P->Y, P->U, MODE_RK_LAST, 1.0 / 6.0, 0.0, last));
+      P->lam_cur = nxt;
+    }
+    P->lam_valid = true;
   }
   if (t_inout) {
     if (use_cfl) {
@@ -440,21 +535,21 @@ esdg_status esdg_entropy_rate(esdg_problem* P, double* dSdt) {
   TRY(check_handle(P, true));
   if (!dSdt) return fail(P, ESDG_EINVAL, "NULL output");
   TRY(rhs_into(P, P->DU));
-  TRY(BY_PREC(P, run_reduce<double>(P, RED_ENTROPY, 0.0, 0)));
+  TRY(BY_PREC(P, run_reduce, P, RED_ENTROPY, 0.0));
   return read_scalars(P, 2, 1, dSdt);
 }
 
 esdg_status esdg_totals(esdg_problem* P, double* totals) {
   TRY(check_handle(P, true));
   if (!totals) return fail(P, ESDG_EINVAL, "NULL output");
-  TRY(BY_PREC(P, run_reduce<double>(P, RED_TOTALS, 0.0, 0)));
+  TRY(BY_PREC(P, run_reduce, P, RED_TOTALS, 0.0));
   return read_scalars(P, 2, P->nv, totals);
 }
 
 esdg_status esdg_max_dt(esdg_problem* P, double cfl, double* dt) {
   TRY(check_handle(P, true));
   if (!dt || !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "need cfl > 0 and an output pointer");
-  TRY(BY_PREC(P, run_reduce<double>(P, RED_MAXLAMBDA, cfl, 0)));
+  TRY(BY_PREC(P, run_reduce, P, RED_MAXLAMBDA, cfl));
   return read_scalars(P, 2, 1, dt);
 }
 

@@ -13,6 +13,8 @@ struct VolKernel {
 
 VolKernel stage_kernel_2d(int prec, int N, int vf, int mesh);
 VolKernel stage_kernel_3d(int prec, int N, int vf, int mesh);
+VolKernel stage_kernel_2d_f32(int N, int vf, int mesh);
+VolKernel stage_kernel_3d_f32(int N, int vf, int mesh);
 const void* reduce_partial_for(int prec, int dim, int mesh, int op);
 const void* reduce_final_for(int op);
 const void* convert_kernel_for(int to_fp64);  // elementwise precision casts

@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) to_fp32_kernel(const double* src, float* 
 }  // namespace
 
 const void* reduce_partial_for(int prec, int dim, int mesh, int op) {
-  if (prec != PREC_FP64) return nullptr;
+  if (prec == PREC_FP32) return dim == 2 ? reduce_pick<2, float>(mesh, op) : reduce_pick<3, float>(mesh, op);
   return dim == 2 ? reduce_pick<2, double>(mesh, op) : reduce_pick<3, double>(mesh, op);
 }
 

@@ -36,6 +36,7 @@ enum StageMode { MODE_RHS = 0, MODE_RK_FIRST = 1, MODE_RK_MID = 2, MODE_RK_LAST 
 enum RedOp { RED_TOTALS = 0, RED_ENTROPY = 1, RED_MAXLAMBDA = 2 };
 
 constexpr int kDevMaxN = 8;
+constexpr int kLamSlots = 64;  // CFL maxima are spread over this many slots (atomic contention)
 
 template <typename Real>
 struct StageOps {
@@ -53,8 +54,16 @@ struct StageArgs {
   Real* out;           // MODE_RHS: du; RK: stage output y (FIRST, MID) or state (LAST)
   Real* acc;           // RK accumulator
   const Real* u0;      // RK state at the start of the step (MID)
-  const double* dt;    // device scalar time step (CFL mode) or NULL
-  double dt_fixed;     // time step when dt is NULL
+  // time step: fixed (lam_in == NULL) or CFL, dt = cfl 2 / (N lam) with lam the
+  // largest sum over directions of wave speeds of the step's start state,
+  // kept as the bit pattern of a non-negative double in a device slot
+  // (kLamSlots slots: the maximum over the slots counts)
+  const unsigned long long* lam_in;
+  double dt_fixed, cfl;
+  unsigned long long* lam_out;    // LAST stage: max over the new state (atomic max per wave), or NULL
+  unsigned long long* lam_clear;  // FIRST stage: slots to reset for this step's LAST stage, or NULL
+  double* t_acc;                  // FIRST stage: elapsed time (t_mode 1: += dt, 2: = dt)
+  int t_mode;
   int* flag;           // non-physical state flag
   int E;               // elements
   int n0, n1, n2;      // elements per direction
@@ -78,7 +87,7 @@ template <> struct LogMeanEps<double> { static constexpr double value = 1.0e-4; 
 template <> struct LogMeanEps<float> { static constexpr float value = 2.0e-2f; };
 
 __device__ __forceinline__ double dev_log(double x) { return log(x); }
-__device__ __forceinline__ float dev_log(float x) { return __logf(x); }
+__device__ __forceinline__ float dev_log(float x) { return logf(x); }
 
 // Reciprocal: hardware estimate refined by Newton's iteration r <- r(2 - q r)
 // written as two fused multiply-adds (two steps in FP64, one in FP32).
@@ -497,7 +506,24 @@ stage_kernel(StageArgs<Real> a) {
   }
 
   // ---- epilogue: lifting, -1/J, stage update
-  const double dt = (a.mode == MODE_RHS) ? 0.0 : (a.dt ? *a.dt : a.dt_fixed);
+  double dt = a.dt_fixed;
+  if (a.mode == MODE_RHS) dt = 0.0;
+  if (a.mode != MODE_RHS && a.lam_in) {
+    // every wave folds the slots: lane l reads slot l, then a max over the wave
+    double lam = __longlong_as_double((long long)a.lam_in[tid & (kLamSlots - 1)]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(lam, off, 64);
+      if (!(o <= lam)) lam = o;
+    }
+    dt = a.cfl * 2.0 / ((double)N * lam);
+  }
+  if (blockIdx.x == 0 && a.mode == MODE_RK_FIRST) {
+    if (a.lam_clear && tid < kLamSlots) a.lam_clear[tid] = 0ull;
+    if (tid == 0 && a.t_mode == 1) *a.t_acc += dt;
+    if (tid == 0 && a.t_mode == 2) *a.t_acc = dt;
+  }
+  double lam_max = 0.0;  // CFL wave-speed sum of the new state (LAST stage)
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
@@ -529,6 +555,7 @@ stage_kernel(StageArgs<Real> a) {
     }
     const Real mul = -rinvj[r];
     const size_t base = (size_t)ee * (NV * NN) + i;
+    Real unew[NV] = {};
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const Real k = mul * S[v];
@@ -542,9 +569,48 @@ stage_kernel(StageArgs<Real> a) {
         a.acc[o] = racc[r][v] + a.coef_b * (Real)dt * k;
         a.out[o] = ru0[r][v] + a.coef_a * (Real)dt * k;
       } else {
-        a.out[o] = racc[r][v] + a.coef_b * (Real)dt * k;
+        unew[v] = racc[r][v] + a.coef_b * (Real)dt * k;
+        a.out[o] = unew[v];
       }
     }
+    if (a.lam_out) {
+      // sum_n (|v.Ja^n| + c |Ja^n|) / J of the new state at this node
+      const Real rho = unew[0], ir = dev_rcp(rho);
+      const Real w0 = unew[1] * ir;
+      const Real w1 = DIM > 1 ? unew[DIM > 1 ? 2 : 1] * ir : Real(0);
+      const Real w2 = DIM > 2 ? unew[DIM > 2 ? 3 : 1] * ir : Real(0);
+      const Real pr = gm1 * (unew[DIM + 1] - Real(0.5) * rho * (w0 * w0 + w1 * w1 + w2 * w2));
+      const Real c = sqrt(a.ops.gamma * pr * ir);
+      Real lam = Real(0);
+      if (MESH == MESH_CURVED) {
+        const Real* me = a.metric + (size_t)ee * (NM * NN) + i;
+#pragma unroll
+        for (int n = 0; n < DIM; ++n) {
+          const Real j0 = me[(n * DIM) * NN];
+          const Real j1 = DIM > 1 ? me[(n * DIM + (DIM > 1 ? 1 : 0)) * NN] : Real(0);
+          const Real j2 = DIM > 2 ? me[(n * DIM + (DIM > 2 ? 2 : 0)) * NN] : Real(0);
+          lam += fabs(w0 * j0 + w1 * j1 + w2 * j2) + c * sqrt(j0 * j0 + j1 * j1 + j2 * j2);
+        }
+        lam *= rinvj[r];
+      } else {
+        lam = (fabs(w0) + c) * a.ops.scale[0];
+        if (DIM > 1) lam += (fabs(w1) + c) * a.ops.scale[DIM > 1 ? 1 : 0];
+        if (DIM > 2) lam += (fabs(w2) + c) * a.ops.scale[DIM > 2 ? 2 : 0];
+      }
+      const double ld = (double)lam;
+      if (!(ld <= lam_max)) lam_max = ld;  // a NaN wins and poisons dt (flagged anyway)
+    }
+  }
+  if (a.lam_out) {
+    // max over the wave, then one atomic per wave: max is exact, so the
+    // result does not depend on the order of the atomics
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(lam_max, off, 64);
+      if (!(o <= lam_max)) lam_max = o;
+    }
+    if ((tid & 63) == 0)
+      atomicMax(a.lam_out + (blockIdx.x & (kLamSlots - 1)), (unsigned long long)__double_as_longlong(lam_max));
   }
 }
 
@@ -658,12 +724,13 @@ __global__ void __launch_bounds__(kRedThreads) reduce_partial_kernel(RedArgs<Rea
 }
 
 // Final pass: one block folds the partials in index order.  For
-// RED_MAXLAMBDA it also turns lam_max into dt = cfl*2/(N lam_max), stores it
-// in scal[0] and adds it to (advance_t == 1) or stores it in (== 2) scal[1].
+// RED_MAXLAMBDA it turns lam_max into dt = cfl*2/(N lam_max) (out[0]) and, if
+// lam_slot is given, stores lam_max in its first slot (bit pattern of the
+// double) and zero in the other kLamSlots - 1.
 template <int OP>
 __global__ void __launch_bounds__(kRedThreads) reduce_final_kernel(const double* partial, int blocks, int K,
                                                                      double* out, double cfl, int N,
-                                                                     double* scal, int advance_t) {
+                                                                     unsigned long long* lam_slot) {
   __shared__ double sh[kRedThreads];
   for (int k = 0; k < K; ++k) {
     double acc = 0.0;
@@ -689,19 +756,11 @@ __global__ void __launch_bounds__(kRedThreads) reduce_final_kernel(const double*
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      if (OP == RED_MAXLAMBDA) {
-        const double lam = sh[0];
-        const double dt = cfl * 2.0 / ((double)N * lam);
-        out[k] = dt;
-        if (scal) {
-          scal[0] = dt;
-          if (advance_t == 1) scal[1] += dt;  // accumulate the time
-          if (advance_t == 2) scal[1] = dt;   // first step of a call
-        }
-      } else {
-        out[k] = sh[0];
-      }
+      if (OP == RED_MAXLAMBDA) out[k] = cfl * 2.0 / ((double)N * sh[0]);
+      else out[k] = sh[0];
     }
+    if (OP == RED_MAXLAMBDA && lam_slot && threadIdx.x < kLamSlots)
+      lam_slot[threadIdx.x] = threadIdx.x == 0 ? (unsigned long long)__double_as_longlong(sh[0]) : 0ull;
     __syncthreads();
   }
 }

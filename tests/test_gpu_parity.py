@@ -173,6 +173,30 @@ def test_llf_entropy_dissipation_and_cfl_steps(orc, esdg):
     assert rel_err(g.get_state(), uo) < TOL
 
 
+def test_cfl_steps_across_calls(orc, esdg):
+    # the CFL step of a step's start state is carried over between calls and
+    # recomputed after set_state; both paths must equal the oracle's CFL steps
+    m, g = make_pair(orc, esdg, 3, 3, (3, 4, 2), warp=0.1, vol="ranocha", surf="llf")
+    u = noisy(inputs.random_fourier(m.coords(), 12), 13)
+    g.set_state(u)
+    t = g.step(dt=0.0, nsteps=2, cfl=0.4, t=0.0)
+    t = g.step(dt=0.0, nsteps=3, cfl=0.4, t=t)
+    uo, to = m.rk4(u, 0.0, 5, cfl=0.4)
+    assert abs(t - to) < 1e-13 * to
+    assert rel_err(g.get_state(), uo) < TOL
+    # fixed-dt step in between, then CFL again (state changed: recomputed)
+    g.step(dt=1e-4, nsteps=1)
+    uo, _ = m.rk4(uo, 1e-4, 1)
+    t2 = g.step(dt=0.0, nsteps=2, cfl=0.3, t=0.0)
+    uo, to2 = m.rk4(uo, 0.0, 2, cfl=0.3)
+    assert abs(t2 - to2) < 1e-13 * to2
+    assert rel_err(g.get_state(), uo) < TOL
+    # a new state invalidates the carried CFL value
+    g.set_state(u)
+    t3 = g.step(dt=0.0, nsteps=1, cfl=0.4, t=0.0)
+    assert abs(t3 - m.max_dt(u, 0.4)) < 1e-13 * t3
+
+
 def test_free_stream_gpu(esdg):
     g = esdg.Problem(3, 4, (4, 3, 5), warp=0.1, volume_flux="ranocha", surface_flux="llf")
     u = np.zeros(g.shape)
