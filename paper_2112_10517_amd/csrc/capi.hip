@@ -50,6 +50,7 @@ struct esdg_problem {
   double* PARTIAL = nullptr;  // reduction partials (FP64)
   double* SCAL = nullptr;     // FP64 scalars: [1] t, [2..7] results
   unsigned long long* LAM = nullptr;  // CFL slots: 2 x kLamSlots (bit patterns of doubles)
+  void* DESC = nullptr;               // ProbDesc<Real> of this problem (device)
   int* FLAG = nullptr;        // non-physical flag
   int red_blocks = 1;
   int64_t red_per_block = 256;
@@ -92,10 +93,31 @@ StageOps<Real> stage_ops(const esdg_problem* P) {
   for (int i = 0; i < P->N * P->N; ++i) o.Dt[i] = (Real)P->ops.Dt[i];
   o.inv_w0 = (Real)(1.0 / P->ops.w[0]);
   o.inv_wp = (Real)(1.0 / P->ops.w[P->N - 1]);
-  for (int j = 0; j < 3; ++j) o.scale[j] = (Real)(P->mesh == MESH_AFFINE ? P->geo.inv_half_h[j] : 1.0);
   o.gamma = (Real)P->gamma;
   o.inv_gm1 = (Real)(1.0 / (P->gamma - 1.0));
   return o;
+}
+
+// descriptor of problem P as the first (tile0) tile of a launch
+template <typename Real>
+ProbDesc<Real> prob_desc(const esdg_problem* P, int tile0) {
+  ProbDesc<Real> d{};
+  d.buf[0] = (Real*)P->U;
+  d.buf[1] = (Real*)P->Y;
+  d.buf[2] = (Real*)P->Y2;
+  d.buf[3] = (Real*)P->R;
+  d.metric = (const Real*)P->METRIC;
+  d.nface = (const Real*)P->NFACE;
+  d.lam = P->LAM;
+  d.t_acc = P->SCAL + 1;
+  d.flag = P->FLAG;
+  d.E = (int)P->E;
+  d.n0 = P->spec.n[0];
+  d.n1 = P->spec.n[1];
+  d.n2 = P->dim == 3 ? P->spec.n[2] : 1;
+  d.tile0 = tile0;
+  for (int j = 0; j < 3; ++j) d.scale[j] = (Real)(P->mesh == MESH_AFFINE ? P->geo.inv_half_h[j] : 1.0);
+  return d;
 }
 
 // launch with optional event bracketing for per-kernel timing
@@ -125,50 +147,55 @@ esdg_status launch(esdg_problem* P, int kind, const void* fn, dim3 grid, dim3 bl
 // terms) and, for the RK modes, the stage update into out / R.
 unsigned long long* lam_slot(esdg_problem* P, int k) { return P->LAM + k * kLamSlots; }
 
-// Time stepping of one stage launch: fixed dt, or CFL from a lam slot.
+// Time stepping of one stage launch: fixed dt, or CFL from the lam slots.
 struct StepCtl {
   double dt_fixed = 0.0, cfl = 0.0;
-  const unsigned long long* lam_in = nullptr;
-  unsigned long long* lam_out = nullptr;
-  unsigned long long* lam_clear = nullptr;
-  int t_mode = 0;
+  int lam_cur = 0, lam_update = 0, t_mode = 0;
 };
 
-// One fused stage launch: right-hand side of `uin` (surface and volume
-// terms) and, for the RK modes, the stage update into out / R.
+enum { BUF_U = 0, BUF_Y = 1, BUF_Y2 = 2, BUF_R = 3 };
+
+// the stage-kernel instantiation and tile size for P's parameters
+VolKernel pick_stage_kernel(const esdg_problem* P) {
+  return P->dim == 2 ? stage_kernel_2d(P->prec, P->N, P->vf, P->mesh) : stage_kernel_3d(P->prec, P->N, P->vf, P->mesh);
+}
+
+// One fused stage launch over the tiles of `nprob` problems sharing P's
+// parameters (descriptors `probs` in device memory): right-hand side of
+// buf[in_idx] (surface and volume terms) and, for the RK modes, the stage
+// update into buf[out_idx] / R; RHS mode may write to out_ext instead.
 template <typename Real>
-esdg_status run_stage(esdg_problem* P, const void* uin, void* out, int mode, double coef_b, double coef_a,
-                      const StepCtl& ctl = StepCtl()) {
+esdg_status run_stage_on(esdg_problem* P, const void* probs, int nprob, int64_t tiles, int in_idx, int out_idx,
+                         void* out_ext, int mode, double coef_b, double coef_a, const StepCtl& ctl) {
   StageArgs<Real> a{};
-  a.uin = (const Real*)uin;
-  a.metric = (const Real*)P->METRIC;
-  a.nface = (const Real*)P->NFACE;
-  a.out = (Real*)out;
-  a.acc = (Real*)P->R;
-  a.u0 = (const Real*)P->U;
-  a.lam_in = ctl.lam_in;
-  a.dt_fixed = ctl.dt_fixed;
-  a.cfl = ctl.cfl;
-  a.lam_out = ctl.lam_out;
-  a.lam_clear = ctl.lam_clear;
-  a.t_acc = P->SCAL + 1;
-  a.t_mode = ctl.t_mode;
-  a.flag = P->FLAG;
-  a.E = (int)P->E;
-  a.n0 = P->spec.n[0];
-  a.n1 = P->spec.n[1];
-  a.n2 = P->dim == 3 ? P->spec.n[2] : 1;
+  a.probs = (const ProbDesc<Real>*)probs;
+  a.nprob = nprob;
+  a.out_ext = (Real*)out_ext;
+  a.in_idx = in_idx;
+  a.out_idx = out_idx;
   a.mode = mode;
   a.surf = P->sf;
   a.coef_b = (Real)coef_b;
   a.coef_a = (Real)coef_a;
+  a.dt_fixed = ctl.dt_fixed;
+  a.cfl = ctl.cfl;
+  a.lam_cur = ctl.lam_cur;
+  a.lam_update = ctl.lam_update;
+  a.t_mode = ctl.t_mode;
   a.ops = stage_ops<Real>(P);
-  VolKernel k = P->dim == 2 ? stage_kernel_2d(P->prec, P->N, P->vf, P->mesh)
-                            : stage_kernel_3d(P->prec, P->N, P->vf, P->mesh);
+  VolKernel k = pick_stage_kernel(P);
   if (!k.fn) return fail(P, ESDG_EINVAL, "no stage kernel for dim=%d p=%d flux=%d", P->dim, P->p, P->vf);
-  dim3 grid((unsigned)((P->E + k.epb - 1) / k.epb));
   void* args[] = {&a};
-  return launch(P, ESDG_KERNEL_STAGE, k.fn, grid, dim3(k.threads), args);
+  return launch(P, ESDG_KERNEL_STAGE, k.fn, dim3((unsigned)tiles), dim3(k.threads), args);
+}
+
+template <typename Real>
+esdg_status run_stage(esdg_problem* P, int in_idx, int out_idx, void* out_ext, int mode, double coef_b,
+                      double coef_a, const StepCtl& ctl = StepCtl()) {
+  const VolKernel k = pick_stage_kernel(P);
+  if (!k.fn) return fail(P, ESDG_EINVAL, "no stage kernel for dim=%d p=%d flux=%d", P->dim, P->p, P->vf);
+  return run_stage_on<Real>(P, P->DESC, 1, (P->E + k.epb - 1) / k.epb, in_idx, out_idx, out_ext, mode, coef_b,
+                            coef_a, ctl);
 }
 
 // FP64 reduction of op over the state (and DU for the entropy rate); the
@@ -204,7 +231,7 @@ esdg_status run_reduce(esdg_problem* P, int op, double cfl, unsigned long long* 
 #define BY_PREC(P, fn, ...) ((P)->prec == PREC_FP32 ? fn<float>(__VA_ARGS__) : fn<double>(__VA_ARGS__))
 
 esdg_status rhs_into(esdg_problem* P, void* out) {
-  return BY_PREC(P, run_stage, P, P->U, out, MODE_RHS, 0.0, 0.0);
+  return BY_PREC(P, run_stage, P, BUF_U, BUF_U, out, MODE_RHS, 0.0, 0.0);
 }
 
 // elementwise precision conversion of n values on the handle's stream
@@ -228,7 +255,8 @@ esdg_status read_scalars(esdg_problem* P, int first, int count, double* out) {
 }
 
 void free_buffers(esdg_problem* P) {
-  void* bufs[] = {P->U, P->Y, P->Y2, P->R, P->DU, P->STAGE64, P->METRIC, P->NFACE, P->PARTIAL, P->SCAL, P->LAM, P->FLAG};
+  void* bufs[] = {P->U, P->Y, P->Y2, P->R, P->DU, P->STAGE64, P->METRIC, P->NFACE, P->PARTIAL, P->SCAL, P->LAM, P->FLAG,
+                  P->DESC};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& t : P->launches) {
@@ -389,6 +417,25 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
     std::vector<double>().swap(P->geo.metric);
     std::vector<double>().swap(P->geo.nface);
   }
+  {
+    const size_t db = P->prec == PREC_FP32 ? sizeof(ProbDesc<float>) : sizeof(ProbDesc<double>);
+    hipError_t e1 = hipMalloc(&P->DESC, db);
+    hipError_t e2 = hipErrorOutOfMemory;
+    if (e1 == hipSuccess) {
+      if (P->prec == PREC_FP32) {
+        ProbDesc<float> d = prob_desc<float>(P, 0);
+        e2 = hipMemcpy(P->DESC, &d, db, hipMemcpyHostToDevice);
+      } else {
+        ProbDesc<double> d = prob_desc<double>(P, 0);
+        e2 = hipMemcpy(P->DESC, &d, db, hipMemcpyHostToDevice);
+      }
+    }
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      free_buffers(P);
+      delete P;
+      return fail(nullptr, ESDG_ENOMEM, "device problem descriptor failed");
+    }
+  }
   if (hipMemset(P->FLAG, 0, sizeof(int)) != hipSuccess || hipMemset(P->SCAL, 0, sizeof(double) * 16) != hipSuccess) {
     free_buffers(P);
     delete P;
@@ -486,39 +533,30 @@ esdg_status esdg_step(esdg_problem* P, double dt, int32_t nsteps, double cfl, do
   const bool use_cfl = !(dt > 0.0);
   if (use_cfl && !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "dt <= 0 needs cfl > 0");
   if (nsteps == 0) return ESDG_OK;
+  // classical RK4 in low-storage form: U (state), R (accumulator) and the
+  // stage state, alternating between Y and Y2 (stage inputs are read across
+  // element faces, so a stage never writes its own input)
+  StepCtl ctl;
   if (!use_cfl) {
-    StepCtl ctl;
     ctl.dt_fixed = dt;
-    for (int s = 0; s < nsteps; ++s) {
-      // stage inputs are read across element faces, so inputs and outputs alternate
-      TRY(BY_PREC(P, run_stage, P, P->U, P->Y, MODE_RK_FIRST, 1.0 / 6.0, 0.5, ctl));
-      TRY(BY_PREC(P, run_stage, P, P->Y, P->Y2, MODE_RK_MID, 1.0 / 3.0, 0.5, ctl));
-      TRY(BY_PREC(P, run_stage, P, P->Y2, P->Y, MODE_RK_MID, 1.0 / 3.0, 1.0, ctl));
-      TRY(BY_PREC(P, run_stage, P, P->Y, P->U, MODE_RK_LAST, 1.0 / 6.0, 0.0, ctl));
-    }
-    P->lam_valid = false;
   } else {
-    // the CFL wave-speed sum of the start state comes from the previous CFL
-    // step's last stage; otherwise from one reduction
+    ctl.cfl = cfl;
+    // the CFL value of the start state comes from the previous CFL step's
+    // last stage; otherwise from one reduction
     if (!P->lam_valid) TRY(BY_PREC(P, run_reduce, P, RED_MAXLAMBDA, cfl, lam_slot(P, P->lam_cur)));
-    for (int s = 0; s < nsteps; ++s) {
-      const int cur = P->lam_cur, nxt = 1 - cur;
-      StepCtl ctl;
-      ctl.cfl = cfl;
-      ctl.lam_in = lam_slot(P, cur);
-      StepCtl first = ctl;
-      first.lam_clear = lam_slot(P, nxt);
-      first.t_mode = s == 0 ? 2 : 1;
-      StepCtl last = ctl;
-      last.lam_out = lam_slot(P, nxt);
-      TRY(BY_PREC(P, run_stage, P, P->U, P->Y, MODE_RK_FIRST, 1.0 / 6.0, 0.5, first));
-      TRY(BY_PREC(P, run_stage, P, P->Y, P->Y2, MODE_RK_MID, 1.0 / 3.0, 0.5, ctl));
-      TRY(BY_PREC(P, run_stage, P, P->Y2, P->Y, MODE_RK_MID, 1.0 / 3.0, 1.0, ctl));
-      TRY(BY_PREC(P, run_stage, P, P->Y, P->U, MODE_RK_LAST, 1.0 / 6.0, 0.0, last));
-      P->lam_cur = nxt;
-    }
-    P->lam_valid = true;
   }
+  for (int s = 0; s < nsteps; ++s) {
+    ctl.lam_cur = P->lam_cur;
+    StepCtl first = ctl, last = ctl;
+    first.t_mode = use_cfl ? (s == 0 ? 2 : 1) : 0;
+    last.lam_update = use_cfl ? 1 : 0;
+    TRY(BY_PREC(P, run_stage, P, BUF_U, BUF_Y, nullptr, MODE_RK_FIRST, 1.0 / 6.0, 0.5, first));
+    TRY(BY_PREC(P, run_stage, P, BUF_Y, BUF_Y2, nullptr, MODE_RK_MID, 1.0 / 3.0, 0.5, ctl));
+    TRY(BY_PREC(P, run_stage, P, BUF_Y2, BUF_Y, nullptr, MODE_RK_MID, 1.0 / 3.0, 1.0, ctl));
+    TRY(BY_PREC(P, run_stage, P, BUF_Y, BUF_U, nullptr, MODE_RK_LAST, 1.0 / 6.0, 0.0, last));
+    if (use_cfl) P->lam_cur = 1 - P->lam_cur;
+  }
+  P->lam_valid = use_cfl;
   if (t_inout) {
     if (use_cfl) {
       double tsum = 0.0;

@@ -1,8 +1,11 @@
 // Host-side LGL operators and mesh geometry (built once per problem).
 #include "host_ops.hpp"
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 namespace esdg {
 
@@ -123,6 +126,20 @@ inline int ipow(int b, int k) {
   return r;
 }
 
+// fn(begin, end) over [0, n) split across the host's threads
+template <typename Fn>
+void parallel_for(int64_t n, Fn fn) {
+  const int64_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t nt = std::min<int64_t>(hw, std::max<int64_t>(1, n / 64));
+  if (nt <= 1) {
+    fn(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int64_t t = 0; t < nt; ++t) th.emplace_back(fn, n * t / nt, n * (t + 1) / nt);
+  for (auto& x : th) x.join();
+}
+
 // b = D_dir a over one element's nodal field (x-fastest tensor layout)
 void apply_d(const Operators& ops, int dim, int dir, const double* a, double* b) {
   const int N = ops.N, nn = ipow(N, dim);
@@ -174,7 +191,8 @@ bool make_geometry(const MeshSpec& s, const Operators& ops, Geometry* g, std::st
   if (s.coords) {
     std::memcpy(g->coords.data(), s.coords, sizeof(double) * g->coords.size());
   } else {
-    for (int64_t e = 0; e < E; ++e) {
+    parallel_for(E, [&](int64_t eb, int64_t ee_) {
+    for (int64_t e = eb; e < ee_; ++e) {
       const int64_t ie[3] = {e % n[0], (e / n[0]) % n[1], e / ((int64_t)n[0] * n[1])};
       for (int q = 0; q < nn; ++q) {
         double xh[3], bump = 1.0;
@@ -187,14 +205,17 @@ bool make_geometry(const MeshSpec& s, const Operators& ops, Geometry* g, std::st
         for (int j = 0; j < dim; ++j) g->coords[((size_t)e * dim + j) * nn + q] = xh[j] + s.warp * bump;
       }
     }
+    });
   }
   if (g->affine) return true;
 
   // metric terms per node: 2D cross-product form, 3D conservative curl form
   const int nm = dim * dim + 1;
   g->metric.assign((size_t)E * nm * nn, 0.0);
+  std::atomic<bool> positive{true};
+  parallel_for(E, [&](int64_t eb, int64_t ee_) {
   std::vector<double> X(3 * nn), dX(9 * nn), t(nn), t2(nn), r1(nn), r2(nn);
-  for (int64_t e = 0; e < E; ++e) {
+  for (int64_t e = eb; e < ee_; ++e) {
     for (int m = 0; m < dim; ++m) {
       const double* xs = &g->coords[((size_t)e * dim + m) * nn];
       double mean = 0.0;
@@ -240,19 +261,22 @@ bool make_geometry(const MeshSpec& s, const Operators& ops, Geometry* g, std::st
             d(1, 0) * (d(0, 1) * d(2, 2) - d(2, 1) * d(0, 2)) +
             d(2, 0) * (d(0, 1) * d(1, 2) - d(1, 1) * d(0, 2));
       }
-      if (!(J > 0.0)) {
-        *err = "mesh has a non-positive Jacobian";
-        return false;
-      }
+      if (!(J > 0.0)) positive.store(false, std::memory_order_relaxed);
       invJ[q] = 1.0 / J;
     }
+  }
+  });
+  if (!positive.load()) {
+    *err = "mesh has a non-positive Jacobian";
+    return false;
   }
 
   // one normal per face node: average of both sides' (Ja)^a
   g->nface.assign((size_t)dim * E * dim * nf, 0.0);
   for (int a = 0; a < dim; ++a) {
     const int sa = ipow(N, a);
-    for (int64_t e = 0; e < E; ++e) {
+    parallel_for(E, [&](int64_t eb, int64_t ee_) {
+    for (int64_t e = eb; e < ee_; ++e) {
       int64_t ie[3] = {e % n[0], (e / n[0]) % n[1], e / ((int64_t)n[0] * n[1])};
       ie[a] = (ie[a] + 1) % n[a];
       const int64_t eR = ie[0] + (int64_t)n[0] * (ie[1] + (int64_t)n[1] * ie[2]);
@@ -268,6 +292,7 @@ bool make_geometry(const MeshSpec& s, const Operators& ops, Geometry* g, std::st
         }
       }
     }
+    });
   }
   return true;
 }

@@ -42,34 +42,43 @@ template <typename Real>
 struct StageOps {
   Real Dt[kDevMaxN * kDevMaxN];  // D~ row-major
   Real inv_w0, inv_wp;           // 1/w_0, 1/w_p
-  Real scale[3];                 // affine: 2/h_n ; curved: 1
   Real gamma, inv_gm1;           // gamma, 1/(gamma-1)
+};
+
+// One problem of a launch (device memory).  A launch covers the tiles of one
+// or more problems of equal degree, flux, mesh kind and precision; a problem
+// computes the same values whether it runs alone or with others.
+template <typename Real>
+struct ProbDesc {
+  Real* buf[4];              // U (state), Y, Y2 (stage states), R (RK accumulator): [E][nv][nn]
+  const Real* metric;        // curved: [E][dim*dim+1][nn] (Ja^n_m, then 1/J)
+  const Real* nface;         // curved: [dim][E][dim][nf] normal of the + face of each element
+  unsigned long long* lam;   // CFL: 2 x kLamSlots slots (bit patterns of non-negative doubles)
+  double* t_acc;             // elapsed time of the current step call
+  int* flag;                 // non-physical state flag
+  int E, n0, n1, n2;         // elements, per direction
+  int tile0;                 // first tile of this problem in the launch
+  int pad;
+  Real scale[3];             // affine: 2/h_n ; curved: 1
 };
 
 template <typename Real>
 struct StageArgs {
-  const Real* uin;     // stage input state [E][nv][nn]
-  const Real* metric;  // curved: [E][dim*dim+1][nn] (Ja^n_m, then 1/J)
-  const Real* nface;   // curved: [dim][E][dim][nf] normal of the + face of each element
-  Real* out;           // MODE_RHS: du; RK: stage output y (FIRST, MID) or state (LAST)
-  Real* acc;           // RK accumulator
-  const Real* u0;      // RK state at the start of the step (MID)
-  // time step: fixed (lam_in == NULL) or CFL, dt = cfl 2 / (N lam) with lam the
-  // largest sum over directions of wave speeds of the step's start state,
-  // kept as the bit pattern of a non-negative double in a device slot
-  // (kLamSlots slots: the maximum over the slots counts)
-  const unsigned long long* lam_in;
+  const ProbDesc<Real>* probs;  // problems of the launch, ordered by tile0
+  int nprob;
+  Real* out_ext;        // RHS mode of a single problem: output; else NULL (buf[out_idx])
+  int in_idx, out_idx;  // ProbDesc::buf indices of the stage input and output
+  int mode;             // StageMode
+  int surf;             // SurfFlux
+  Real coef_b, coef_a;  // RK: acc += b dt k ; y = u0 + a dt k
+  // time step: fixed (cfl <= 0) or dt = cfl 2 / (N lam) with lam the largest
+  // sum over directions of wave speeds of the step's start state, the maximum
+  // over the problem's kLamSlots slots of parity lam_cur
   double dt_fixed, cfl;
-  unsigned long long* lam_out;    // LAST stage: max over the new state (atomic max per wave), or NULL
-  unsigned long long* lam_clear;  // FIRST stage: slots to reset for this step's LAST stage, or NULL
-  double* t_acc;                  // FIRST stage: elapsed time (t_mode 1: += dt, 2: = dt)
-  int t_mode;
-  int* flag;           // non-physical state flag
-  int E;               // elements
-  int n0, n1, n2;      // elements per direction
-  int mode;            // StageMode
-  int surf;            // SurfFlux
-  Real coef_b, coef_a; // RK: acc += b dt k ; y = u0 + a dt k
+  int lam_cur;
+  int lam_update;       // LAST stage: atomic max of the new state's value into parity 1 - lam_cur
+  int t_mode;           // FIRST stage: 1: t += dt, 2: t = dt (one lane per problem)
+  int pad;
   StageOps<Real> ops;
 };
 
@@ -281,7 +290,7 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 // compile-time constants).
 template <int DIR, int DIM, int N, int VF, int MESH, typename Real>
 __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value], const Real (&nrm)[N][3], int base,
-                                            const StageOps<Real>& ops, Real (&A)[N][DIM + 2]) {
+                                            const StageOps<Real>& ops, Real scale, Real (&A)[N][DIM + 2]) {
   constexpr int NV = DIM + 2;
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int stride = Pow<N, DIR>::value;
@@ -325,7 +334,7 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
 #pragma unroll
     for (int k = 0; k < N; ++k)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) A[k][v] *= ops.scale[DIR];
+      for (int v = 0; v < NV; ++v) A[k][v] *= scale;
   }
 }
 
@@ -343,23 +352,47 @@ stage_kernel(StageArgs<Real> a) {
   __shared__ int s_nbr[EPB][2 * DIM];      // neighbour across face (2 dir + side), side 1 = +
 
   const int tid = threadIdx.x;
-  const int e0 = xcd_tile(blockIdx.x, gridDim.x) * EPB;
+  // tile -> problem (binary search over the problems' first tiles)
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  int pi = 0;
+  if (a.nprob > 1) {
+    int lo = 0, hi = a.nprob - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.probs[mid].tile0 <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    pi = lo;
+  }
+  const ProbDesc<Real>& P = a.probs[pi];
+  const Real* uin = P.buf[a.in_idx];
+  Real* out = a.out_ext ? a.out_ext : P.buf[a.out_idx];
+  Real* racc_buf = P.buf[3];
+  const Real* u0 = P.buf[0];
+  const Real* metric = P.metric;
+  const Real* nface = P.nface;
+  const int E = P.E, n0 = P.n0, n1 = P.n1, n2 = P.n2;
+  const int e0 = (tile - P.tile0) * EPB;
+  const bool cfl_mode = a.cfl > 0.0;
+  const unsigned long long* lam_in = P.lam + a.lam_cur * kLamSlots;
+  unsigned long long* lam_next = P.lam + (1 - a.lam_cur) * kLamSlots;
+  const bool lam_out = a.mode == MODE_RK_LAST && cfl_mode && a.lam_update;
   const Real gm1 = a.ops.gamma - Real(1);
   if (tid < EPB) {
     const int e = e0 + tid;
-    const int ex = e % a.n0, ey = (e / a.n0) % a.n1, ez = e / (a.n0 * a.n1);
-    const int exm = ex == 0 ? a.n0 - 1 : ex - 1, exp_ = ex == a.n0 - 1 ? 0 : ex + 1;
-    s_nbr[tid][0] = exm + a.n0 * (ey + a.n1 * ez);
-    s_nbr[tid][1] = exp_ + a.n0 * (ey + a.n1 * ez);
+    const int ex = e % n0, ey = (e / n0) % n1, ez = e / (n0 * n1);
+    const int exm = ex == 0 ? n0 - 1 : ex - 1, exp_ = ex == n0 - 1 ? 0 : ex + 1;
+    s_nbr[tid][0] = exm + n0 * (ey + n1 * ez);
+    s_nbr[tid][1] = exp_ + n0 * (ey + n1 * ez);
     if (DIM > 1) {
-      const int eym = ey == 0 ? a.n1 - 1 : ey - 1, eyp = ey == a.n1 - 1 ? 0 : ey + 1;
-      s_nbr[tid][DIM > 1 ? 2 : 0] = ex + a.n0 * (eym + a.n1 * ez);
-      s_nbr[tid][DIM > 1 ? 3 : 0] = ex + a.n0 * (eyp + a.n1 * ez);
+      const int eym = ey == 0 ? n1 - 1 : ey - 1, eyp = ey == n1 - 1 ? 0 : ey + 1;
+      s_nbr[tid][DIM > 1 ? 2 : 0] = ex + n0 * (eym + n1 * ez);
+      s_nbr[tid][DIM > 1 ? 3 : 0] = ex + n0 * (eyp + n1 * ez);
     }
     if (DIM > 2) {
-      const int ezm = ez == 0 ? a.n2 - 1 : ez - 1, ezp = ez == a.n2 - 1 ? 0 : ez + 1;
-      s_nbr[tid][DIM > 2 ? 4 : 0] = ex + a.n0 * (ey + a.n1 * ezm);
-      s_nbr[tid][DIM > 2 ? 5 : 0] = ex + a.n0 * (ey + a.n1 * ezp);
+      const int ezm = ez == 0 ? n2 - 1 : ez - 1, ezp = ez == n2 - 1 ? 0 : ez + 1;
+      s_nbr[tid][DIM > 2 ? 4 : 0] = ex + n0 * (ey + n1 * ezm);
+      s_nbr[tid][DIM > 2 ? 5 : 0] = ex + n0 * (ey + n1 * ezp);
     }
   }
 
@@ -368,7 +401,7 @@ stage_kernel(StageArgs<Real> a) {
   const int lrem = tid - ldir * LANES_DIR;
   const int lel = lrem / L;
   const int lline = lrem - lel * L;
-  const bool lactive = lel < EPB && e0 + lel < a.E;
+  const bool lactive = lel < EPB && e0 + lel < E;
   const int stride = ldir == 0 ? 1 : (ldir == 1 ? N : N * N);
   const int lbase = (lline % stride) + (lline / stride) * stride * N;
 
@@ -381,16 +414,16 @@ stage_kernel(StageArgs<Real> a) {
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
     const int el = q / NN, i = q - el * NN;
-    const bool ok = q < EPB * NN && e0 + el < a.E;
+    const bool ok = q < EPB * NN && e0 + el < E;
     const size_t o = ok ? (size_t)(e0 + el) * (NV * NN) + i : 0;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) uo[r][v] = a.uin[o + (size_t)v * NN];
-    rinvj[r] = MESH == MESH_CURVED ? a.metric[(ok ? (size_t)(e0 + el) * (NM * NN) + i : 0) + (size_t)(NM - 1) * NN]
+    for (int v = 0; v < NV; ++v) uo[r][v] = uin[o + (size_t)v * NN];
+    rinvj[r] = MESH == MESH_CURVED ? metric[(ok ? (size_t)(e0 + el) * (NM * NN) + i : 0) + (size_t)(NM - 1) * NN]
                                    : Real(1);
   }
   Real nrm[N][3];
   if (MESH == MESH_CURVED) {
-    const Real* me = a.metric + (size_t)(lactive ? e0 + lel : 0) * (NM * NN);
+    const Real* me = metric + (size_t)(lactive ? e0 + lel : 0) * (NM * NN);
 #pragma unroll
     for (int k = 0; k < N; ++k)
 #pragma unroll
@@ -402,7 +435,7 @@ stage_kernel(StageArgs<Real> a) {
   for (int r = 0; r < FPT; ++r) {
     const int t = tid + r * THREADS;
     const int el = t / NFACE, rr = t - el * NFACE;
-    const bool ok = t < EPB * NFACE && e0 + el < a.E;
+    const bool ok = t < EPB * NFACE && e0 + el < E;
     const int fc = rr / NF, f = rr - fc * NF, dir = fc >> 1, side = fc & 1;
     const int e = ok ? e0 + el : 0;
     const int en = ok ? s_nbr[el][fc] : 0;
@@ -410,11 +443,11 @@ stage_kernel(StageArgs<Real> a) {
     const int qL = face_node<N>(dir, f, N - 1), qR = face_node<N>(dir, f, 0);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      tL[r][v] = a.uin[(size_t)eL * (NV * NN) + v * NN + qL];
-      tR[r][v] = a.uin[(size_t)eR * (NV * NN) + v * NN + qR];
+      tL[r][v] = uin[(size_t)eL * (NV * NN) + v * NN + qL];
+      tR[r][v] = uin[(size_t)eR * (NV * NN) + v * NN + qR];
     }
     if (MESH == MESH_CURVED) {
-      const Real* nf = a.nface + ((size_t)dir * a.E + eL) * (DIM * NF) + f;
+      const Real* nf = nface + ((size_t)dir * E + eL) * (DIM * NF) + f;
       tn[r][0] = nf[0];
       tn[r][1] = DIM > 1 ? nf[NF] : Real(0);
       tn[r][2] = DIM > 2 ? nf[2 * NF] : Real(0);
@@ -430,7 +463,7 @@ stage_kernel(StageArgs<Real> a) {
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
     const int el = q / NN, i = q - el * NN;
-    if (!(q < EPB * NN && e0 + el < a.E)) continue;
+    if (!(q < EPB * NN && e0 + el < E)) continue;
     const Real rho = uo[r][0];
     const Real inv_rho = dev_rcp(rho);
     const Real m0 = uo[r][1];
@@ -439,7 +472,7 @@ stage_kernel(StageArgs<Real> a) {
     const Real E_ = uo[r][DIM + 1];
     const Real v0 = m0 * inv_rho, v1 = m1 * inv_rho, v2 = m2 * inv_rho;
     const Real p = gm1 * (E_ - Real(0.5) * (m0 * v0 + m1 * v1 + m2 * v2));
-    if (!(rho > Real(0)) || !(p > Real(0)) || !isfinite(E_) || !isfinite(m0 + m1 + m2)) atomicOr(a.flag, 1);
+    if (!(rho > Real(0)) || !(p > Real(0)) || !isfinite(E_) || !isfinite(m0 + m1 + m2)) atomicOr(P.flag, 1);
     s_prim[el][0][i] = rho;
     s_prim[el][1][i] = v0;
     if (DIM > 1) s_prim[el][DIM > 1 ? 2 : 0][i] = v1;
@@ -456,7 +489,7 @@ stage_kernel(StageArgs<Real> a) {
   for (int r = 0; r < FPT; ++r) {
     const int t = tid + r * THREADS;
     const int el = t / NFACE, rr = t - el * NFACE;
-    if (!(t < EPB * NFACE && e0 + el < a.E)) continue;
+    if (!(t < EPB * NFACE && e0 + el < E)) continue;
     Real F[NV];
     surface_flux<DIM>(a.surf, tL[r], tR[r], tn[r][0], tn[r][1], tn[r][2], a.ops.gamma, a.ops.inv_gm1, F);
 #pragma unroll
@@ -468,9 +501,10 @@ stage_kernel(StageArgs<Real> a) {
   Real A[N][NV];
   {
     const Real(*sp)[NN] = s_prim[lactive ? lel : 0];
-    if (ldir == 0) line_fluxes<0, DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, A);
-    else if (DIM > 1 && ldir == 1) line_fluxes<(DIM > 1 ? 1 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, A);
-    else if (DIM > 2) line_fluxes<(DIM > 2 ? 2 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, A);
+    const Real sc = P.scale[ldir];
+    if (ldir == 0) line_fluxes<0, DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, sc, A);
+    else if (DIM > 1 && ldir == 1) line_fluxes<(DIM > 1 ? 1 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, sc, A);
+    else if (DIM > 2) line_fluxes<(DIM > 2 ? 2 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, sc, A);
   }
   // RK registers of the owned nodes, in flight while the line sums are merged
   Real ru0[NPT][NV], racc[NPT][NV];
@@ -480,12 +514,12 @@ stage_kernel(StageArgs<Real> a) {
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
     const int el = q / NN, i = q - el * NN;
-    const bool ok = q < EPB * NN && e0 + el < a.E;
+    const bool ok = q < EPB * NN && e0 + el < E;
     const size_t o = ok ? (size_t)(e0 + el) * (NV * NN) + i : 0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      ru0[r][v] = need_u0 ? a.u0[o + (size_t)v * NN] : Real(0);
-      racc[r][v] = need_acc ? a.acc[o + (size_t)v * NN] : Real(0);
+      ru0[r][v] = need_u0 ? u0[o + (size_t)v * NN] : Real(0);
+      racc[r][v] = need_acc ? racc_buf[o + (size_t)v * NN] : Real(0);
     }
   }
   // fixed summation order over directions: dir 0 writes, then dir 1, dir 2 add
@@ -508,9 +542,9 @@ stage_kernel(StageArgs<Real> a) {
   // ---- epilogue: lifting, -1/J, stage update
   double dt = a.dt_fixed;
   if (a.mode == MODE_RHS) dt = 0.0;
-  if (a.mode != MODE_RHS && a.lam_in) {
+  if (a.mode != MODE_RHS && cfl_mode) {
     // every wave folds the slots: lane l reads slot l, then a max over the wave
-    double lam = __longlong_as_double((long long)a.lam_in[tid & (kLamSlots - 1)]);
+    double lam = __longlong_as_double((long long)lam_in[tid & (kLamSlots - 1)]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       const double o = __shfl_xor(lam, off, 64);
@@ -518,17 +552,17 @@ stage_kernel(StageArgs<Real> a) {
     }
     dt = a.cfl * 2.0 / ((double)N * lam);
   }
-  if (blockIdx.x == 0 && a.mode == MODE_RK_FIRST) {
-    if (a.lam_clear && tid < kLamSlots) a.lam_clear[tid] = 0ull;
-    if (tid == 0 && a.t_mode == 1) *a.t_acc += dt;
-    if (tid == 0 && a.t_mode == 2) *a.t_acc = dt;
+  if (e0 == 0 && a.mode == MODE_RK_FIRST) {
+    if (cfl_mode && tid < kLamSlots) lam_next[tid] = 0ull;
+    if (tid == 0 && a.t_mode == 1) *P.t_acc += dt;
+    if (tid == 0 && a.t_mode == 2) *P.t_acc = dt;
   }
   double lam_max = 0.0;  // CFL wave-speed sum of the new state (LAST stage)
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
     const int el = q / NN, i = q - el * NN;
-    if (!(q < EPB * NN && e0 + el < a.E)) continue;
+    if (!(q < EPB * NN && e0 + el < E)) continue;
     const int ee = e0 + el;
     const int ix = i % N;
     const int iy = DIM > 1 ? (i / N) % N : 0;
@@ -541,7 +575,7 @@ stage_kernel(StageArgs<Real> a) {
       const int id = dir == 0 ? ix : (dir == 1 ? iy : iz);
       if (id != 0 && id != N - 1) continue;
       const int f = dir == 0 ? (iy + N * iz) : (dir == 1 ? (ix + N * iz) : (ix + N * iy));
-      const Real sc = MESH == MESH_AFFINE ? a.ops.scale[dir] : Real(1);
+      const Real sc = MESH == MESH_AFFINE ? P.scale[dir] : Real(1);
       if (id == N - 1) {
         const Real w = sc * a.ops.inv_wp;
 #pragma unroll
@@ -561,19 +595,19 @@ stage_kernel(StageArgs<Real> a) {
       const Real k = mul * S[v];
       const size_t o = base + (size_t)v * NN;
       if (a.mode == MODE_RHS) {
-        a.out[o] = k;
+        out[o] = k;
       } else if (a.mode == MODE_RK_FIRST) {
-        a.acc[o] = uo[r][v] + a.coef_b * (Real)dt * k;
-        a.out[o] = uo[r][v] + a.coef_a * (Real)dt * k;
+        racc_buf[o] = uo[r][v] + a.coef_b * (Real)dt * k;
+        out[o] = uo[r][v] + a.coef_a * (Real)dt * k;
       } else if (a.mode == MODE_RK_MID) {
-        a.acc[o] = racc[r][v] + a.coef_b * (Real)dt * k;
-        a.out[o] = ru0[r][v] + a.coef_a * (Real)dt * k;
+        racc_buf[o] = racc[r][v] + a.coef_b * (Real)dt * k;
+        out[o] = ru0[r][v] + a.coef_a * (Real)dt * k;
       } else {
         unew[v] = racc[r][v] + a.coef_b * (Real)dt * k;
-        a.out[o] = unew[v];
+        out[o] = unew[v];
       }
     }
-    if (a.lam_out) {
+    if (lam_out) {
       // sum_n (|v.Ja^n| + c |Ja^n|) / J of the new state at this node
       const Real rho = unew[0], ir = dev_rcp(rho);
       const Real w0 = unew[1] * ir;
@@ -583,7 +617,7 @@ stage_kernel(StageArgs<Real> a) {
       const Real c = sqrt(a.ops.gamma * pr * ir);
       Real lam = Real(0);
       if (MESH == MESH_CURVED) {
-        const Real* me = a.metric + (size_t)ee * (NM * NN) + i;
+        const Real* me = metric + (size_t)ee * (NM * NN) + i;
 #pragma unroll
         for (int n = 0; n < DIM; ++n) {
           const Real j0 = me[(n * DIM) * NN];
@@ -593,15 +627,15 @@ stage_kernel(StageArgs<Real> a) {
         }
         lam *= rinvj[r];
       } else {
-        lam = (fabs(w0) + c) * a.ops.scale[0];
-        if (DIM > 1) lam += (fabs(w1) + c) * a.ops.scale[DIM > 1 ? 1 : 0];
-        if (DIM > 2) lam += (fabs(w2) + c) * a.ops.scale[DIM > 2 ? 2 : 0];
+        lam = (fabs(w0) + c) * P.scale[0];
+        if (DIM > 1) lam += (fabs(w1) + c) * P.scale[DIM > 1 ? 1 : 0];
+        if (DIM > 2) lam += (fabs(w2) + c) * P.scale[DIM > 2 ? 2 : 0];
       }
       const double ld = (double)lam;
       if (!(ld <= lam_max)) lam_max = ld;  // a NaN wins and poisons dt (flagged anyway)
     }
   }
-  if (a.lam_out) {
+  if (lam_out) {
     // max over the wave, then one atomic per wave: max is exact, so the
     // result does not depend on the order of the atomics
 #pragma unroll
@@ -610,7 +644,7 @@ stage_kernel(StageArgs<Real> a) {
       if (!(o <= lam_max)) lam_max = o;
     }
     if ((tid & 63) == 0)
-      atomicMax(a.lam_out + (blockIdx.x & (kLamSlots - 1)), (unsigned long long)__double_as_longlong(lam_max));
+      atomicMax(lam_next + (blockIdx.x & (kLamSlots - 1)), (unsigned long long)__double_as_longlong(lam_max));
   }
 }
 
