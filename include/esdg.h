@@ -119,10 +119,15 @@ esdg_status esdg_rhs(esdg_problem *prob, double *du, int32_t where);
  * accumulator and two alternating stage buffers), each stage one fused
  * launch (surface flux + volume term + lifting + stage update).  dt > 0: fixed step; dt <= 0:
  * dt = cfl*2/((p+1) max_i sum_n (|v.Ja^n|+c|Ja^n|)/J_i) recomputed at the start
- * of every step on the device.  *t_inout (may be NULL) is advanced by the
- * total time; in CFL mode this synchronises the stream. */
+ * of every step on the device.  The problem's time (device, FP64) advances by
+ * each step's dt.  t_inout (may be NULL): on entry the time to start from, on
+ * return the time reached (this synchronises the stream). */
 esdg_status esdg_step(esdg_problem *prob, double dt, int32_t nsteps, double cfl,
                       double *t_inout);
+
+/* The problem's time (0 after esdg_init_mesh); esdg_get_time synchronises. */
+esdg_status esdg_set_time(esdg_problem *prob, double t);
+esdg_status esdg_get_time(esdg_problem *prob, double *t);
 
 /* entropy_rate: dS/dt = sum_i J_i W_i w(u_i) . RHS_i with the entropy
  * U = -rho s/(gamma-1), s = ln p - gamma ln rho (Sec. 2 entropy definitions);
@@ -151,6 +156,139 @@ esdg_status esdg_timing_enable(esdg_problem *prob, int32_t enable);
 esdg_status esdg_timing_read(esdg_problem *prob, int32_t kernel, double *total_ms,
                              int64_t *launches);
 esdg_status esdg_timing_reset(esdg_problem *prob);
+
+/* Tile variants of the fused stage kernel (workgroup shapes: elements per
+ * workgroup and lanes per direction).  Every variant computes bit-identical
+ * results; only the speed differs.  The variant in use is chosen per
+ * (dim, p, volume flux, mesh kind, precision) in a process-wide table,
+ * variant 0 until changed.  2D problems have variant 0 only.
+ *   esdg_autotune: times every variant on the problem's current state (reps
+ *     right-hand-side launches each, written to internal scratch; the state
+ *     is unchanged), stores the fastest in the table and returns it in *best
+ *     and the time per launch of each variant in us_per_variant
+ *     [ESDG_TILE_VARIANTS] (either may be NULL; -1 for a missing variant).
+ *     Synchronises the stream.
+ *   esdg_set_tile_variant: store a variant for the problem's parameters.
+ *   esdg_get_tile_variant: the variant in use and its elements per workgroup. */
+#define ESDG_TILE_VARIANTS 3
+esdg_status esdg_autotune(esdg_problem *prob, int32_t reps, int32_t *best, double *us_per_variant);
+esdg_status esdg_set_tile_variant(esdg_problem *prob, int32_t variant);
+esdg_status esdg_get_tile_variant(const esdg_problem *prob, int32_t *variant, int32_t *elems_per_block);
+
+/* Device memory (bytes) esdg_init_mesh would allocate for the descriptor:
+ * five state-sized arrays (state, two stage states, accumulator, RHS), an
+ * FP64 staging array in FP32 mode, metrics and face normals on curved
+ * meshes, and small scalars.  No device call. */
+esdg_status esdg_footprint(const esdg_mesh_desc *desc, int64_t *bytes);
+
+/* ---- batches: several problems advanced together ------------------------
+ * A batch groups problems by (dim, p, volume and surface flux, mesh kind,
+ * precision, gamma); each RK stage is one launch per group over the
+ * element tiles of all its problems.  Every problem computes exactly what it
+ * computes alone (same kernels, same per-element arithmetic): states, times
+ * and CFL steps are bit-identical to esdg_step on the problem by itself.
+ * The batch references the problems (it does not own them): they must stay
+ * alive, on one device, and keep their state set while the batch exists.
+ *   t_end: optional per-problem end times (NULL: none); a step of problem i
+ *     never passes t_end[i] (dt = min(dt, t_end[i] - t)), so a problem that
+ *     has reached its end time takes steps of dt = 0 (no change).
+ *   stream: hipStream_t of the batch's work; NULL: the batch creates a
+ *     non-blocking stream of its own.  Work already enqueued on a member's
+ *     stream is ordered before the batch's work, and the batch's work before
+ *     later work on the members' streams.
+ *   flags: ESDG_BATCH_GRAPHS replays each step as a captured HIP graph;
+ *     ESDG_BATCH_CONCURRENT lets the groups of a stage run on concurrent
+ *     streams. */
+typedef struct esdg_batch esdg_batch;
+#define ESDG_BATCH_GRAPHS 1
+#define ESDG_BATCH_CONCURRENT 2
+esdg_status esdg_batch_create(esdg_problem *const *probs, int32_t count, const double *t_end, void *stream,
+                              int32_t flags, esdg_batch **out);
+void esdg_batch_destroy(esdg_batch *batch);
+
+/* nsteps RK4 steps of every member as in esdg_step (dt > 0 fixed, else CFL
+ * with each member's own dt). */
+esdg_status esdg_batch_step(esdg_batch *batch, double dt, int32_t nsteps, double cfl);
+
+/* Right-hand side of every member's state; du[i] (FP64, state layout, host or
+ * device as `where` says) receives member i's; du or du[i] may be NULL (the
+ * result then stays in the member's internal buffer). */
+esdg_status esdg_batch_rhs(esdg_batch *batch, double *const *du, int32_t where);
+
+/* Current time of every member into t[count] (host); synchronises. */
+esdg_status esdg_batch_times(esdg_batch *batch, double *t);
+
+/* Wait for the batch's work; ESDG_ENONPHYSICAL with *bad (may be NULL) the
+ * first member whose kernels met a non-physical state (its flag is cleared,
+ * so a further call reports the next one), else *bad = -1. */
+esdg_status esdg_batch_sync(esdg_batch *batch, int32_t *bad);
+
+/* Tune the tile variant of every group on its largest member (esdg_autotune). */
+esdg_status esdg_batch_autotune(esdg_batch *batch, int32_t reps);
+
+/* Groups (launches per stage) and total element tiles of the batch. */
+esdg_status esdg_batch_info(esdg_batch *batch, int32_t *groups, int64_t *tiles);
+
+/* Whole-step timing: while enabled every esdg_batch_step step is bracketed by
+ * an event pair on the batch stream; read returns the summed ms and the
+ * number of steps since the last read, and resets. */
+esdg_status esdg_batch_timing_enable(esdg_batch *batch, int32_t enable);
+esdg_status esdg_batch_timing_read(esdg_batch *batch, double *total_ms, int64_t *steps);
+
+const char *esdg_batch_last_error(const esdg_batch *batch);
+
+/* ---- serving: a continuous-batching loop over time-integration jobs -----
+ * Jobs (a mesh, an initial state, a start and an end time) are queued by
+ * esdg_server_submit and admitted in arrival order while the device memory
+ * of the admitted and unfetched jobs (esdg_footprint) stays within
+ * hbm_budget and at most max_active jobs are being stepped.  Each
+ * esdg_server_tick enqueues steps_per_tick CFL steps of every admitted job as
+ * one batch (a job that reaches t_end stops there), admits what fits while
+ * the device works (geometry and state upload of new jobs), then retires
+ * the jobs that have reached their end time.  A retired job's final state
+ * stays on the device until esdg_server_fetch.  Each job's result is
+ * bit-identical to the same job served alone.  Host-side calls on one
+ * server are not thread-safe. */
+typedef struct esdg_server esdg_server;
+typedef struct {
+  int64_t hbm_budget;      /* bytes for admitted jobs; 0: 90% of the free device memory */
+  int32_t max_active;      /* admitted jobs at most; 0: no limit */
+  int32_t steps_per_tick;  /* RK steps per tick, >= 1 */
+  int32_t flags;           /* ESDG_BATCH_* for the batch of admitted jobs */
+  int32_t pad;
+  double cfl;              /* CFL number of every job's steps, > 0 */
+} esdg_server_config;
+
+typedef struct {
+  esdg_mesh_desc mesh;  /* the stream field is ignored */
+  const double *u0;     /* initial state (host, FP64, state layout); copied by submit */
+  double t0, t_end;     /* start and end time, t_end > t0 */
+} esdg_job_desc;
+
+typedef enum {
+  ESDG_JOB_QUEUED = 0,
+  ESDG_JOB_ACTIVE = 1,
+  ESDG_JOB_DONE = 2,     /* reached t_end; state ready for esdg_server_fetch */
+  ESDG_JOB_FAILED = 3    /* non-physical state or device error; see esdg_server_last_error */
+} esdg_job_status;
+
+esdg_status esdg_server_create(const esdg_server_config *cfg, esdg_server **out);
+void esdg_server_destroy(esdg_server *server);
+/* Queue a job; ESDG_EINVAL if its footprint exceeds the whole budget. */
+esdg_status esdg_server_submit(esdg_server *server, const esdg_job_desc *job, int64_t *job_id);
+/* One tick (see above); the counts after it (any may be NULL). */
+esdg_status esdg_server_tick(esdg_server *server, int32_t *finished, int32_t *active, int32_t *queued);
+/* Status, current time and RK steps taken (including dt = 0 steps after
+ * t_end within the last tick) of a job (any output may be NULL). */
+esdg_status esdg_server_job(esdg_server *server, int64_t job_id, int32_t *status, double *t, int64_t *steps);
+/* Jobs that finished (DONE or FAILED) in the last tick: up to max ids, *n of them. */
+esdg_status esdg_server_finished(esdg_server *server, int64_t *ids, int32_t max, int32_t *n);
+/* Copy a DONE job's final state to u (host, FP64; may be NULL) and release
+ * the job (also releases a FAILED job). */
+esdg_status esdg_server_fetch(esdg_server *server, int64_t job_id, double *u);
+/* Device memory held by admitted and finished-but-unfetched jobs. */
+esdg_status esdg_server_memory(esdg_server *server, int64_t *used, int64_t *budget);
+const char *esdg_server_last_error(const esdg_server *server);
 
 /* Last error message of the handle (or of the calling thread if prob is NULL). */
 const char *esdg_last_error(const esdg_problem *prob);

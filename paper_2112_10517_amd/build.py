@@ -18,8 +18,9 @@ LIB = os.path.join(OUTDIR, "libesdg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("ESDG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["capi.hip", "host_ops.cpp", "dispatch_misc.hip", "dispatch_vol2d.hip", "dispatch_vol3d.hip",
-           "dispatch_vol2d_f32.hip", "dispatch_vol3d_f32.hip"]
+SOURCES = ["capi.hip", "batch.hip", "host_ops.cpp", "server.cpp", "dispatch_misc.hip", "dispatch_vol2d.hip",
+           "dispatch_vol3d.hip", "dispatch_vol2d_f32.hip", "dispatch_vol3d_f32.hip", "dispatch_vol3d_tuned.hip",
+           "dispatch_vol3d_f32_tuned.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include")]

@@ -1,17 +1,18 @@
 // C ABI of the library (include/esdg.h): problem handles, device buffers,
-// launch sequencing and error reporting.
+// launch sequencing, the tile-variant autotuner and error reporting.
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
-#include "esdg.h"
-#include "dispatch.hpp"
-#include "host_ops.hpp"
-#include "kernels.hpp"
+#include "problem.hpp"
 
 using namespace esdg;
 
@@ -19,54 +20,20 @@ namespace {
 
 thread_local std::string g_thread_error;
 
-struct TimedLaunch {
-  int kind;
-  hipEvent_t start, stop;
-};
-
 }  // namespace
 
-struct esdg_problem {
-  MeshSpec spec;
-  Operators ops;
-  Geometry geo;
-  int dim = 3, p = 3, N = 4, nn = 64, nv = 5, nf = 16;
-  int64_t E = 0;
-  int vf = VF_RANOCHA, sf = SF_LLF, prec = PREC_FP64, mesh = MESH_AFFINE;
-  double gamma = 1.4;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  size_t rsize = 8;  // bytes per internal real
+namespace esdg {
 
-  // device buffers (internal precision unless noted)
-  void* U = nullptr;       // state
-  void* Y = nullptr;       // RK stage state
-  void* R = nullptr;       // RK accumulator
-  void* DU = nullptr;      // right-hand side scratch
-  double* STAGE64 = nullptr;  // FP32 mode: FP64 staging of states crossing the ABI
-  void* Y2 = nullptr;      // second RK stage state (stage inputs and outputs alternate)
-  void* METRIC = nullptr;  // curved metrics
-  void* NFACE = nullptr;   // curved face normals
-  double* PARTIAL = nullptr;  // reduction partials (FP64)
-  double* SCAL = nullptr;     // FP64 scalars: [1] t, [2..7] results
-  unsigned long long* LAM = nullptr;  // CFL slots: 2 x kLamSlots (bit patterns of doubles)
-  void* DESC = nullptr;               // ProbDesc<Real> of this problem (device)
-  int* FLAG = nullptr;        // non-physical flag
-  int red_blocks = 1;
-  int64_t red_per_block = 256;
-
-  bool have_state = false;
-  // CFL: the largest wave-speed sum of the current state lives in one of two
-  // device slots (bit pattern of a double); valid until the state changes
-  // other than through esdg_step in CFL mode
-  bool lam_valid = false;
-  int lam_cur = 0;
-  bool timing = false;
-  std::vector<TimedLaunch> launches;
-  std::string err;
-};
-
-namespace {
+esdg_status report(std::string* dst, esdg_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (dst) *dst = buf;
+  g_thread_error = buf;
+  return st;
+}
 
 esdg_status fail(esdg_problem* P, esdg_status st, const char* fmt, ...) {
   char buf[512];
@@ -79,130 +46,57 @@ esdg_status fail(esdg_problem* P, esdg_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIPCHECK(P, call)                                                                   \
-  do {                                                                                      \
-    hipError_t e_ = (call);                                                                 \
-    if (e_ != hipSuccess) return fail((P), ESDG_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
-
-size_t state_count(const esdg_problem* P) { return (size_t)P->E * P->nv * P->nn; }
-
-template <typename Real>
-StageOps<Real> stage_ops(const esdg_problem* P) {
-  StageOps<Real> o{};
-  for (int i = 0; i < P->N * P->N; ++i) o.Dt[i] = (Real)P->ops.Dt[i];
-  o.inv_w0 = (Real)(1.0 / P->ops.w[0]);
-  o.inv_wp = (Real)(1.0 / P->ops.w[P->N - 1]);
-  o.gamma = (Real)P->gamma;
-  o.inv_gm1 = (Real)(1.0 / (P->gamma - 1.0));
-  return o;
-}
-
-// descriptor of problem P as the first (tile0) tile of a launch
-template <typename Real>
-ProbDesc<Real> prob_desc(const esdg_problem* P, int tile0) {
-  ProbDesc<Real> d{};
-  d.buf[0] = (Real*)P->U;
-  d.buf[1] = (Real*)P->Y;
-  d.buf[2] = (Real*)P->Y2;
-  d.buf[3] = (Real*)P->R;
-  d.metric = (const Real*)P->METRIC;
-  d.nface = (const Real*)P->NFACE;
-  d.lam = P->LAM;
-  d.t_acc = P->SCAL + 1;
-  d.flag = P->FLAG;
-  d.E = (int)P->E;
-  d.n0 = P->spec.n[0];
-  d.n1 = P->spec.n[1];
-  d.n2 = P->dim == 3 ? P->spec.n[2] : 1;
-  d.tile0 = tile0;
-  for (int j = 0; j < 3; ++j) d.scale[j] = (Real)(P->mesh == MESH_AFFINE ? P->geo.inv_half_h[j] : 1.0);
-  return d;
-}
-
-// launch with optional event bracketing for per-kernel timing
-esdg_status launch(esdg_problem* P, int kind, const void* fn, dim3 grid, dim3 block, void** args) {
-  if (!fn) return fail(P, ESDG_EINVAL, "no kernel instantiated for this configuration");
+esdg_status launch_kernel(const Launcher& L, int kind, const void* fn, dim3 grid, dim3 block, void** args) {
+  if (!fn) return report(L.err, ESDG_EINVAL, "no kernel instantiated for this configuration");
   TimedLaunch tl{kind, nullptr, nullptr};
-  if (P->timing) {
-    HIPCHECK(P, hipEventCreate(&tl.start));
-    HIPCHECK(P, hipEventCreate(&tl.stop));
-    HIPCHECK(P, hipEventRecord(tl.start, P->stream));
+  if (L.timed) {
+    ESDG_HIP(L.err, hipEventCreate(&tl.start));
+    ESDG_HIP(L.err, hipEventCreate(&tl.stop));
+    ESDG_HIP(L.err, hipEventRecord(tl.start, L.stream));
   }
-  HIPCHECK(P, hipLaunchKernel(fn, grid, block, args, 0, P->stream));
-  if (P->timing) {
-    HIPCHECK(P, hipEventRecord(tl.stop, P->stream));
-    P->launches.push_back(tl);
+  ESDG_HIP(L.err, hipLaunchKernel(fn, grid, block, args, 0, L.stream));
+  if (L.timed) {
+    ESDG_HIP(L.err, hipEventRecord(tl.stop, L.stream));
+    L.timed->push_back(tl);
   }
   return ESDG_OK;
 }
 
-#define TRY(x)                        \
-  do {                                \
-    esdg_status s_ = (x);             \
-    if (s_ != ESDG_OK) return s_;     \
-  } while (0)
+// ---- tile-variant table (autotuner results), keyed by the kernel parameters
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int>, int> g_tune;
+int g_tune_version = 0;
 
-// One fused stage launch: right-hand side of `uin` (surface and volume
-// terms) and, for the RK modes, the stage update into out / R.
-unsigned long long* lam_slot(esdg_problem* P, int k) { return P->LAM + k * kLamSlots; }
+std::tuple<int, int, int, int, int> tune_key(const esdg_problem* P) {
+  return std::make_tuple(P->dim, P->N, P->vf, P->mesh, P->prec);
+}
+}  // namespace
 
-// Time stepping of one stage launch: fixed dt, or CFL from the lam slots.
-struct StepCtl {
-  double dt_fixed = 0.0, cfl = 0.0;
-  int lam_cur = 0, lam_update = 0, t_mode = 0;
-};
+int tile_variant_of(const esdg_problem* P) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  auto it = g_tune.find(tune_key(P));
+  return it == g_tune.end() ? 0 : it->second;
+}
 
-enum { BUF_U = 0, BUF_Y = 1, BUF_Y2 = 2, BUF_R = 3 };
+int tile_table_version() {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  return g_tune_version;
+}
 
-// the stage-kernel instantiation and tile size for P's parameters
+static void set_tile_variant(const esdg_problem* P, int v) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  int& cur = g_tune[tune_key(P)];
+  if (cur != v) ++g_tune_version;
+  cur = v;
+}
+
 VolKernel pick_stage_kernel(const esdg_problem* P) {
-  return P->dim == 2 ? stage_kernel_2d(P->prec, P->N, P->vf, P->mesh) : stage_kernel_3d(P->prec, P->N, P->vf, P->mesh);
-}
-
-// One fused stage launch over the tiles of `nprob` problems sharing P's
-// parameters (descriptors `probs` in device memory): right-hand side of
-// buf[in_idx] (surface and volume terms) and, for the RK modes, the stage
-// update into buf[out_idx] / R; RHS mode may write to out_ext instead.
-template <typename Real>
-esdg_status run_stage_on(esdg_problem* P, const void* probs, int nprob, int64_t tiles, int in_idx, int out_idx,
-                         void* out_ext, int mode, double coef_b, double coef_a, const StepCtl& ctl) {
-  StageArgs<Real> a{};
-  a.probs = (const ProbDesc<Real>*)probs;
-  a.nprob = nprob;
-  a.out_ext = (Real*)out_ext;
-  a.in_idx = in_idx;
-  a.out_idx = out_idx;
-  a.mode = mode;
-  a.surf = P->sf;
-  a.coef_b = (Real)coef_b;
-  a.coef_a = (Real)coef_a;
-  a.dt_fixed = ctl.dt_fixed;
-  a.cfl = ctl.cfl;
-  a.lam_cur = ctl.lam_cur;
-  a.lam_update = ctl.lam_update;
-  a.t_mode = ctl.t_mode;
-  a.ops = stage_ops<Real>(P);
-  VolKernel k = pick_stage_kernel(P);
-  if (!k.fn) return fail(P, ESDG_EINVAL, "no stage kernel for dim=%d p=%d flux=%d", P->dim, P->p, P->vf);
-  void* args[] = {&a};
-  return launch(P, ESDG_KERNEL_STAGE, k.fn, dim3((unsigned)tiles), dim3(k.threads), args);
+  return stage_kernel_for(P->prec, P->dim, P->N, P->vf, P->mesh, tile_variant_of(P));
 }
 
 template <typename Real>
-esdg_status run_stage(esdg_problem* P, int in_idx, int out_idx, void* out_ext, int mode, double coef_b,
-                      double coef_a, const StepCtl& ctl = StepCtl()) {
-  const VolKernel k = pick_stage_kernel(P);
-  if (!k.fn) return fail(P, ESDG_EINVAL, "no stage kernel for dim=%d p=%d flux=%d", P->dim, P->p, P->vf);
-  return run_stage_on<Real>(P, P->DESC, 1, (P->E + k.epb - 1) / k.epb, in_idx, out_idx, out_ext, mode, coef_b,
-                            coef_a, ctl);
-}
-
-// FP64 reduction of op over the state (and DU for the entropy rate); the
-// result lands in SCAL[2..] (dt for RED_MAXLAMBDA, whose lam_max also goes
-// to `slot` if given).
-template <typename Real>
-esdg_status run_reduce(esdg_problem* P, int op, double cfl, unsigned long long* slot = nullptr) {
+static esdg_status reduce_t(esdg_problem* P, const Launcher& L, int op, double cfl, unsigned long long* slot) {
   RedArgs<Real> a{};
   a.u = (const Real*)P->U;
   a.du = (const Real*)P->DU;
@@ -218,40 +112,86 @@ esdg_status run_reduce(esdg_problem* P, int op, double cfl, unsigned long long* 
   a.gamma = P->gamma;
   int64_t per_block = P->red_per_block;
   void* args[] = {&a, &per_block};
-  TRY(launch(P, ESDG_KERNEL_REDUCE, reduce_partial_for(P->prec, P->dim, P->mesh, op), dim3(P->red_blocks),
-             dim3(kRedThreads), args));
+  ESDG_TRY(launch_kernel(L, ESDG_KERNEL_REDUCE, reduce_partial_for(P->prec, P->dim, P->mesh, op),
+                         dim3(P->red_blocks), dim3(kRedThreads), args));
   int K = op == RED_TOTALS ? P->nv : 1;
   double* out = P->SCAL + 2;
   int blocks = P->red_blocks, N = P->N;
   void* args2[] = {&P->PARTIAL, &blocks, &K, &out, &cfl, &N, &slot};
-  return launch(P, ESDG_KERNEL_REDUCE, reduce_final_for(op), dim3(1), dim3(kRedThreads), args2);
+  return launch_kernel(L, ESDG_KERNEL_REDUCE, reduce_final_for(op), dim3(1), dim3(kRedThreads), args2);
 }
+
+esdg_status run_reduce(esdg_problem* P, const Launcher& L, int op, double cfl, unsigned long long* slot) {
+  return P->prec == PREC_FP32 ? reduce_t<float>(P, L, op, cfl, slot) : reduce_t<double>(P, L, op, cfl, slot);
+}
+
+esdg_status convert_state(esdg_problem* P, const Launcher& L, const void* src, void* dst, int to_fp64) {
+  int64_t n = (int64_t)state_count(P);
+  void* args[] = {(void*)&src, &dst, &n};
+  return launch_kernel(L, -1, convert_kernel_for(to_fp64), dim3((unsigned)((n + 255) / 256)), dim3(256), args);
+}
+
+namespace {
+
+__global__ void __launch_bounds__(64) copy_parity_kernel(double* time, unsigned long long* lam, int from) {
+  const int t = threadIdx.x;
+  lam[(1 - from) * kLamSlots + t] = lam[from * kLamSlots + t];
+  if (t == 0) time[1 - from] = time[from];
+}
+
+__global__ void __launch_bounds__(64) set_scalar_kernel(double* dst, double v) {
+  if (threadIdx.x == 0) dst[0] = v;
+}
+
+}  // namespace
+
+esdg_status copy_parity(esdg_problem* P, const Launcher& L, int from) {
+  double* t = P->SCAL;
+  unsigned long long* lam = P->LAM;
+  void* args[] = {&t, &lam, &from};
+  return launch_kernel(L, -1, (const void*)&copy_parity_kernel, dim3(1), dim3(kLamSlots), args);
+}
+
+}  // namespace esdg
+
+namespace {
 
 // dispatch on internal precision
 #define BY_PREC(P, fn, ...) ((P)->prec == PREC_FP32 ? fn<float>(__VA_ARGS__) : fn<double>(__VA_ARGS__))
 
-esdg_status rhs_into(esdg_problem* P, void* out) {
-  return BY_PREC(P, run_stage, P, BUF_U, BUF_U, out, MODE_RHS, 0.0, 0.0);
+template <typename Real>
+esdg_status run_stage(esdg_problem* P, int in_idx, int out_idx, void* out_ext, int mode, double coef_b,
+                      double coef_a, const StepCtl& ctl = StepCtl()) {
+  const VolKernel k = pick_stage_kernel(P);
+  return run_stage_on<Real>(P, launcher_of(P), k, P->DESC, nullptr, (P->E + k.epb - 1) / std::max(1, k.epb), in_idx,
+                            out_idx, out_ext, mode, coef_b, coef_a, ctl);
 }
 
-// elementwise precision conversion of n values on the handle's stream
+esdg_status rhs_into(esdg_problem* P, void* out) {
+  return BY_PREC(P, run_stage, P, BUF_U, BUF_DU, out, MODE_RHS, 0.0, 0.0);
+}
+
 esdg_status convert(esdg_problem* P, const void* src, void* dst, int to_fp64) {
-  int64_t n = (int64_t)state_count(P);
-  void* args[] = {(void*)&src, &dst, &n};
-  return launch(P, -1, convert_kernel_for(to_fp64), dim3((unsigned)((n + 255) / 256)), dim3(256), args);
+  return convert_state(P, launcher_of(P), src, dst, to_fp64);
 }
 
 esdg_status check_handle(esdg_problem* P, bool need_state) {
   if (!P) return fail(nullptr, ESDG_EINVAL, "NULL problem handle");
   if (need_state && !P->have_state) return fail(P, ESDG_ESTATE, "no state set (call esdg_set_state first)");
-  HIPCHECK(P, hipSetDevice(P->device));
+  ESDG_HIP(&P->err, hipSetDevice(P->device));
   return ESDG_OK;
 }
 
 esdg_status read_scalars(esdg_problem* P, int first, int count, double* out) {
-  HIPCHECK(P, hipMemcpyAsync(out, P->SCAL + first, sizeof(double) * count, hipMemcpyDeviceToHost, P->stream));
-  HIPCHECK(P, hipStreamSynchronize(P->stream));
+  ESDG_HIP(&P->err, hipMemcpyAsync(out, P->SCAL + first, sizeof(double) * count, hipMemcpyDeviceToHost, P->stream));
+  ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
   return ESDG_OK;
+}
+
+esdg_status set_time(esdg_problem* P, double t) {
+  double* dst = P->SCAL + P->par;
+  void* args[] = {&dst, &t};
+  return launch_kernel(launcher_of(P), -1, (const void*)&set_scalar_kernel, dim3(1), dim3(64), args);
 }
 
 void free_buffers(esdg_problem* P) {
@@ -293,9 +233,8 @@ esdg_status esdg_operators(int32_t p, double* x, double* w, double* D, double* D
   return ESDG_OK;
 }
 
-esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
-  if (!d || !out) return fail(nullptr, ESDG_EINVAL, "NULL descriptor or output pointer");
-  *out = nullptr;
+// validation of a mesh descriptor shared by esdg_init_mesh and esdg_footprint
+static esdg_status check_desc(const esdg_mesh_desc* d) {
   if (d->dim != 2 && d->dim != 3) return fail(nullptr, ESDG_EINVAL, "dim must be 2 or 3");
   if (d->p < 1 || d->p > ESDG_PMAX) return fail(nullptr, ESDG_EINVAL, "p must be in [1, %d]", ESDG_PMAX);
   if (!(d->gamma > 1.0)) return fail(nullptr, ESDG_EINVAL, "gamma must be > 1");
@@ -311,6 +250,43 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
     ne *= d->n[j];
   }
   if (ne > (int64_t)1 << 30) return fail(nullptr, ESDG_EINVAL, "at most 2^30 elements");
+  return ESDG_OK;
+}
+
+// reduction geometry: fixed per problem size, so results are reproducible
+static void reduction_blocks(int64_t total, int* blocks_out, int64_t* per_block) {
+  int64_t blocks = (total + kRedThreads - 1) / kRedThreads;
+  if (blocks > 2048) blocks = 2048;
+  *blocks_out = (int)blocks;
+  *per_block = ((total + blocks - 1) / blocks + kRedThreads - 1) / kRedThreads * kRedThreads;
+}
+
+esdg_status esdg_footprint(const esdg_mesh_desc* d, int64_t* bytes) {
+  if (!d || !bytes) return fail(nullptr, ESDG_EINVAL, "NULL descriptor or output pointer");
+  ESDG_TRY(check_desc(d));
+  int64_t E = 1, nn = 1, nf = 1;
+  for (int j = 0; j < d->dim; ++j) {
+    E *= d->n[j];
+    nn *= d->p + 1;
+  }
+  nf = nn / (d->p + 1);
+  const int64_t rs = d->precision == ESDG_FP32 ? 4 : 8;
+  const int64_t ns = E * (d->dim + 2) * nn;
+  int64_t b = 5 * ns * rs;
+  if (d->precision == ESDG_FP32) b += ns * 8;
+  if (d->warp != 0.0 || d->coords) b += (E * (d->dim * d->dim + 1) * nn + (int64_t)d->dim * E * d->dim * nf) * rs;
+  int blocks;
+  int64_t per;
+  reduction_blocks(E * nn, &blocks, &per);
+  b += 8 * 8 * (int64_t)blocks + 16 * 8 + 2 * kLamSlots * 8 + 4 + (int64_t)sizeof(ProbDesc<double>);
+  *bytes = b;
+  return ESDG_OK;
+}
+
+esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
+  if (!d || !out) return fail(nullptr, ESDG_EINVAL, "NULL descriptor or output pointer");
+  *out = nullptr;
+  ESDG_TRY(check_desc(d));
 
   esdg_problem* P = new esdg_problem();
   P->spec.dim = d->dim;
@@ -350,12 +326,7 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
     delete P;
     return st;
   }
-  // reduction geometry: fixed per problem size, so results are reproducible
-  const int64_t total = P->E * P->nn;
-  int64_t blocks = (total + kRedThreads - 1) / kRedThreads;
-  if (blocks > 2048) blocks = 2048;
-  P->red_blocks = (int)blocks;
-  P->red_per_block = ((total + blocks - 1) / blocks + kRedThreads - 1) / kRedThreads * kRedThreads;
+  reduction_blocks(P->E * P->nn, &P->red_blocks, &P->red_per_block);
 
   const size_t ns = state_count(P) * P->rsize;
   struct {
@@ -423,10 +394,10 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
     hipError_t e2 = hipErrorOutOfMemory;
     if (e1 == hipSuccess) {
       if (P->prec == PREC_FP32) {
-        ProbDesc<float> d = prob_desc<float>(P, 0);
+        ProbDesc<float> d = prob_desc<float>(P, 0, INFINITY);
         e2 = hipMemcpy(P->DESC, &d, db, hipMemcpyHostToDevice);
       } else {
-        ProbDesc<double> d = prob_desc<double>(P, 0);
+        ProbDesc<double> d = prob_desc<double>(P, 0, INFINITY);
         e2 = hipMemcpy(P->DESC, &d, db, hipMemcpyHostToDevice);
       }
     }
@@ -475,131 +446,211 @@ esdg_status esdg_get_coords(const esdg_problem* P, double* x) {
 }
 
 esdg_status esdg_set_state(esdg_problem* P, const double* u, int32_t where) {
-  TRY(check_handle(P, false));
+  ESDG_TRY(check_handle(P, false));
   if (!u) return fail(P, ESDG_EINVAL, "NULL state");
   const size_t bytes = state_count(P) * sizeof(double);
   if (P->prec == PREC_FP32) {
     const void* src = u;
     if (where != ESDG_DEVICE) {
-      HIPCHECK(P, hipMemcpyAsync(P->STAGE64, u, bytes, hipMemcpyHostToDevice, P->stream));
+      ESDG_HIP(&P->err, hipMemcpyAsync(P->STAGE64, u, bytes, hipMemcpyHostToDevice, P->stream));
       src = P->STAGE64;
     }
-    TRY(convert(P, src, P->U, 0));
+    ESDG_TRY(convert(P, src, P->U, 0));
   } else {
-    HIPCHECK(P, hipMemcpyAsync(P->U, u, bytes, where == ESDG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+    ESDG_HIP(&P->err, hipMemcpyAsync(P->U, u, bytes, where == ESDG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                                P->stream));
   }
-  if (where != ESDG_DEVICE) HIPCHECK(P, hipStreamSynchronize(P->stream));
+  if (where != ESDG_DEVICE) ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
   P->have_state = true;
   P->lam_valid = false;
   return ESDG_OK;
 }
 
 esdg_status esdg_get_state(esdg_problem* P, double* u, int32_t where) {
-  TRY(check_handle(P, true));
+  ESDG_TRY(check_handle(P, true));
   if (!u) return fail(P, ESDG_EINVAL, "NULL output");
   const size_t bytes = state_count(P) * sizeof(double);
   if (P->prec == PREC_FP32) {
-    TRY(convert(P, P->U, where == ESDG_DEVICE ? (void*)u : (void*)P->STAGE64, 1));
-    if (where != ESDG_DEVICE) HIPCHECK(P, hipMemcpyAsync(u, P->STAGE64, bytes, hipMemcpyDeviceToHost, P->stream));
+    ESDG_TRY(convert(P, P->U, where == ESDG_DEVICE ? (void*)u : (void*)P->STAGE64, 1));
+    if (where != ESDG_DEVICE) ESDG_HIP(&P->err, hipMemcpyAsync(u, P->STAGE64, bytes, hipMemcpyDeviceToHost, P->stream));
   } else {
-    HIPCHECK(P, hipMemcpyAsync(u, P->U, bytes, where == ESDG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+    ESDG_HIP(&P->err, hipMemcpyAsync(u, P->U, bytes, where == ESDG_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                                P->stream));
   }
-  if (where != ESDG_DEVICE) HIPCHECK(P, hipStreamSynchronize(P->stream));
+  if (where != ESDG_DEVICE) ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
   return ESDG_OK;
 }
 
 esdg_status esdg_rhs(esdg_problem* P, double* du, int32_t where) {
-  TRY(check_handle(P, true));
+  ESDG_TRY(check_handle(P, true));
   if (!du) return fail(P, ESDG_EINVAL, "NULL output");
   const bool direct = where == ESDG_DEVICE;
   const size_t bytes = state_count(P) * sizeof(double);
   if (P->prec == PREC_FP32) {
-    TRY(rhs_into(P, P->DU));
-    TRY(convert(P, P->DU, direct ? (void*)du : (void*)P->STAGE64, 1));
-    if (!direct) HIPCHECK(P, hipMemcpyAsync(du, P->STAGE64, bytes, hipMemcpyDeviceToHost, P->stream));
+    ESDG_TRY(rhs_into(P, P->DU));
+    ESDG_TRY(convert(P, P->DU, direct ? (void*)du : (void*)P->STAGE64, 1));
+    if (!direct) ESDG_HIP(&P->err, hipMemcpyAsync(du, P->STAGE64, bytes, hipMemcpyDeviceToHost, P->stream));
   } else {
-    TRY(rhs_into(P, direct ? (void*)du : P->DU));
-    if (!direct) HIPCHECK(P, hipMemcpyAsync(du, P->DU, bytes, hipMemcpyDeviceToHost, P->stream));
+    ESDG_TRY(rhs_into(P, direct ? (void*)du : P->DU));
+    if (!direct) ESDG_HIP(&P->err, hipMemcpyAsync(du, P->DU, bytes, hipMemcpyDeviceToHost, P->stream));
   }
-  if (!direct) HIPCHECK(P, hipStreamSynchronize(P->stream));
+  if (!direct) ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
   return ESDG_OK;
 }
 
 esdg_status esdg_step(esdg_problem* P, double dt, int32_t nsteps, double cfl, double* t_inout) {
-  TRY(check_handle(P, true));
+  ESDG_TRY(check_handle(P, true));
   if (nsteps < 0) return fail(P, ESDG_EINVAL, "nsteps must be >= 0");
   const bool use_cfl = !(dt > 0.0);
   if (use_cfl && !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "dt <= 0 needs cfl > 0");
-  if (nsteps == 0) return ESDG_OK;
-  // classical RK4 in low-storage form: U (state), R (accumulator) and the
-  // stage state, alternating between Y and Y2 (stage inputs are read across
-  // element faces, so a stage never writes its own input)
-  StepCtl ctl;
-  if (!use_cfl) {
-    ctl.dt_fixed = dt;
-  } else {
-    ctl.cfl = cfl;
-    // the CFL value of the start state comes from the previous CFL step's
-    // last stage; otherwise from one reduction
-    if (!P->lam_valid) TRY(BY_PREC(P, run_reduce, P, RED_MAXLAMBDA, cfl, lam_slot(P, P->lam_cur)));
-  }
-  for (int s = 0; s < nsteps; ++s) {
-    ctl.lam_cur = P->lam_cur;
-    StepCtl first = ctl, last = ctl;
-    first.t_mode = use_cfl ? (s == 0 ? 2 : 1) : 0;
-    last.lam_update = use_cfl ? 1 : 0;
-    TRY(BY_PREC(P, run_stage, P, BUF_U, BUF_Y, nullptr, MODE_RK_FIRST, 1.0 / 6.0, 0.5, first));
-    TRY(BY_PREC(P, run_stage, P, BUF_Y, BUF_Y2, nullptr, MODE_RK_MID, 1.0 / 3.0, 0.5, ctl));
-    TRY(BY_PREC(P, run_stage, P, BUF_Y2, BUF_Y, nullptr, MODE_RK_MID, 1.0 / 3.0, 1.0, ctl));
-    TRY(BY_PREC(P, run_stage, P, BUF_Y, BUF_U, nullptr, MODE_RK_LAST, 1.0 / 6.0, 0.0, last));
-    if (use_cfl) P->lam_cur = 1 - P->lam_cur;
-  }
-  P->lam_valid = use_cfl;
-  if (t_inout) {
-    if (use_cfl) {
-      double tsum = 0.0;
-      TRY(read_scalars(P, 1, 1, &tsum));
-      *t_inout += tsum;
+  if (t_inout) ESDG_TRY(set_time(P, *t_inout));
+  if (nsteps > 0) {
+    // classical RK4 in low-storage form: U (state), R (accumulator) and the
+    // stage state, alternating between Y and Y2 (stage inputs are read across
+    // element faces, so a stage never writes its own input)
+    StepCtl ctl;
+    if (!use_cfl) {
+      ctl.dt_fixed = dt;
     } else {
-      *t_inout += dt * nsteps;
+      ctl.cfl = cfl;
+      // the CFL value of the start state comes from the previous CFL step's
+      // last stage; otherwise from one reduction
+      if (!P->lam_valid) ESDG_TRY(run_reduce(P, launcher_of(P), RED_MAXLAMBDA, cfl, lam_slot(P, P->par)));
     }
+    for (int s = 0; s < nsteps; ++s) {
+      ctl.par = P->par;
+      StepCtl last = ctl;
+      last.lam_update = use_cfl ? 1 : 0;
+      ESDG_TRY(BY_PREC(P, run_stage, P, BUF_U, BUF_Y, nullptr, MODE_RK_FIRST, 1.0 / 6.0, 0.5, ctl));
+      ESDG_TRY(BY_PREC(P, run_stage, P, BUF_Y, BUF_Y2, nullptr, MODE_RK_MID, 1.0 / 3.0, 0.5, ctl));
+      ESDG_TRY(BY_PREC(P, run_stage, P, BUF_Y2, BUF_Y, nullptr, MODE_RK_MID, 1.0 / 3.0, 1.0, ctl));
+      ESDG_TRY(BY_PREC(P, run_stage, P, BUF_Y, BUF_U, nullptr, MODE_RK_LAST, 1.0 / 6.0, 0.0, last));
+      P->par = 1 - P->par;
+    }
+    P->lam_valid = use_cfl;
   }
+  if (t_inout) ESDG_TRY(read_scalars(P, P->par, 1, t_inout));
   return ESDG_OK;
 }
 
+esdg_status esdg_set_time(esdg_problem* P, double t) {
+  ESDG_TRY(check_handle(P, false));
+  return set_time(P, t);
+}
+
+esdg_status esdg_get_time(esdg_problem* P, double* t) {
+  ESDG_TRY(check_handle(P, false));
+  if (!t) return fail(P, ESDG_EINVAL, "NULL output");
+  return read_scalars(P, P->par, 1, t);
+}
+
 esdg_status esdg_entropy_rate(esdg_problem* P, double* dSdt) {
-  TRY(check_handle(P, true));
+  ESDG_TRY(check_handle(P, true));
   if (!dSdt) return fail(P, ESDG_EINVAL, "NULL output");
-  TRY(rhs_into(P, P->DU));
-  TRY(BY_PREC(P, run_reduce, P, RED_ENTROPY, 0.0));
+  ESDG_TRY(rhs_into(P, P->DU));
+  ESDG_TRY(run_reduce(P, launcher_of(P), RED_ENTROPY, 0.0, nullptr));
   return read_scalars(P, 2, 1, dSdt);
 }
 
 esdg_status esdg_totals(esdg_problem* P, double* totals) {
-  TRY(check_handle(P, true));
+  ESDG_TRY(check_handle(P, true));
   if (!totals) return fail(P, ESDG_EINVAL, "NULL output");
-  TRY(BY_PREC(P, run_reduce, P, RED_TOTALS, 0.0));
+  ESDG_TRY(run_reduce(P, launcher_of(P), RED_TOTALS, 0.0, nullptr));
   return read_scalars(P, 2, P->nv, totals);
 }
 
 esdg_status esdg_max_dt(esdg_problem* P, double cfl, double* dt) {
-  TRY(check_handle(P, true));
+  ESDG_TRY(check_handle(P, true));
   if (!dt || !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "need cfl > 0 and an output pointer");
-  TRY(BY_PREC(P, run_reduce, P, RED_MAXLAMBDA, cfl));
+  ESDG_TRY(run_reduce(P, launcher_of(P), RED_MAXLAMBDA, cfl, nullptr));
   return read_scalars(P, 2, 1, dt);
 }
 
 esdg_status esdg_sync(esdg_problem* P) {
-  TRY(check_handle(P, false));
-  HIPCHECK(P, hipStreamSynchronize(P->stream));
+  ESDG_TRY(check_handle(P, false));
+  ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
   int flag = 0;
-  HIPCHECK(P, hipMemcpy(&flag, P->FLAG, sizeof(int), hipMemcpyDeviceToHost));
+  ESDG_HIP(&P->err, hipMemcpy(&flag, P->FLAG, sizeof(int), hipMemcpyDeviceToHost));
   if (flag) {
-    HIPCHECK(P, hipMemset(P->FLAG, 0, sizeof(int)));
+    ESDG_HIP(&P->err, hipMemset(P->FLAG, 0, sizeof(int)));
     return fail(P, ESDG_ENONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or non-finite) met by a kernel");
   }
+  return ESDG_OK;
+}
+
+esdg_status esdg_get_tile_variant(const esdg_problem* P, int32_t* variant, int32_t* elems_per_block) {
+  if (!P) return fail(nullptr, ESDG_EINVAL, "NULL problem handle");
+  const int v = tile_variant_of(P);
+  if (variant) *variant = v;
+  if (elems_per_block) *elems_per_block = pick_stage_kernel(P).epb;
+  return ESDG_OK;
+}
+
+esdg_status esdg_set_tile_variant(esdg_problem* P, int32_t variant) {
+  if (!P) return fail(nullptr, ESDG_EINVAL, "NULL problem handle");
+  if (!stage_kernel_for(P->prec, P->dim, P->N, P->vf, P->mesh, variant).fn)
+    return fail(P, ESDG_EINVAL, "tile variant %d does not exist for dim=%d p=%d", variant, P->dim, P->p);
+  set_tile_variant(P, variant);
+  return ESDG_OK;
+}
+
+esdg_status esdg_autotune(esdg_problem* P, int32_t reps, int32_t* best, double* us_per_variant) {
+  ESDG_TRY(check_handle(P, true));
+  if (reps < 1) return fail(P, ESDG_EINVAL, "reps must be >= 1");
+  // every variant computes the right-hand side of the current state into DU
+  // (the state is not modified); variants with the same tile size share one
+  // measurement
+  double us[ESDG_TILE_VARIANTS];
+  int epb[ESDG_TILE_VARIANTS];
+  int pick = -1;
+  Launcher L = launcher_of(P);
+  L.timed = nullptr;
+  hipEvent_t e0, e1;
+  ESDG_HIP(&P->err, hipEventCreate(&e0));
+  ESDG_HIP(&P->err, hipEventCreate(&e1));
+  esdg_status st = ESDG_OK;
+  for (int v = 0; v < ESDG_TILE_VARIANTS && st == ESDG_OK; ++v) {
+    us[v] = -1.0;
+    epb[v] = 0;
+    const VolKernel k = stage_kernel_for(P->prec, P->dim, P->N, P->vf, P->mesh, v);
+    if (!k.fn) continue;
+    epb[v] = k.epb;
+    int same = -1;
+    for (int w = 0; w < v; ++w)
+      if (epb[w] == k.epb) same = w;
+    if (same >= 0) {
+      us[v] = us[same];
+      continue;
+    }
+    const int64_t tiles = (P->E + k.epb - 1) / k.epb;
+    auto one = [&]() {
+      return P->prec == PREC_FP32
+                 ? run_stage_on<float>(P, L, k, P->DESC, nullptr, tiles, BUF_U, BUF_DU, nullptr, MODE_RHS, 0, 0, StepCtl())
+                 : run_stage_on<double>(P, L, k, P->DESC, nullptr, tiles, BUF_U, BUF_DU, nullptr, MODE_RHS, 0, 0,
+                                        StepCtl());
+    };
+    for (int r = 0; r < 2 && st == ESDG_OK; ++r) st = one();
+    if (st != ESDG_OK) break;
+    if (hipEventRecord(e0, P->stream) != hipSuccess) st = fail(P, ESDG_EDEVICE, "hipEventRecord failed");
+    for (int r = 0; r < reps && st == ESDG_OK; ++r) st = one();
+    if (st != ESDG_OK) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, P->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(P, ESDG_EDEVICE, "event timing failed");
+      break;
+    }
+    us[v] = 1000.0 * ms / reps;
+    if (pick < 0 || us[v] < us[pick]) pick = v;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ESDG_TRY(st);
+  if (pick < 0) return fail(P, ESDG_EINVAL, "no stage kernel for dim=%d p=%d", P->dim, P->p);
+  set_tile_variant(P, pick);
+  if (best) *best = pick;
+  if (us_per_variant)
+    for (int v = 0; v < ESDG_TILE_VARIANTS; ++v) us_per_variant[v] = us[v];
   return ESDG_OK;
 }
 
@@ -610,14 +661,14 @@ esdg_status esdg_timing_enable(esdg_problem* P, int32_t enable) {
 }
 
 esdg_status esdg_timing_read(esdg_problem* P, int32_t kernel, double* total_ms, int64_t* launches) {
-  TRY(check_handle(P, false));
+  ESDG_TRY(check_handle(P, false));
   double sum = 0.0;
   int64_t cnt = 0;
   for (auto& t : P->launches) {
     if (t.kind != kernel) continue;
-    HIPCHECK(P, hipEventSynchronize(t.stop));
+    ESDG_HIP(&P->err, hipEventSynchronize(t.stop));
     float ms = 0.0f;
-    HIPCHECK(P, hipEventElapsedTime(&ms, t.start, t.stop));
+    ESDG_HIP(&P->err, hipEventElapsedTime(&ms, t.start, t.stop));
     sum += ms;
     ++cnt;
   }
@@ -627,8 +678,8 @@ esdg_status esdg_timing_read(esdg_problem* P, int32_t kernel, double* total_ms, 
 }
 
 esdg_status esdg_timing_reset(esdg_problem* P) {
-  TRY(check_handle(P, false));
-  HIPCHECK(P, hipStreamSynchronize(P->stream));
+  ESDG_TRY(check_handle(P, false));
+  ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
   for (auto& t : P->launches) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);

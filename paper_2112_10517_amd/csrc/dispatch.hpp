@@ -11,10 +11,17 @@ struct VolKernel {
   int threads = 0;           // lanes per workgroup
 };
 
-VolKernel stage_kernel_2d(int prec, int N, int vf, int mesh);
-VolKernel stage_kernel_3d(int prec, int N, int vf, int mesh);
+// number of tile variants of the 3D stage kernel (2D has one)
+constexpr int kTileVariants = 3;
+
+// stage kernel for the given parameters and tile variant (fn == NULL if none)
+VolKernel stage_kernel_for(int prec, int dim, int N, int vf, int mesh, int variant);
+VolKernel stage_kernel_2d_f64(int N, int vf, int mesh);
 VolKernel stage_kernel_2d_f32(int N, int vf, int mesh);
-VolKernel stage_kernel_3d_f32(int N, int vf, int mesh);
+VolKernel stage_kernel_3d_f64(int N, int vf, int mesh, int variant);
+VolKernel stage_kernel_3d_f32(int N, int vf, int mesh, int variant);
+VolKernel stage_kernel_3d_f64_tuned(int N, int vf, int mesh, int variant);
+VolKernel stage_kernel_3d_f32_tuned(int N, int vf, int mesh, int variant);
 const void* reduce_partial_for(int prec, int dim, int mesh, int op);
 const void* reduce_final_for(int op);
 const void* convert_kernel_for(int to_fp64);  // elementwise precision casts

@@ -36,6 +36,16 @@ __global__ void __launch_bounds__(256) to_fp32_kernel(const double* src, float* 
 
 }  // namespace
 
+VolKernel stage_kernel_for(int prec, int dim, int N, int vf, int mesh, int variant) {
+  if (variant < 0 || variant >= kTileVariants) return VolKernel{};
+  if (dim == 2) {
+    if (variant != 0) return VolKernel{};
+    return prec == PREC_FP32 ? stage_kernel_2d_f32(N, vf, mesh) : stage_kernel_2d_f64(N, vf, mesh);
+  }
+  if (dim == 3) return prec == PREC_FP32 ? stage_kernel_3d_f32(N, vf, mesh, variant) : stage_kernel_3d_f64(N, vf, mesh, variant);
+  return VolKernel{};
+}
+
 const void* reduce_partial_for(int prec, int dim, int mesh, int op) {
   if (prec == PREC_FP32) return dim == 2 ? reduce_pick<2, float>(mesh, op) : reduce_pick<3, float>(mesh, op);
   return dim == 2 ? reduce_pick<2, double>(mesh, op) : reduce_pick<3, double>(mesh, op);

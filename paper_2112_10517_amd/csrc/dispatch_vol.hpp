@@ -1,5 +1,6 @@
-// Stage-kernel instantiation table for one dimension (included by the
-// per-dimension translation units so that they compile in parallel).
+// Stage-kernel instantiation table for one dimension, precision and tile
+// variant (included by the per-dimension translation units so that they
+// compile in parallel).
 #pragma once
 
 #include "dispatch.hpp"
@@ -7,33 +8,41 @@
 
 namespace esdg {
 
-template <int DIM, typename Real, int N>
-VolKernel vol_pick_n(int vf, int mesh) {
+template <int DIM, typename Real, int N, int VF, int MESH, int V>
+VolKernel vol_kernel() {
+  constexpr int EPB = tile_epb(DIM, N, PrimCount<VF, DIM>::value, (int)sizeof(Real), V);
+  using T = Tile<DIM, N, EPB>;
   VolKernel k;
-  k.epb = Tile<DIM, N>::EPB;
-  k.threads = Tile<DIM, N>::THREADS;
-  if (mesh == MESH_AFFINE) {
-    if (vf == VF_RANOCHA) k.fn = (const void*)&stage_kernel<DIM, N, VF_RANOCHA, MESH_AFFINE, Real>;
-    else if (vf == VF_SHIMA) k.fn = (const void*)&stage_kernel<DIM, N, VF_SHIMA, MESH_AFFINE, Real>;
-    else if (vf == VF_CENTRAL) k.fn = (const void*)&stage_kernel<DIM, N, VF_CENTRAL, MESH_AFFINE, Real>;
-  } else {
-    if (vf == VF_RANOCHA) k.fn = (const void*)&stage_kernel<DIM, N, VF_RANOCHA, MESH_CURVED, Real>;
-    else if (vf == VF_SHIMA) k.fn = (const void*)&stage_kernel<DIM, N, VF_SHIMA, MESH_CURVED, Real>;
-    else if (vf == VF_CENTRAL) k.fn = (const void*)&stage_kernel<DIM, N, VF_CENTRAL, MESH_CURVED, Real>;
-  }
+  k.fn = (const void*)&stage_kernel<DIM, N, VF, MESH, Real, EPB>;
+  k.epb = T::EPB;
+  k.threads = T::THREADS;
   return k;
 }
 
-template <int DIM, typename Real>
+template <int DIM, typename Real, int V, int N>
+VolKernel vol_pick_n(int vf, int mesh) {
+  if (mesh == MESH_AFFINE) {
+    if (vf == VF_RANOCHA) return vol_kernel<DIM, Real, N, VF_RANOCHA, MESH_AFFINE, V>();
+    if (vf == VF_SHIMA) return vol_kernel<DIM, Real, N, VF_SHIMA, MESH_AFFINE, V>();
+    if (vf == VF_CENTRAL) return vol_kernel<DIM, Real, N, VF_CENTRAL, MESH_AFFINE, V>();
+  } else {
+    if (vf == VF_RANOCHA) return vol_kernel<DIM, Real, N, VF_RANOCHA, MESH_CURVED, V>();
+    if (vf == VF_SHIMA) return vol_kernel<DIM, Real, N, VF_SHIMA, MESH_CURVED, V>();
+    if (vf == VF_CENTRAL) return vol_kernel<DIM, Real, N, VF_CENTRAL, MESH_CURVED, V>();
+  }
+  return VolKernel{};
+}
+
+template <int DIM, typename Real, int V>
 VolKernel vol_pick(int N, int vf, int mesh) {
   switch (N) {
-    case 2: return vol_pick_n<DIM, Real, 2>(vf, mesh);
-    case 3: return vol_pick_n<DIM, Real, 3>(vf, mesh);
-    case 4: return vol_pick_n<DIM, Real, 4>(vf, mesh);
-    case 5: return vol_pick_n<DIM, Real, 5>(vf, mesh);
-    case 6: return vol_pick_n<DIM, Real, 6>(vf, mesh);
-    case 7: return vol_pick_n<DIM, Real, 7>(vf, mesh);
-    case 8: return vol_pick_n<DIM, Real, 8>(vf, mesh);
+    case 2: return vol_pick_n<DIM, Real, V, 2>(vf, mesh);
+    case 3: return vol_pick_n<DIM, Real, V, 3>(vf, mesh);
+    case 4: return vol_pick_n<DIM, Real, V, 4>(vf, mesh);
+    case 5: return vol_pick_n<DIM, Real, V, 5>(vf, mesh);
+    case 6: return vol_pick_n<DIM, Real, V, 6>(vf, mesh);
+    case 7: return vol_pick_n<DIM, Real, V, 7>(vf, mesh);
+    case 8: return vol_pick_n<DIM, Real, V, 8>(vf, mesh);
     default: return VolKernel{};
   }
 }

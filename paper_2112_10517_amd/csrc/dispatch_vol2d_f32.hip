@@ -3,6 +3,6 @@
 
 namespace esdg {
 
-VolKernel stage_kernel_2d_f32(int N, int vf, int mesh) { return vol_pick<2, float>(N, vf, mesh); }
+VolKernel stage_kernel_2d_f32(int N, int vf, int mesh) { return vol_pick<2, float, 0>(N, vf, mesh); }
 
 }  // namespace esdg

@@ -1,8 +1,11 @@
-// 3D stage-kernel instantiations, FP32 bulk precision.
+// 3D stage-kernel instantiations, FP32 bulk precision, default tile.
 #include "dispatch_vol.hpp"
 
 namespace esdg {
 
-VolKernel stage_kernel_3d_f32(int N, int vf, int mesh) { return vol_pick<3, float>(N, vf, mesh); }
+VolKernel stage_kernel_3d_f32(int N, int vf, int mesh, int variant) {
+  if (variant == 0) return vol_pick<3, float, 0>(N, vf, mesh);
+  return stage_kernel_3d_f32_tuned(N, vf, mesh, variant);
+}
 
 }  // namespace esdg

@@ -50,12 +50,13 @@ struct StageOps {
 // computes the same values whether it runs alone or with others.
 template <typename Real>
 struct ProbDesc {
-  Real* buf[4];              // U (state), Y, Y2 (stage states), R (RK accumulator): [E][nv][nn]
+  Real* buf[5];              // U (state), Y, Y2 (stage states), R (RK accumulator), DU (RHS): [E][nv][nn]
   const Real* metric;        // curved: [E][dim*dim+1][nn] (Ja^n_m, then 1/J)
   const Real* nface;         // curved: [dim][E][dim][nf] normal of the + face of each element
-  unsigned long long* lam;   // CFL: 2 x kLamSlots slots (bit patterns of non-negative doubles)
-  double* t_acc;             // elapsed time of the current step call
+  unsigned long long* lam;   // CFL: 2 x kLamSlots slots by step parity (bit patterns of non-negative doubles)
+  double* time;              // time of the state, 2 slots by step parity
   int* flag;                 // non-physical state flag
+  double t_end;              // a step never passes t_end: dt = min(dt, t_end - t)
   int E, n0, n1, n2;         // elements, per direction
   int tile0;                 // first tile of this problem in the launch
   int pad;
@@ -65,7 +66,7 @@ struct ProbDesc {
 template <typename Real>
 struct StageArgs {
   const ProbDesc<Real>* probs;  // problems of the launch, ordered by tile0
-  int nprob;
+  const int* tile_prob;         // problem index of every tile; NULL for a single problem
   Real* out_ext;        // RHS mode of a single problem: output; else NULL (buf[out_idx])
   int in_idx, out_idx;  // ProbDesc::buf indices of the stage input and output
   int mode;             // StageMode
@@ -73,12 +74,10 @@ struct StageArgs {
   Real coef_b, coef_a;  // RK: acc += b dt k ; y = u0 + a dt k
   // time step: fixed (cfl <= 0) or dt = cfl 2 / (N lam) with lam the largest
   // sum over directions of wave speeds of the step's start state, the maximum
-  // over the problem's kLamSlots slots of parity lam_cur
+  // over the problem's kLamSlots slots of parity par; then clipped to t_end
   double dt_fixed, cfl;
-  int lam_cur;
-  int lam_update;       // LAST stage: atomic max of the new state's value into parity 1 - lam_cur
-  int t_mode;           // FIRST stage: 1: t += dt, 2: t = dt (one lane per problem)
-  int pad;
+  int par;              // step parity: time and CFL slots of the step's start state
+  int lam_update;       // LAST stage: atomic max of the new state's value into parity 1 - par
   StageOps<Real> ops;
 };
 
@@ -249,12 +248,19 @@ __device__ __forceinline__ void surface_flux(int sf, const Real* uL, const Real*
 // a wave never diverges on the direction.  Node and face-node work is spread
 // over all lanes of the workgroup.
 template <int DIM, int N>
+struct TileShape {
+  static constexpr int NN = Pow<N, DIM>::value;   // nodes per element
+  static constexpr int L = NN / N;                // lines per direction
+  static constexpr int EPB0 = (64 / L) > 0 ? 64 / L : 1;  // default elements per block: one wave per direction
+};
+
+template <int DIM, int N, int EPB_ = TileShape<DIM, N>::EPB0>
 struct Tile {
   static constexpr int NN = Pow<N, DIM>::value;   // nodes per element
   static constexpr int NF = NN / N;               // nodes per face
   static constexpr int L = NN / N;                // lines per direction
   static constexpr int NFACE = 2 * DIM * NF;      // face nodes per element
-  static constexpr int EPB = (64 / L) > 0 ? 64 / L : 1;  // elements per block
+  static constexpr int EPB = EPB_;                // elements per block
   static constexpr int LANES_DIR = ((EPB * L + 63) / 64) * 64;  // lanes per direction
   static constexpr int THREADS = DIM * LANES_DIR;
   static constexpr int NPT = (EPB * NN + THREADS - 1) / THREADS;     // nodes per lane
@@ -264,6 +270,38 @@ struct Tile {
   // typical launch resident at once (3 x 64-lane waves per SIMD for N <= 4)
   static constexpr int WPE = N <= 4 ? 3 : (N <= 6 ? 2 : 1);
 };
+
+// LDS budget of one workgroup of a tile variant (two workgroups fit a CU)
+constexpr int kTileLdsCap = 80 * 1024;
+
+// Elements per workgroup of tile variant `variant` (0: one wave per
+// direction; 1: the fewest elements that fill >= 90% of the lanes of whole
+// waves; 2: twice the default), falling back to the default when the LDS of
+// the variant would exceed kTileLdsCap.  Every variant computes the same
+// values; only the speed differs.
+constexpr int tile_epb(int dim, int N, int np, int rbytes, int variant) {
+  int nn = 1;
+  for (int j = 0; j < dim; ++j) nn *= N;
+  const int L = nn / N, nv = dim + 2, nface = 2 * dim * L;
+  const int epb0 = 64 / L > 0 ? 64 / L : 1;
+  const int per = ((np + nv) * nn + nv * nface) * rbytes + 2 * dim * 4;
+  if (variant == 1) {
+    for (int e = epb0; e <= 32; ++e) {
+      const int lanes = (e * L + 63) / 64 * 64;
+      if (10 * e * L >= 9 * lanes) return e * per <= kTileLdsCap ? e : epb0;
+    }
+    return epb0;
+  }
+  if (variant == 2) return 2 * epb0 * per <= kTileLdsCap ? 2 * epb0 : epb0;
+  return epb0;
+}
+
+// D~ is a scalar operand of the pair loop (N^2 values in scalar registers)
+// except for N = 8 in FP64: its 128 scalar registers exceed a wave's, and
+// the code generated at -O2/-O3 for the spilled operands gave wrong volume
+// sums (correct at -O1 and with D~ in LDS), so that tile reads D~ from LDS.
+template <int N, typename Real>
+struct DtInLds { static constexpr bool value = N * N * (int)sizeof(Real) > 400; };
 
 template <int VF, int DIM>
 struct PrimCount { static constexpr int value = (VF == VF_RANOCHA) ? DIM + 4 : DIM + 2; };
@@ -290,7 +328,8 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 // compile-time constants).
 template <int DIR, int DIM, int N, int VF, int MESH, typename Real>
 __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value], const Real (&nrm)[N][3], int base,
-                                            const StageOps<Real>& ops, Real scale, Real (&A)[N][DIM + 2]) {
+                                            const StageOps<Real>& ops, const Real* s_dt, Real scale,
+                                            Real (&A)[N][DIM + 2]) {
   constexpr int NV = DIM + 2;
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int stride = Pow<N, DIR>::value;
@@ -322,7 +361,8 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
         volume_flux<VF, DIM>(P[i], P[k], DIR == 0 ? Real(1) : Real(0), DIR == 1 ? Real(1) : Real(0),
                              DIR == 2 ? Real(1) : Real(0), ops.inv_gm1, F);
       }
-      const Real dik = ops.Dt[i * N + k], dki = ops.Dt[k * N + i];
+      const Real dik = DtInLds<N, Real>::value ? s_dt[i * N + k] : ops.Dt[i * N + k];
+      const Real dki = DtInLds<N, Real>::value ? s_dt[k * N + i] : ops.Dt[k * N + i];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         A[i][v] += dik * F[v];
@@ -338,10 +378,10 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
   }
 }
 
-template <int DIM, int N, int VF, int MESH, typename Real>
-__global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(Tile<DIM, N>::WPE)))
-stage_kernel(StageArgs<Real> a) {
-  using T = Tile<DIM, N>;
+template <int DIM, int N, int VF, int MESH, typename Real, int EPB_>
+__global__ void __launch_bounds__((Tile<DIM, N, EPB_>::THREADS))
+__attribute__((amdgpu_waves_per_eu(Tile<DIM, N, EPB_>::WPE))) stage_kernel(StageArgs<Real> a) {
+  using T = Tile<DIM, N, EPB_>;
   constexpr int NN = T::NN, NF = T::NF, L = T::L, EPB = T::EPB, NV = T::NV, NFACE = T::NFACE;
   constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, LANES_DIR = T::LANES_DIR;
   constexpr int NP = PrimCount<VF, DIM>::value;
@@ -350,20 +390,11 @@ stage_kernel(StageArgs<Real> a) {
   __shared__ Real s_face[EPB][NV][NFACE];  // surface fluxes of the element's faces
   __shared__ Real s_acc[EPB][NV][NN];      // volume term, summed over directions in order
   __shared__ int s_nbr[EPB][2 * DIM];      // neighbour across face (2 dir + side), side 1 = +
+  __shared__ Real s_dt[DtInLds<N, Real>::value ? N * N : 1];  // D~ when it stays out of scalar registers
 
   const int tid = threadIdx.x;
-  // tile -> problem (binary search over the problems' first tiles)
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  int pi = 0;
-  if (a.nprob > 1) {
-    int lo = 0, hi = a.nprob - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (a.probs[mid].tile0 <= tile) lo = mid;
-      else hi = mid - 1;
-    }
-    pi = lo;
-  }
+  const int pi = a.tile_prob ? a.tile_prob[tile] : 0;
   const ProbDesc<Real>& P = a.probs[pi];
   const Real* uin = P.buf[a.in_idx];
   Real* out = a.out_ext ? a.out_ext : P.buf[a.out_idx];
@@ -374,8 +405,8 @@ stage_kernel(StageArgs<Real> a) {
   const int E = P.E, n0 = P.n0, n1 = P.n1, n2 = P.n2;
   const int e0 = (tile - P.tile0) * EPB;
   const bool cfl_mode = a.cfl > 0.0;
-  const unsigned long long* lam_in = P.lam + a.lam_cur * kLamSlots;
-  unsigned long long* lam_next = P.lam + (1 - a.lam_cur) * kLamSlots;
+  const unsigned long long* lam_in = P.lam + a.par * kLamSlots;
+  unsigned long long* lam_next = P.lam + (1 - a.par) * kLamSlots;
   const bool lam_out = a.mode == MODE_RK_LAST && cfl_mode && a.lam_update;
   const Real gm1 = a.ops.gamma - Real(1);
   if (tid < EPB) {
@@ -429,7 +460,9 @@ stage_kernel(StageArgs<Real> a) {
 #pragma unroll
       for (int m = 0; m < 3; ++m) nrm[k][m] = m < DIM ? me[(ldir * DIM + m) * NN + lbase + k * stride] : Real(0);
   }
-  __syncthreads();  // s_nbr
+  if (DtInLds<N, Real>::value)
+    for (int t = tid; t < N * N; t += THREADS) s_dt[t] = a.ops.Dt[t];
+  __syncthreads();  // s_nbr, s_dt
   Real tL[FPT][NV], tR[FPT][NV], tn[FPT][3];
 #pragma unroll
   for (int r = 0; r < FPT; ++r) {
@@ -502,9 +535,9 @@ stage_kernel(StageArgs<Real> a) {
   {
     const Real(*sp)[NN] = s_prim[lactive ? lel : 0];
     const Real sc = P.scale[ldir];
-    if (ldir == 0) line_fluxes<0, DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, sc, A);
-    else if (DIM > 1 && ldir == 1) line_fluxes<(DIM > 1 ? 1 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, sc, A);
-    else if (DIM > 2) line_fluxes<(DIM > 2 ? 2 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, sc, A);
+    if (ldir == 0) line_fluxes<0, DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, s_dt, sc, A);
+    else if (DIM > 1 && ldir == 1) line_fluxes<(DIM > 1 ? 1 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, s_dt, sc, A);
+    else if (DIM > 2) line_fluxes<(DIM > 2 ? 2 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, s_dt, sc, A);
   }
   // RK registers of the owned nodes, in flight while the line sums are merged
   Real ru0[NPT][NV], racc[NPT][NV];
@@ -552,10 +585,12 @@ stage_kernel(StageArgs<Real> a) {
     }
     dt = a.cfl * 2.0 / ((double)N * lam);
   }
-  if (e0 == 0 && a.mode == MODE_RK_FIRST) {
-    if (cfl_mode && tid < kLamSlots) lam_next[tid] = 0ull;
-    if (tid == 0 && a.t_mode == 1) *P.t_acc += dt;
-    if (tid == 0 && a.t_mode == 2) *P.t_acc = dt;
+  if (a.mode != MODE_RHS) {
+    const double t0 = P.time[a.par];
+    const double rem = P.t_end - t0;
+    if (dt > rem) dt = rem > 0.0 ? rem : 0.0;  // a NaN dt stays NaN
+    if (e0 == 0 && a.mode == MODE_RK_FIRST && cfl_mode && tid < kLamSlots) lam_next[tid] = 0ull;
+    if (e0 == 0 && a.mode == MODE_RK_LAST && tid == 0) P.time[1 - a.par] = t0 + dt;
   }
   double lam_max = 0.0;  // CFL wave-speed sum of the new state (LAST stage)
 #pragma unroll

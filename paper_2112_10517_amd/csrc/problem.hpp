@@ -1,0 +1,194 @@
+// Internal state of a problem handle and the launch helpers shared by the
+// single-problem entry points and the batch entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "esdg.h"
+#include "dispatch.hpp"
+#include "host_ops.hpp"
+#include "kernels.hpp"
+
+namespace esdg {
+
+struct TimedLaunch {
+  int kind;
+  hipEvent_t start, stop;
+};
+
+}  // namespace esdg
+
+struct esdg_problem {
+  esdg::MeshSpec spec;
+  esdg::Operators ops;
+  esdg::Geometry geo;
+  int dim = 3, p = 3, N = 4, nn = 64, nv = 5, nf = 16;
+  int64_t E = 0;
+  int vf = esdg::VF_RANOCHA, sf = esdg::SF_LLF, prec = esdg::PREC_FP64, mesh = esdg::MESH_AFFINE;
+  double gamma = 1.4;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  size_t rsize = 8;  // bytes per internal real
+
+  // device buffers (internal precision unless noted)
+  void* U = nullptr;          // state
+  void* Y = nullptr;          // RK stage state
+  void* Y2 = nullptr;         // second RK stage state (stage inputs and outputs alternate)
+  void* R = nullptr;          // RK accumulator
+  void* DU = nullptr;         // right-hand side
+  double* STAGE64 = nullptr;  // FP32 mode: FP64 staging of states crossing the ABI
+  void* METRIC = nullptr;     // curved metrics
+  void* NFACE = nullptr;      // curved face normals
+  double* PARTIAL = nullptr;  // reduction partials (FP64)
+  double* SCAL = nullptr;     // FP64 scalars: [0..1] time by step parity, [2..7] results
+  unsigned long long* LAM = nullptr;  // CFL slots: 2 x kLamSlots by step parity (bit patterns of doubles)
+  void* DESC = nullptr;               // ProbDesc<Real> of this problem (device)
+  int* FLAG = nullptr;                // non-physical flag
+  int red_blocks = 1;
+  int64_t red_per_block = 256;
+
+  bool have_state = false;
+  // step parity: the time and the CFL value of the current state live in
+  // slot `par` of SCAL[0..1] and LAM; every step flips it.  The CFL value is
+  // valid until the state changes other than through a CFL-mode step.
+  int par = 0;
+  bool lam_valid = false;
+  bool timing = false;
+  std::vector<esdg::TimedLaunch> launches;
+  std::string err;
+};
+
+namespace esdg {
+
+// Record an error message in *dst (if given) and in the calling thread's slot.
+esdg_status report(std::string* dst, esdg_status st, const char* fmt, ...);
+esdg_status fail(esdg_problem* P, esdg_status st, const char* fmt, ...);
+
+#define ESDG_TRY(x)                   \
+  do {                                \
+    esdg_status s_ = (x);             \
+    if (s_ != ESDG_OK) return s_;     \
+  } while (0)
+
+#define ESDG_HIP(errp, call)                                                                          \
+  do {                                                                                                \
+    hipError_t e_ = (call);                                                                           \
+    if (e_ != hipSuccess)                                                                             \
+      return ::esdg::report((errp), ESDG_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));            \
+  } while (0)
+
+// Where and how a kernel is launched: stream, optional event bracketing, error slot.
+struct Launcher {
+  hipStream_t stream = nullptr;
+  std::vector<TimedLaunch>* timed = nullptr;  // NULL: untimed
+  std::string* err = nullptr;
+};
+
+inline Launcher launcher_of(esdg_problem* P) {
+  Launcher L;
+  L.stream = P->stream;
+  L.timed = P->timing ? &P->launches : nullptr;
+  L.err = &P->err;
+  return L;
+}
+
+esdg_status launch_kernel(const Launcher& L, int kind, const void* fn, dim3 grid, dim3 block, void** args);
+
+// Time stepping of one stage launch: fixed dt, or CFL from the lam slots.
+struct StepCtl {
+  double dt_fixed = 0.0, cfl = 0.0;
+  int par = 0, lam_update = 0;
+};
+
+enum { BUF_U = 0, BUF_Y = 1, BUF_Y2 = 2, BUF_R = 3, BUF_DU = 4 };
+
+inline unsigned long long* lam_slot(esdg_problem* P, int k) { return P->LAM + k * kLamSlots; }
+
+// Tile variant of the stage kernel currently chosen for P's parameters
+// (process-wide table, written by the autotuner) and its version counter.
+int tile_variant_of(const esdg_problem* P);
+int tile_table_version();
+VolKernel pick_stage_kernel(const esdg_problem* P);
+
+template <typename Real>
+StageOps<Real> stage_ops(const esdg_problem* P) {
+  StageOps<Real> o{};
+  for (int i = 0; i < P->N * P->N; ++i) o.Dt[i] = (Real)P->ops.Dt[i];
+  o.inv_w0 = (Real)(1.0 / P->ops.w[0]);
+  o.inv_wp = (Real)(1.0 / P->ops.w[P->N - 1]);
+  o.gamma = (Real)P->gamma;
+  o.inv_gm1 = (Real)(1.0 / (P->gamma - 1.0));
+  return o;
+}
+
+// descriptor of problem P as the tile0-th tile of a launch
+template <typename Real>
+ProbDesc<Real> prob_desc(const esdg_problem* P, int tile0, double t_end) {
+  ProbDesc<Real> d{};
+  d.buf[BUF_U] = (Real*)P->U;
+  d.buf[BUF_Y] = (Real*)P->Y;
+  d.buf[BUF_Y2] = (Real*)P->Y2;
+  d.buf[BUF_R] = (Real*)P->R;
+  d.buf[BUF_DU] = (Real*)P->DU;
+  d.metric = (const Real*)P->METRIC;
+  d.nface = (const Real*)P->NFACE;
+  d.lam = P->LAM;
+  d.time = P->SCAL;
+  d.flag = P->FLAG;
+  d.t_end = t_end;
+  d.E = (int)P->E;
+  d.n0 = P->spec.n[0];
+  d.n1 = P->spec.n[1];
+  d.n2 = P->dim == 3 ? P->spec.n[2] : 1;
+  d.tile0 = tile0;
+  for (int j = 0; j < 3; ++j) d.scale[j] = (Real)(P->mesh == MESH_AFFINE ? P->geo.inv_half_h[j] : 1.0);
+  return d;
+}
+
+// One fused stage launch of kernel k over `tiles` tiles of the problems whose
+// descriptors (device memory) are `probs`, all with the parameters of `rep`:
+// right-hand side of buf[in_idx] (surface and volume terms) and, for the RK
+// modes, the stage update into buf[out_idx] / R; RHS mode writes buf[out_idx]
+// or out_ext.
+template <typename Real>
+esdg_status run_stage_on(const esdg_problem* rep, const Launcher& L, const VolKernel& k, const void* probs,
+                         const int* tile_prob, int64_t tiles, int in_idx, int out_idx, void* out_ext, int mode,
+                         double coef_b, double coef_a, const StepCtl& ctl) {
+  if (!k.fn) return report(L.err, ESDG_EINVAL, "no stage kernel for dim=%d p=%d flux=%d", rep->dim, rep->p, rep->vf);
+  StageArgs<Real> a{};
+  a.probs = (const ProbDesc<Real>*)probs;
+  a.tile_prob = tile_prob;
+  a.out_ext = (Real*)out_ext;
+  a.in_idx = in_idx;
+  a.out_idx = out_idx;
+  a.mode = mode;
+  a.surf = rep->sf;
+  a.coef_b = (Real)coef_b;
+  a.coef_a = (Real)coef_a;
+  a.dt_fixed = ctl.dt_fixed;
+  a.cfl = ctl.cfl;
+  a.par = ctl.par;
+  a.lam_update = ctl.lam_update;
+  a.ops = stage_ops<Real>(rep);
+  void* args[] = {&a};
+  return launch_kernel(L, ESDG_KERNEL_STAGE, k.fn, dim3((unsigned)tiles), dim3(k.threads), args);
+}
+
+// FP64 reduction of op over P's state (and DU for the entropy rate) on L's
+// stream; the result lands in SCAL[2..] (dt for RED_MAXLAMBDA, whose lam_max
+// also goes to `slot` if given).
+esdg_status run_reduce(esdg_problem* P, const Launcher& L, int op, double cfl, unsigned long long* slot);
+
+// elementwise precision conversion of P's state-sized arrays on L's stream
+esdg_status convert_state(esdg_problem* P, const Launcher& L, const void* src, void* dst, int to_fp64);
+
+// copy slot `from` of P's time and CFL slots to slot 1 - from (L's stream)
+esdg_status copy_parity(esdg_problem* P, const Launcher& L, int from);
+
+inline size_t state_count(const esdg_problem* P) { return (size_t)P->E * P->nv * P->nn; }
+
+}  // namespace esdg

@@ -23,6 +23,9 @@ PRECISION = {"fp64": 0, "fp32": 1}
 HOST, DEVICE = 0, 1
 KERNEL_STAGE, KERNEL_REDUCE = 1, 2
 PMAX = 7
+TILE_VARIANTS = 3
+BATCH_GRAPHS, BATCH_CONCURRENT = 1, 2
+JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 
 class EsdgError(RuntimeError):
@@ -43,13 +46,71 @@ class MeshDesc(C.Structure):
                 ("precision", C.c_int32), ("stream", C.c_void_p)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_active", C.c_int32), ("steps_per_tick", C.c_int32),
+                ("flags", C.c_int32), ("pad", C.c_int32), ("cfl", C.c_double)]
+
+
+class JobDesc(C.Structure):
+    _fields_ = [("mesh", MeshDesc), ("u0", C.POINTER(C.c_double)), ("t0", C.c_double), ("t_end", C.c_double)]
+
+
 _lib = None
 _lock = threading.Lock()
 
-EXPORTS = ["esdg_init_mesh", "esdg_destroy", "esdg_sizes", "esdg_set_stream", "esdg_get_coords",
-           "esdg_set_state", "esdg_get_state", "esdg_rhs", "esdg_step", "esdg_entropy_rate",
-           "esdg_totals", "esdg_max_dt", "esdg_sync", "esdg_timing_enable", "esdg_timing_read",
-           "esdg_timing_reset", "esdg_operators", "esdg_last_error", "esdg_version"]
+_vp, _dp, _i32, _i64, _d = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64, C.c_double
+_pi32, _pi64 = C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+_st, _str = C.c_int, C.c_char_p
+
+# name -> (restype, argtypes) of every exported symbol of include/esdg.h
+SIGNATURES = {
+    "esdg_init_mesh": (_st, [C.POINTER(MeshDesc), C.POINTER(_vp)]),
+    "esdg_destroy": (None, [_vp]),
+    "esdg_sizes": (_st, [_vp, _pi64, _pi32, _pi32]),
+    "esdg_set_stream": (_st, [_vp, _vp]),
+    "esdg_get_coords": (_st, [_vp, _dp]),
+    "esdg_set_state": (_st, [_vp, _vp, _i32]),
+    "esdg_get_state": (_st, [_vp, _vp, _i32]),
+    "esdg_rhs": (_st, [_vp, _vp, _i32]),
+    "esdg_step": (_st, [_vp, _d, _i32, _d, _dp]),
+    "esdg_set_time": (_st, [_vp, _d]),
+    "esdg_get_time": (_st, [_vp, _dp]),
+    "esdg_entropy_rate": (_st, [_vp, _dp]),
+    "esdg_totals": (_st, [_vp, _dp]),
+    "esdg_max_dt": (_st, [_vp, _d, _dp]),
+    "esdg_sync": (_st, [_vp]),
+    "esdg_timing_enable": (_st, [_vp, _i32]),
+    "esdg_timing_read": (_st, [_vp, _i32, _dp, _pi64]),
+    "esdg_timing_reset": (_st, [_vp]),
+    "esdg_autotune": (_st, [_vp, _i32, _pi32, _dp]),
+    "esdg_set_tile_variant": (_st, [_vp, _i32]),
+    "esdg_get_tile_variant": (_st, [_vp, _pi32, _pi32]),
+    "esdg_footprint": (_st, [C.POINTER(MeshDesc), _pi64]),
+    "esdg_batch_create": (_st, [C.POINTER(_vp), _i32, _dp, _vp, _i32, C.POINTER(_vp)]),
+    "esdg_batch_destroy": (None, [_vp]),
+    "esdg_batch_step": (_st, [_vp, _d, _i32, _d]),
+    "esdg_batch_rhs": (_st, [_vp, C.POINTER(_vp), _i32]),
+    "esdg_batch_times": (_st, [_vp, _dp]),
+    "esdg_batch_sync": (_st, [_vp, _pi32]),
+    "esdg_batch_autotune": (_st, [_vp, _i32]),
+    "esdg_batch_info": (_st, [_vp, _pi32, _pi64]),
+    "esdg_batch_timing_enable": (_st, [_vp, _i32]),
+    "esdg_batch_timing_read": (_st, [_vp, _dp, _pi64]),
+    "esdg_batch_last_error": (_str, [_vp]),
+    "esdg_server_create": (_st, [C.POINTER(ServerConfig), C.POINTER(_vp)]),
+    "esdg_server_destroy": (None, [_vp]),
+    "esdg_server_submit": (_st, [_vp, C.POINTER(JobDesc), _pi64]),
+    "esdg_server_tick": (_st, [_vp, _pi32, _pi32, _pi32]),
+    "esdg_server_job": (_st, [_vp, _i64, _pi32, _dp, _pi64]),
+    "esdg_server_finished": (_st, [_vp, _pi64, _i32, _pi32]),
+    "esdg_server_fetch": (_st, [_vp, _i64, _dp]),
+    "esdg_server_memory": (_st, [_vp, _pi64, _pi64]),
+    "esdg_server_last_error": (_str, [_vp]),
+    "esdg_operators": (_st, [_i32, _dp, _dp, _dp, _dp]),
+    "esdg_last_error": (_str, [_vp]),
+    "esdg_version": (_str, []),
+}
+EXPORTS = list(SIGNATURES)
 
 
 def load_library(path: str | None = None):
@@ -70,32 +131,10 @@ def load_library(path: str | None = None):
         except ImportError:
             pass
         lib = C.CDLL(p)
-        vp, dp, st = C.c_void_p, C.POINTER(C.c_double), C.c_int
-        lib.esdg_init_mesh.argtypes = [C.POINTER(MeshDesc), C.POINTER(vp)]
-        lib.esdg_destroy.argtypes = [vp]
-        lib.esdg_destroy.restype = None
-        lib.esdg_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
-        lib.esdg_set_stream.argtypes = [vp, vp]
-        lib.esdg_get_coords.argtypes = [vp, dp]
-        lib.esdg_set_state.argtypes = [vp, vp, C.c_int32]
-        lib.esdg_get_state.argtypes = [vp, vp, C.c_int32]
-        lib.esdg_rhs.argtypes = [vp, vp, C.c_int32]
-        lib.esdg_step.argtypes = [vp, C.c_double, C.c_int32, C.c_double, dp]
-        lib.esdg_entropy_rate.argtypes = [vp, dp]
-        lib.esdg_totals.argtypes = [vp, dp]
-        lib.esdg_max_dt.argtypes = [vp, C.c_double, dp]
-        lib.esdg_sync.argtypes = [vp]
-        lib.esdg_timing_enable.argtypes = [vp, C.c_int32]
-        lib.esdg_timing_read.argtypes = [vp, C.c_int32, dp, C.POINTER(C.c_int64)]
-        lib.esdg_timing_reset.argtypes = [vp]
-        lib.esdg_last_error.argtypes = [vp]
-        lib.esdg_last_error.restype = C.c_char_p
-        lib.esdg_operators.argtypes = [C.c_int32, dp, dp, dp, dp]
-        lib.esdg_version.argtypes = []
-        lib.esdg_version.restype = C.c_char_p
-        for name in EXPORTS:
-            if name not in ("esdg_destroy", "esdg_last_error", "esdg_version"):
-                getattr(lib, name).restype = st
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
         if path is None:
             _lib = lib
         return lib
@@ -132,6 +171,31 @@ def _where_ptr(arr, shape, writable: bool):
     raise TypeError("expected numpy.ndarray or torch.Tensor")
 
 
+def mesh_desc(dim: int, p: int, n, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), warp: float = 0.0,
+              gamma: float = 1.4, volume_flux="ranocha", surface_flux="llf", precision="fp64") -> MeshDesc:
+    """esdg_mesh_desc of a periodic box (coords and stream unset)."""
+    d = MeshDesc()
+    d.dim, d.p = dim, p
+    n = list(n) + [1] * (3 - len(n))
+    lo = list(lo) + [0.0] * (3 - len(lo))
+    hi = list(hi) + [1.0] * (3 - len(hi))
+    for j in range(3):
+        d.n[j], d.lo[j], d.hi[j] = int(n[j]), float(lo[j]), float(hi[j])
+    d.warp, d.gamma = float(warp), float(gamma)
+    d.volume_flux = FLUX[volume_flux] if isinstance(volume_flux, str) else int(volume_flux)
+    d.surface_flux = FLUX[surface_flux] if isinstance(surface_flux, str) else int(surface_flux)
+    d.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    return d
+
+
+def footprint(dim: int, p: int, n, **kw) -> int:
+    """Device bytes a problem of these parameters allocates (esdg_footprint)."""
+    lib = load_library()
+    b = C.c_int64()
+    _check(lib, None, lib.esdg_footprint(C.byref(mesh_desc(dim, p, n, **kw)), C.byref(b)))
+    return b.value
+
+
 class Problem:
     """One periodic Euler problem on the GPU (handle of ``esdg_init_mesh``)."""
 
@@ -139,17 +203,7 @@ class Problem:
                  warp: float = 0.0, gamma: float = 1.4, volume_flux: str = "ranocha",
                  surface_flux: str = "llf", precision: str = "fp64", coords=None, stream=None):
         self._lib = load_library()
-        d = MeshDesc()
-        d.dim, d.p = dim, p
-        n = list(n) + [1] * (3 - len(n))
-        lo = list(lo) + [0.0] * (3 - len(lo))
-        hi = list(hi) + [1.0] * (3 - len(hi))
-        for j in range(3):
-            d.n[j], d.lo[j], d.hi[j] = int(n[j]), float(lo[j]), float(hi[j])
-        d.warp, d.gamma = float(warp), float(gamma)
-        d.volume_flux = FLUX[volume_flux] if isinstance(volume_flux, str) else int(volume_flux)
-        d.surface_flux = FLUX[surface_flux] if isinstance(surface_flux, str) else int(surface_flux)
-        d.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        d = mesh_desc(dim, p, n, lo, hi, warp, gamma, volume_flux, surface_flux, precision)
         keep = None
         if coords is not None:
             keep = np.ascontiguousarray(coords, dtype=np.float64)
@@ -232,6 +286,30 @@ class Problem:
                    C.byref(tt) if t is not None else None)
         return tt.value if t is not None else None
 
+    def set_time(self, t: float):
+        self._call(self._lib.esdg_set_time, float(t))
+
+    def get_time(self) -> float:
+        r = C.c_double()
+        self._call(self._lib.esdg_get_time, C.byref(r))
+        return r.value
+
+    def autotune(self, reps: int = 20):
+        """Time every tile variant on the current state; (best variant, us per variant)."""
+        best = C.c_int32()
+        us = (C.c_double * TILE_VARIANTS)()
+        self._call(self._lib.esdg_autotune, int(reps), C.byref(best), us)
+        return best.value, list(us)
+
+    def tile_variant(self):
+        """(variant in use for this problem's parameters, elements per workgroup)."""
+        v, e = C.c_int32(), C.c_int32()
+        self._call(self._lib.esdg_get_tile_variant, C.byref(v), C.byref(e))
+        return v.value, e.value
+
+    def set_tile_variant(self, variant: int):
+        self._call(self._lib.esdg_set_tile_variant, int(variant))
+
     def entropy_rate(self) -> float:
         r = C.c_double()
         self._call(self._lib.esdg_entropy_rate, C.byref(r))
@@ -275,3 +353,174 @@ def operators(p: int):
 
 def version() -> str:
     return load_library().esdg_version().decode()
+
+
+class Batch:
+    """Problems advanced together (handle of ``esdg_batch_create``).
+
+    The batch references its members: keep the Problem objects alive while it
+    exists."""
+
+    def __init__(self, problems, t_end=None, stream=None, graphs: bool = True, concurrent: bool = False):
+        self._lib = load_library()
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[q._h.value for q in self.problems])
+        te = None
+        if t_end is not None:
+            te = np.ascontiguousarray(t_end, dtype=np.float64)
+            if te.shape != (len(self.problems),):
+                raise ValueError("t_end needs one entry per problem")
+        flags = (BATCH_GRAPHS if graphs else 0) | (BATCH_CONCURRENT if concurrent else 0)
+        sp = None if stream is None else (C.c_void_p(stream) if isinstance(stream, int) else C.c_void_p(stream.cuda_stream))
+        h = C.c_void_p()
+        st = self._lib.esdg_batch_create(arr, len(self.problems), None if te is None else te.ctypes.data_as(_dp),
+                                         sp, flags, C.byref(h))
+        _check(self._lib, None, st)
+        self._h = h
+
+    def _call(self, fn, *args):
+        st = fn(self._h, *args)
+        if st != OK:
+            msg = self._lib.esdg_batch_last_error(self._h)
+            cls = NonPhysicalState if st == ENONPHYSICAL else EsdgError
+            raise cls(st, msg.decode() if msg else "")
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.esdg_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, dt: float = 0.0, nsteps: int = 1, cfl: float = 0.0):
+        self._call(self._lib.esdg_batch_step, float(dt), int(nsteps), float(cfl))
+
+    def rhs(self, outs=None):
+        """RHS of every member; outs: list of arrays/tensors (or None entries), or None."""
+        if outs is None:
+            self._call(self._lib.esdg_batch_rhs, None, HOST)
+            return None
+        ptrs, wheres, keep = [], set(), []
+        for q, o in zip(self.problems, outs):
+            if o is None:
+                ptrs.append(None)
+                continue
+            ptr, where, k = _where_ptr(o, q.shape, True)
+            ptrs.append(ptr.value)
+            wheres.add(where)
+            keep.append(k)
+        if len(wheres) > 1:
+            raise ValueError("outputs must all be host or all be device memory")
+        arr = (C.c_void_p * len(ptrs))(*ptrs)
+        self._call(self._lib.esdg_batch_rhs, arr, wheres.pop() if wheres else HOST)
+        return outs
+
+    def times(self) -> np.ndarray:
+        t = np.zeros(len(self.problems))
+        self._call(self._lib.esdg_batch_times, t.ctypes.data_as(_dp))
+        return t
+
+    def sync(self):
+        bad = C.c_int32()
+        self._call(self._lib.esdg_batch_sync, C.byref(bad))
+
+    def autotune(self, reps: int = 10):
+        self._call(self._lib.esdg_batch_autotune, int(reps))
+
+    def info(self):
+        g, t = C.c_int32(), C.c_int64()
+        self._call(self._lib.esdg_batch_info, C.byref(g), C.byref(t))
+        return g.value, t.value
+
+    def timing(self, enable: bool):
+        self._call(self._lib.esdg_batch_timing_enable, 1 if enable else 0)
+
+    def timing_read(self):
+        ms, n = C.c_double(), C.c_int64()
+        self._call(self._lib.esdg_batch_timing_read, C.byref(ms), C.byref(n))
+        return ms.value, n.value
+
+
+class Server:
+    """Continuous-batching request loop (handle of ``esdg_server_create``)."""
+
+    def __init__(self, cfl: float, steps_per_tick: int = 8, hbm_budget: int = 0, max_active: int = 0,
+                 graphs: bool = True, concurrent: bool = False):
+        self._lib = load_library()
+        c = ServerConfig()
+        c.hbm_budget, c.max_active, c.steps_per_tick = int(hbm_budget), int(max_active), int(steps_per_tick)
+        c.flags = (BATCH_GRAPHS if graphs else 0) | (BATCH_CONCURRENT if concurrent else 0)
+        c.cfl = float(cfl)
+        h = C.c_void_p()
+        st = self._lib.esdg_server_create(C.byref(c), C.byref(h))
+        if st != OK:
+            raise EsdgError(st, "esdg_server_create failed")
+        self._h = h
+        self._shapes = {}
+
+    def _call(self, fn, *args):
+        st = fn(self._h, *args)
+        if st != OK:
+            msg = self._lib.esdg_server_last_error(self._h)
+            raise EsdgError(st, msg.decode() if msg else "")
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.esdg_server_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, u0: np.ndarray, t_end: float, t0: float = 0.0, **mesh) -> int:
+        """Queue a job: u0 (host FP64 state), end time, mesh keywords of mesh_desc()."""
+        j = JobDesc()
+        j.mesh = mesh_desc(**mesh)
+        u = np.ascontiguousarray(u0, dtype=np.float64)
+        j.u0 = u.ctypes.data_as(_dp)
+        j.t0, j.t_end = float(t0), float(t_end)
+        jid = C.c_int64()
+        self._call(self._lib.esdg_server_submit, C.byref(j), C.byref(jid))
+        self._shapes[jid.value] = u.shape
+        return jid.value
+
+    def tick(self):
+        """One tick; returns (finished ids, active, queued)."""
+        f, a, q = C.c_int32(), C.c_int32(), C.c_int32()
+        self._call(self._lib.esdg_server_tick, C.byref(f), C.byref(a), C.byref(q))
+        ids = (C.c_int64 * max(1, f.value))()
+        n = C.c_int32()
+        self._call(self._lib.esdg_server_finished, ids, f.value, C.byref(n))
+        return [ids[i] for i in range(n.value)], a.value, q.value
+
+    def job(self, jid: int):
+        """(status, time, steps) of a job."""
+        s, t, n = C.c_int32(), C.c_double(), C.c_int64()
+        self._call(self._lib.esdg_server_job, int(jid), C.byref(s), C.byref(t), C.byref(n))
+        return s.value, t.value, n.value
+
+    def fetch(self, jid: int, want_state: bool = True):
+        u = np.empty(self._shapes[jid]) if want_state else None
+        self._call(self._lib.esdg_server_fetch, int(jid), None if u is None else u.ctypes.data_as(_dp))
+        del self._shapes[jid]
+        return u
+
+    def memory(self):
+        used, budget = C.c_int64(), C.c_int64()
+        self._call(self._lib.esdg_server_memory, C.byref(used), C.byref(budget))
+        return used.value, budget.value
