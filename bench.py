@@ -98,6 +98,214 @@ def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
     return out
 
 
+def random_fourier_device(x, seed, torch, gamma=1.4):
+    """inputs.random_fourier evaluated with torch on the device (same seeded
+    modes and scaling; for the large batched workload)."""
+    import numpy as np
+    from paper_2112_10517_amd import inputs
+    d = x.shape[1]
+    s = x  # box [-1,1]^3
+
+    def field(modes):
+        g = torch.zeros((x.shape[0], x.shape[2]), dtype=torch.float64, device=x.device)
+        for k, a, phi in modes:
+            arg = sum(float(k[j]) * s[:, j] for j in range(d))
+            g += a * torch.sin(np.pi * arg + phi)
+        return g / g.abs().max()
+
+    fields = [field(m) for m in inputs.random_fourier_modes(seed, d)]
+    rho = 1.0 + 0.2 * fields[0]
+    p = 1.0 + 0.2 * fields[1]
+    v = [0.1 * f for f in fields[2:]]
+    u = torch.empty((x.shape[0], d + 2, x.shape[2]), dtype=torch.float64, device=x.device)
+    u[:, 0] = rho
+    for j in range(d):
+        u[:, 1 + j] = rho * v[j]
+    u[:, d + 1] = p / (gamma - 1.0) + 0.5 * rho * sum(vj * vj for vj in v)
+    return u
+
+
+def batched(args, esdg, torch, dev, fp64_pid):
+    """256 uneven periodic 3D problems (n ~ U{4..24}, p ~ U{2..7}, Cartesian or
+    warped with equal probability, seeded random Fourier states, seed =
+    problem index), FP32 bulk, Ranocha + LLF, one launch per (p, mesh kind)
+    group per RK stage, each step replayed as a HIP graph, tiles autotuned."""
+    import numpy as np
+    rng = np.random.default_rng(args.batch_seed)
+    specs = [(int(rng.integers(4, 25)), int(rng.integers(2, 8)), 0.1 if rng.random() < 0.5 else 0.0)
+             for _ in range(args.batch_problems)]
+    t0 = time.perf_counter()
+    probs = []
+    for i, (n, p, warp) in enumerate(specs):
+        q = esdg.Problem(3, p, (n, n, n), warp=warp, precision="fp32")
+        x = torch.from_numpy(q.coords()).to(dev)
+        q.set_state(random_fourier_device(x, i, torch))
+        del x
+        probs.append(q)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    nodes = sum(q.n_dof for q in probs)
+    B = esdg.Batch(probs, graphs=True)
+    t0 = time.perf_counter()
+    B.autotune(args.batch_tune_reps)
+    tune_s = time.perf_counter() - t0
+    groups, tiles = B.info()
+    chosen = {}
+    for q, (n, p, warp) in zip(probs, specs):
+        chosen["p%d_%s" % (p, "warped" if warp else "affine")] = q.tile_variant()
+    B.step(nsteps=args.batch_warmup, cfl=args.cfl)
+    B.sync()
+    torch.cuda.synchronize()
+    B.timing(True)
+    B.timing_read()
+    t0 = time.perf_counter()
+    B.step(nsteps=args.batch_steps, cfl=args.cfl)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms, ev_n = B.timing_read()
+    B.timing(False)
+    B.sync()
+    ms = 1e3 * wall / args.batch_steps
+    pid = ms * 1e6 / (4 * nodes)
+    # the same problems stepped one after another (no batch): launch-bound small problems
+    t0 = time.perf_counter()
+    for _ in range(args.batch_seq_steps):
+        for q in probs:
+            q.step(dt=0.0, nsteps=1, cfl=args.cfl)
+    torch.cuda.synchronize()
+    seq_ms = 1e3 * (time.perf_counter() - t0) / args.batch_seq_steps
+    B.close()
+    for q in probs:
+        q.close()
+    return {
+        "workload": "%d periodic 3D Euler problems, n ~ U{4..24}, p ~ U{2..7}, Cartesian/warped 50/50 (seed %d), "
+                    "random Fourier states (seed = problem index), FP32 bulk, Ranocha + LLF, RK4 in CFL %.2f"
+                    % (args.batch_problems, args.batch_seed, args.cfl),
+        "nodes": nodes,
+        "groups": groups,
+        "tiles": tiles,
+        "pid_ns": round(pid, 6),
+        "ms_per_step": round(ms, 4),
+        "event_ms_per_step": round(ev_ms / max(ev_n, 1), 4),
+        "steps": args.batch_steps,
+        "vs_fp64_plain_pid": round(fp64_pid / pid, 3),
+        "unbatched_ms_per_step": round(seq_ms, 4),
+        "batching_speedup": round(seq_ms / ms, 3),
+        "tile_variant_epb": {k: chosen[k] for k in sorted(chosen)},
+        "setup_s": round(setup_s, 1),
+        "autotune_s": round(tune_s, 2),
+    }
+
+
+def box_coords(esdg, p, n, lo, hi):
+    """Node coordinates [elem][3][node] of the affine periodic n^3 box."""
+    import numpy as np
+    xi = esdg.operators(p)[0]
+    N = p + 1
+    h = (hi - lo) / n
+    i = np.arange(n)
+    line = lo + h * (i[:, None] + 0.5 * (xi[None, :] + 1.0))  # [n][N]
+    ex, ey, ez = np.meshgrid(i, i, i, indexing="ij")
+    ex, ey, ez = ex.transpose(2, 1, 0).ravel(), ey.transpose(2, 1, 0).ravel(), ez.transpose(2, 1, 0).ravel()
+    q = np.arange(N ** 3)
+    qx, qy, qz = q % N, (q // N) % N, q // (N * N)
+    x = np.empty((n ** 3, 3, N ** 3))
+    x[:, 0] = line[ex][:, qx]
+    x[:, 1] = line[ey][:, qy]
+    x[:, 2] = line[ez][:, qz]
+    return x
+
+
+def serve_run(args, esdg, jobs, arrivals):
+    """Run the server over jobs [(kind, n, p, u0)] arriving at the given
+    times (s, relative to the start); returns per-job latencies and totals."""
+    import numpy as np
+    S = esdg.Server(cfl=args.cfl, steps_per_tick=args.serve_tick, graphs=True)
+    t_end = args.serve_t_end
+    ids, lat, steps_of, pending = {}, {}, {}, list(range(len(jobs)))
+    dw_err = None
+    max_active, depth = 0, []
+    t_start = time.perf_counter()
+    while len(lat) < len(jobs):
+        now = time.perf_counter() - t_start
+        while pending and arrivals[pending[0]] <= now:
+            i = pending.pop(0)
+            kind, n, p, u0 = jobs[i]
+            lo, hi = (-1.0, 1.0) if kind == "dw" else (0.0, 2 * np.pi)
+            ids[S.submit(u0, t_end, dim=3, p=p, n=(n, n, n), lo=(lo,) * 3, hi=(hi,) * 3, precision="fp32")] = i
+        done, active, queued = S.tick()
+        max_active = max(max_active, active)
+        depth.append(queued)
+        if not done and active == 0 and pending:
+            time.sleep(max(0.0, arrivals[pending[0]] - (time.perf_counter() - t_start)))
+        for jid in done:
+            i = ids[jid]
+            st, t, nsteps = S.job(jid)
+            if st != esdg.JOB_DONE:
+                raise RuntimeError("served job %d failed" % i)
+            want = dw_err is None and jobs[i][0] == "dw"
+            u = S.fetch(jid, want_state=want)
+            lat[i] = time.perf_counter() - t_start - arrivals[i]
+            steps_of[i] = nsteps
+            if want:
+                kind, n, p, _ = jobs[i]
+                from paper_2112_10517_amd import inputs
+                exact = inputs.density_wave(box_coords(esdg, p, n, -1.0, 1.0), t=t_end)
+                dw_err = {"n": n, "p": p, "rho_linf_error": float("%.3e" % np.abs(u[:, 0] - exact[:, 0]).max())}
+    elapsed = time.perf_counter() - t_start
+    S.close()
+    node_rhs = sum(4 * steps_of[i] * jobs[i][1] ** 3 * (jobs[i][2] + 1) ** 3 for i in range(len(jobs)))
+    L = np.array([lat[i] for i in range(len(jobs))])
+    return {
+        "jobs": len(jobs),
+        "elapsed_s": round(elapsed, 3),
+        "jobs_per_s": round(len(jobs) / (elapsed - arrivals[0]), 4),
+        "p50_latency_s": round(float(np.percentile(L, 50)), 3),
+        "p99_latency_s": round(float(np.percentile(L, 99)), 3),
+        "max_latency_s": round(float(L.max()), 3),
+        "max_active": max_active,
+        "mean_queue_depth": round(float(np.mean(depth)), 2),
+        "served_pid_ns": round(elapsed * 1e9 / node_rhs, 6),
+        "density_wave_error": dw_err,
+    }
+
+
+def served(args, esdg):
+    """Poisson request stream (rate 200/s, seeded) of 3D Euler jobs: density
+    wave on [-1,1]^3 or Taylor-Green vortex (Mach 0.1) on [0,2pi]^3 with equal
+    probability, n ~ U{8..32}, p ~ U{3,4,5}, affine, t_end 0.5, CFL 0.5, FP32
+    bulk, Ranocha + LLF.  The offered load exceeds one GPU's capacity by far,
+    so the first `serve_jobs` arrivals are served to completion (saturated
+    throughput), then a second window at 80% of the measured capacity."""
+    import numpy as np
+    from paper_2112_10517_amd import inputs
+    rng = np.random.default_rng(args.serve_seed)
+    njobs = max(args.serve_jobs, args.serve_sub_jobs)
+    gaps = rng.exponential(1.0 / args.serve_rate, size=njobs)
+    specs = [("dw" if rng.random() < 0.5 else "tgv", int(rng.integers(8, 33)), int(rng.integers(3, 6)))
+             for _ in range(njobs)]
+    jobs = []
+    for kind, n, p in specs:  # initial states are built before the clock starts
+        if kind == "dw":
+            u0 = inputs.density_wave(box_coords(esdg, p, n, -1.0, 1.0))
+        else:
+            u0 = inputs.taylor_green(box_coords(esdg, p, n, 0.0, 2 * np.pi))
+        jobs.append((kind, n, p, u0))
+    arr = np.cumsum(gaps) - gaps[0]
+    sat = serve_run(args, esdg, jobs[:args.serve_jobs], arr[:args.serve_jobs])
+    out = {"workload": "Poisson arrivals %.0f/s (seed %d): density wave or Taylor-Green vortex, n ~ U{8..32}, "
+                       "p ~ U{3,4,5}, affine, t_end %.2f, CFL %.2f, FP32 bulk, Ranocha + LLF"
+                       % (args.serve_rate, args.serve_seed, args.serve_t_end, args.cfl),
+           "saturated": sat}
+    if args.serve_sub_jobs > 0:
+        rate = 0.8 * sat["jobs_per_s"]
+        arr2 = np.cumsum(gaps * args.serve_rate / rate) - gaps[0] * args.serve_rate / rate
+        sub = serve_run(args, esdg, jobs[:args.serve_sub_jobs], arr2[:args.serve_sub_jobs])
+        sub["arrival_rate_per_s"] = round(rate, 4)
+        out["sub_saturation"] = sub
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +322,20 @@ def main(argv=None):
                     help="steps with per-kernel hipEvent timing (after the timed region)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32-bulk and Shima variants of the workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched FP32 workload")
+    ap.add_argument("--batch-problems", type=int, default=256)
+    ap.add_argument("--batch-seed", type=int, default=4)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--batch-warmup", type=int, default=2)
+    ap.add_argument("--batch-seq-steps", type=int, default=2)
+    ap.add_argument("--batch-tune-reps", type=int, default=5)
+    ap.add_argument("--no-served", action="store_true", help="skip the served workload")
+    ap.add_argument("--serve-jobs", type=int, default=48, help="arrivals served in the saturated window")
+    ap.add_argument("--serve-sub-jobs", type=int, default=32, help="arrivals of the 80%%-capacity window (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-seed", type=int, default=5)
+    ap.add_argument("--serve-t-end", type=float, default=0.5)
+    ap.add_argument("--serve-tick", type=int, default=4, help="RK steps per server tick")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (HBM "
                          "counter calibration under a profiler)")
@@ -174,7 +396,7 @@ def main(argv=None):
     achieved_gbs = traffic_bytes / vol_avg_s / 1e9
 
     line = {
-        "metric": "PID (ns per DOF per RHS), FP64 plain single problem",
+        "metric": "PID (ns per DOF per RHS) FP64 plain vs FP32 batched; served jobs/s + p99 latency",
         "value": round(pid_ns, 6),
         "unit": "ns/DOF/RHS",
         "n_gpus": 1,
@@ -218,6 +440,11 @@ def main(argv=None):
 
     if not args.no_variants:
         line["variants"] = variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n)
+
+    if not args.no_batched:
+        line["batched"] = batched(args, esdg, torch, dev, pid_ns)
+    if not args.no_served:
+        line["served"] = served(args, esdg)
 
     if args.calibrate_copy_mib > 0:
         nb = args.calibrate_copy_mib * (1 << 20)

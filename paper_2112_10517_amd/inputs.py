@@ -58,11 +58,10 @@ def density_wave(x, gamma: float = 1.4, amp: float = 0.98, p0: float = 20.0,
     return prim_to_cons(rho, vv, np.full((E, n), p0), gamma)
 
 
-def _fourier_field(rng, s: np.ndarray, modes: int = 8, kmax: float = 4.0) -> np.ndarray:
-    """sum of `modes` sines sin(pi k.s + phi), 1 <= |k| <= kmax, amplitude U[0.5,1]/|k|."""
-    E, d, n = s.shape
-    g = np.zeros((E, n))
+def fourier_modes(rng, d: int, modes: int = 8, kmax: float = 4.0):
+    """`modes` draws (k, a, phi): integer k with 1 <= |k| <= kmax, a = U[0.5,1]/|k|, phi = U[0,2pi]."""
     K = int(math.floor(kmax))
+    out = []
     for _ in range(modes):
         while True:
             k = rng.integers(-K, K + 1, size=d)
@@ -71,7 +70,21 @@ def _fourier_field(rng, s: np.ndarray, modes: int = 8, kmax: float = 4.0) -> np.
                 break
         a = rng.uniform(0.5, 1.0) / nk
         phi = rng.uniform(0.0, 2.0 * np.pi)
-        g += a * np.sin(np.pi * np.einsum("j,ejn->en", k.astype(np.float64), s) + phi)
+        out.append((k.astype(np.float64), a, phi))
+    return out
+
+
+def random_fourier_modes(seed: int, d: int):
+    """Mode lists of the fields rho, p, v_1..v_d of random_fourier(seed)."""
+    return [fourier_modes(np.random.Generator(np.random.PCG64(seed * 16 + idx)), d) for idx in range(2 + d)]
+
+
+def _fourier_field(rng, s: np.ndarray, modes: int = 8, kmax: float = 4.0) -> np.ndarray:
+    """sum of `modes` sines sin(pi k.s + phi), 1 <= |k| <= kmax, amplitude U[0.5,1]/|k|."""
+    E, d, n = s.shape
+    g = np.zeros((E, n))
+    for k, a, phi in fourier_modes(rng, d, modes, kmax):
+        g += a * np.sin(np.pi * np.einsum("j,ejn->en", k, s) + phi)
     return g
 
 
