@@ -50,6 +50,25 @@ def algorithmic_stage_bytes(dim: int, N: int, curved: bool, real_bytes: int = 8)
     return (state + metric + traces + normals) * real_bytes
 
 
+def recorded_traffic(kernel_source: str, profile: str):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE record
+    in `profile`, if it was taken on the current kernel source (else None)."""
+    import hashlib
+    try:
+        digest = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
+        for line in open(profile):
+            if line.startswith("traffic-record:"):
+                f = line.split()
+                rec = dict(zip(f[1::2], f[2::2]))
+                if rec.get("kernels_sha256") != digest:
+                    return None
+                return (float(rec["fetch_kib"]) * float(rec["fetch_factor"]) +
+                        float(rec["write_kib"]) * float(rec["write_factor"])) * 1024.0
+    except (OSError, KeyError, ValueError, IndexError):
+        return None
+    return None
+
+
 def time_steps(g, steps, warmup, cfl, torch):
     """ms per CFL-mode RK4 step of problem g (state already set)."""
     for _ in range(warmup):
@@ -432,7 +451,9 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": recorded_traffic(os.path.join(ROOT, "paper_2112_10517_amd", "csrc", "kernels.hpp"),
+                                        os.path.join(ROOT, "profiles", "stage_kernel_3d_p3_warped16_fp64.md"))
+            if (dim, p, n, args.flux) == (3, 3, 16, "ranocha") else None,
             "algorithmic_bytes_per_node": bytes_per_node,
             "bytes_per_launch": traffic_bytes,
             "avg_launch_us": round(vol_avg_s * 1e6, 3),
