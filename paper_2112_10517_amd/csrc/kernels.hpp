@@ -355,8 +355,9 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
     for (int k = i + 1; k < N; ++k) {
       Real F[NV];
       if (MESH == MESH_CURVED) {
-        volume_flux<VF, DIM>(P[i], P[k], Real(0.5) * (nrm[i][0] + nrm[k][0]), Real(0.5) * (nrm[i][1] + nrm[k][1]),
-                             Real(0.5) * (nrm[i][2] + nrm[k][2]), ops.inv_gm1, F);
+        // nrm holds half the contravariant vectors: the sum is the pair average
+        volume_flux<VF, DIM>(P[i], P[k], nrm[i][0] + nrm[k][0], nrm[i][1] + nrm[k][1], nrm[i][2] + nrm[k][2],
+                             ops.inv_gm1, F);
       } else {
         volume_flux<VF, DIM>(P[i], P[k], DIR == 0 ? Real(1) : Real(0), DIR == 1 ? Real(1) : Real(0),
                              DIR == 2 ? Real(1) : Real(0), ops.inv_gm1, F);
@@ -458,7 +459,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<DIM, N, EPB_>::WPE))) stage_kernel(Stage
 #pragma unroll
     for (int k = 0; k < N; ++k)
 #pragma unroll
-      for (int m = 0; m < 3; ++m) nrm[k][m] = m < DIM ? me[(ldir * DIM + m) * NN + lbase + k * stride] : Real(0);
+      for (int m = 0; m < 3; ++m) nrm[k][m] = m < DIM ? Real(0.5) * me[(ldir * DIM + m) * NN + lbase + k * stride] : Real(0);
   }
   if (DtInLds<N, Real>::value)
     for (int t = tid; t < N * N; t += THREADS) s_dt[t] = a.ops.Dt[t];
@@ -632,8 +633,11 @@ __attribute__((amdgpu_waves_per_eu(Tile<DIM, N, EPB_>::WPE))) stage_kernel(Stage
       if (a.mode == MODE_RHS) {
         out[o] = k;
       } else if (a.mode == MODE_RK_FIRST) {
-        racc_buf[o] = uo[r][v] + a.coef_b * (Real)dt * k;
-        out[o] = uo[r][v] + a.coef_a * (Real)dt * k;
+        // the stage input is read again (an L2 hit) rather than kept live in
+        // registers through the line phase
+        const Real u_in = uin[o];
+        racc_buf[o] = u_in + a.coef_b * (Real)dt * k;
+        out[o] = u_in + a.coef_a * (Real)dt * k;
       } else if (a.mode == MODE_RK_MID) {
         racc_buf[o] = racc[r][v] + a.coef_b * (Real)dt * k;
         out[o] = ru0[r][v] + a.coef_a * (Real)dt * k;
