@@ -85,6 +85,15 @@ struct StageArgs {
 // small helpers
 // ---------------------------------------------------------------------------
 
+// Global-memory view of a pointer read from a descriptor: accesses through it
+// compile to global_* instructions.  Through the generic pointer they would be
+// flat_* instructions, which also count against the LDS wait counter, so every
+// LDS wait would wait for the outstanding global loads as well.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 template <int B, int K>
 struct Pow { static constexpr int value = B * Pow<B, K - 1>::value; };
 template <int B>
@@ -397,16 +406,16 @@ __attribute__((amdgpu_waves_per_eu(Tile<DIM, N, EPB_>::WPE))) stage_kernel(Stage
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int pi = a.tile_prob ? a.tile_prob[tile] : 0;
   const ProbDesc<Real>& P = a.probs[pi];
-  const Real* uin = P.buf[a.in_idx];
-  Real* out = a.out_ext ? a.out_ext : P.buf[a.out_idx];
-  Real* racc_buf = P.buf[3];
-  const Real* u0 = P.buf[0];
-  const Real* metric = P.metric;
-  const Real* nface = P.nface;
+  const auto uin = as_global((const Real*)P.buf[a.in_idx]);
+  const auto out = as_global(a.out_ext ? a.out_ext : P.buf[a.out_idx]);
+  const auto racc_buf = as_global(P.buf[3]);
+  const auto u0 = as_global((const Real*)P.buf[0]);
+  const auto metric = as_global(P.metric);
+  const auto nface = as_global(P.nface);
   const int E = P.E, n0 = P.n0, n1 = P.n1, n2 = P.n2;
   const int e0 = (tile - P.tile0) * EPB;
   const bool cfl_mode = a.cfl > 0.0;
-  const unsigned long long* lam_in = P.lam + a.par * kLamSlots;
+  const auto lam_in = as_global((const unsigned long long*)P.lam + a.par * kLamSlots);
   unsigned long long* lam_next = P.lam + (1 - a.par) * kLamSlots;
   const bool lam_out = a.mode == MODE_RK_LAST && cfl_mode && a.lam_update;
   const Real gm1 = a.ops.gamma - Real(1);
@@ -455,7 +464,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<DIM, N, EPB_>::WPE))) stage_kernel(Stage
   }
   Real nrm[N][3];
   if (MESH == MESH_CURVED) {
-    const Real* me = metric + (size_t)(lactive ? e0 + lel : 0) * (NM * NN);
+    const auto me = metric + (size_t)(lactive ? e0 + lel : 0) * (NM * NN);
 #pragma unroll
     for (int k = 0; k < N; ++k)
 #pragma unroll
@@ -481,7 +490,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<DIM, N, EPB_>::WPE))) stage_kernel(Stage
       tR[r][v] = uin[(size_t)eR * (NV * NN) + v * NN + qR];
     }
     if (MESH == MESH_CURVED) {
-      const Real* nf = nface + ((size_t)dir * E + eL) * (DIM * NF) + f;
+      const auto nf = nface + ((size_t)dir * E + eL) * (DIM * NF) + f;
       tn[r][0] = nf[0];
       tn[r][1] = DIM > 1 ? nf[NF] : Real(0);
       tn[r][2] = DIM > 2 ? nf[2 * NF] : Real(0);
@@ -587,11 +596,12 @@ __attribute__((amdgpu_waves_per_eu(Tile<DIM, N, EPB_>::WPE))) stage_kernel(Stage
     dt = a.cfl * 2.0 / ((double)N * lam);
   }
   if (a.mode != MODE_RHS) {
-    const double t0 = P.time[a.par];
+    const auto time = as_global(P.time);
+    const double t0 = time[a.par];
     const double rem = P.t_end - t0;
     if (dt > rem) dt = rem > 0.0 ? rem : 0.0;  // a NaN dt stays NaN
     if (e0 == 0 && a.mode == MODE_RK_FIRST && cfl_mode && tid < kLamSlots) lam_next[tid] = 0ull;
-    if (e0 == 0 && a.mode == MODE_RK_LAST && tid == 0) P.time[1 - a.par] = t0 + dt;
+    if (e0 == 0 && a.mode == MODE_RK_LAST && tid == 0) time[1 - a.par] = t0 + dt;
   }
   double lam_max = 0.0;  // CFL wave-speed sum of the new state (LAST stage)
 #pragma unroll
@@ -656,7 +666,7 @@ __attribute__((amdgpu_waves_per_eu(Tile<DIM, N, EPB_>::WPE))) stage_kernel(Stage
       const Real c = sqrt(a.ops.gamma * pr * ir);
       Real lam = Real(0);
       if (MESH == MESH_CURVED) {
-        const Real* me = metric + (size_t)ee * (NM * NN) + i;
+        const auto me = metric + (size_t)ee * (NM * NN) + i;
 #pragma unroll
         for (int n = 0; n < DIM; ++n) {
           const Real j0 = me[(n * DIM) * NN];
