@@ -107,7 +107,8 @@ __device__ __forceinline__ double dev_log(double x) { return log(x); }
 __device__ __forceinline__ float dev_log(float x) { return logf(x); }
 
 // Reciprocal: hardware estimate refined by Newton's iteration r <- r(2 - q r)
-// written as two fused multiply-adds (two steps in FP64, one in FP32).
+// written as two fused multiply-adds (two steps in FP64; the FP32 estimate
+// is used as is).
 __device__ __forceinline__ double dev_rcp(double q) {
   double r = __builtin_amdgcn_rcp(q);
   double e = fma(-q, r, 1.0);
@@ -116,8 +117,7 @@ __device__ __forceinline__ double dev_rcp(double q) {
   return fma(r, e, r);
 }
 __device__ __forceinline__ float dev_rcp(float q) {
-  const float r = __builtin_amdgcn_rcpf(q);
-  return fmaf(r, fmaf(-q, r, 1.0f), r);
+  return __builtin_amdgcn_rcpf(q);  // 1 ulp: below the FP32 parity bar, no refinement
 }
 
 // Primitive variables at one node, with log(rho) and log(p) when the volume
@@ -388,9 +388,17 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
   }
 }
 
+// Waves per SIMD the register allocation of a tile must allow: the tile's
+// default, except for the FP32 p = 7 affine tile, which fits three waves
+// without spilling (measured faster; the curved one would spill).
+template <int DIM, int N, int MESH, typename Real, int EPB_>
+struct StageWaves {
+  static constexpr int value = (sizeof(Real) == 4 && N == 8 && MESH == MESH_AFFINE) ? 3 : Tile<DIM, N, EPB_>::WPE;
+};
+
 template <int DIM, int N, int VF, int MESH, typename Real, int EPB_>
 __global__ void __launch_bounds__((Tile<DIM, N, EPB_>::THREADS))
-__attribute__((amdgpu_waves_per_eu(Tile<DIM, N, EPB_>::WPE))) stage_kernel(StageArgs<Real> a) {
+__attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))) stage_kernel(StageArgs<Real> a) {
   using T = Tile<DIM, N, EPB_>;
   constexpr int NN = T::NN, NF = T::NF, L = T::L, EPB = T::EPB, NV = T::NV, NFACE = T::NFACE;
   constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, LANES_DIR = T::LANES_DIR;
