@@ -515,9 +515,11 @@ class Server:
         return s.value, t.value, n.value
 
     def fetch(self, jid: int, want_state: bool = True):
-        u = np.empty(self._shapes[jid]) if want_state else None
+        """Final state of a finished job (host array, or None) and release of the job."""
+        shape = self._shapes.get(jid)
+        u = np.empty(shape) if want_state and shape is not None else None
         self._call(self._lib.esdg_server_fetch, int(jid), None if u is None else u.ctypes.data_as(_dp))
-        del self._shapes[jid]
+        self._shapes.pop(jid, None)
         return u
 
     def memory(self):

@@ -84,3 +84,25 @@ def test_null_handle_calls(E):
     assert lib.esdg_sync(None) == E.EINVAL
     assert b"NULL" in lib.esdg_last_error(None)
     lib.esdg_destroy(None)  # NULL-safe
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dim=3, p=3, n=(4, 3, 5)),
+    dict(dim=3, p=7, n=(2, 2, 2), warp=0.1),
+    dict(dim=2, p=4, n=(6, 5), precision="fp32"),
+    dict(dim=3, p=5, n=(3, 3, 3), warp=0.1, precision="fp32"),
+])
+def test_footprint_matches_buffer_sizes(E, kw):
+    # host-only: five state-sized arrays, FP64 staging for FP32, metrics and
+    # face normals on curved meshes, scalars; no device is touched
+    dim, p, n = kw["dim"], kw["p"], kw["n"]
+    rs = 4 if kw.get("precision") == "fp32" else 8
+    N = p + 1
+    nn, nf = N ** dim, N ** (dim - 1)
+    Ecount = int(np.prod(n))
+    ns = Ecount * (dim + 2) * nn
+    expect = 5 * ns * rs + (ns * 8 if rs == 4 else 0)
+    if kw.get("warp", 0.0):
+        expect += (Ecount * (dim * dim + 1) * nn + dim * Ecount * dim * nf) * rs
+    got = E.footprint(**kw)
+    assert expect <= got <= expect + 64 * 1024 + 8 * 8 * 2048

@@ -284,3 +284,57 @@ def test_server_admission_by_memory(esdg):
     assert peak == 2 and len(out) == 4
     for i in range(1, 4):
         assert np.array_equal(out[0], out[i])
+
+
+def test_graph_replays_match_eager_step_by_step(esdg):
+    """Each replay of a captured step is checked against the eager batch,
+    with host reads (eager work and synchronisation) between the replays."""
+    a, b = pair(esdg, MIX[:6], seed0=90)
+    with esdg.Batch(a, graphs=True, concurrent=True) as G, esdg.Batch(b, graphs=False) as E:
+        for step in range(5):
+            kw = dict(dt=2e-4) if step == 2 else dict(cfl=0.4)
+            G.step(nsteps=1, **kw)
+            E.step(nsteps=1, **kw)
+            assert np.array_equal(G.times(), E.times()), step
+            for qa, qb in zip(a, b):
+                assert np.array_equal(qa.get_state(), qb.get_state()), step
+
+
+def test_server_reports_failed_job_and_releases_memory(esdg):
+    # a job whose initial pressure is negative is flagged by the stage kernel
+    # (non-physical state), retired as FAILED and its memory returned
+    S = esdg.Server(cfl=0.5, steps_per_tick=2)
+    try:
+        mesh, u = job("dw", 2, 3)
+        good = S.submit(u, 0.01, **mesh)
+        bad_u = u.copy()
+        bad_u[:, 4] = -1.0  # rho e < 0 -> p < 0
+        bad = S.submit(bad_u, 0.01, **mesh)
+        seen = {}
+        for _ in range(200):
+            done, active, queued = S.tick()
+            for jid in done:
+                seen[jid] = S.job(jid)[0]
+            if len(seen) == 2:
+                break
+        assert seen[bad] == esdg.JOB_FAILED and seen[good] == esdg.JOB_DONE
+        S.fetch(bad)
+        u_good = S.fetch(good)
+        assert np.all(np.isfinite(u_good))
+        assert S.memory()[0] == 0
+        with pytest.raises(esdg.EsdgError):
+            S.submit(u, 0.0, **mesh)  # t_end must exceed t0
+        with pytest.raises(esdg.EsdgError):
+            S.fetch(good)  # already released
+    finally:
+        S.close()
+
+
+def test_server_rejects_job_larger_than_budget(esdg):
+    mesh, u = job("dw", 2, 3)
+    S = esdg.Server(cfl=0.5, hbm_budget=1024)
+    try:
+        with pytest.raises(esdg.EsdgError):
+            S.submit(u, 0.01, **mesh)
+    finally:
+        S.close()
