@@ -1,4 +1,5 @@
-"""CPU oracle for the flux-differencing LGL-DGSEM (test infrastructure only).
+"""CPU oracle for the flux-differencing LGL-DGSEM and the Legendre-Gauss
+collocation scheme with entropy projection (test infrastructure only).
 
 Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  It wraps ``esdg_oracle.c`` (plain C,
@@ -7,7 +8,8 @@ library in ``paper_2112_10517_amd``.
 
 Every function follows the definitions of Ranocha et al. (arXiv:2112.10517):
 the flux-differencing DG form of Sec. 2, the Euler fluxes and log means of
-Sec. 3, the metric terms of Sec. 2.3.  See the header of ``esdg_oracle.c`` for
+Sec. 3, the metric terms of Sec. 2.3, the hybridised Gauss collocation form of
+Sec. 5.  See the header of ``esdg_oracle.c`` for
 the readings taken where the paper is silent.
 """
 from __future__ import annotations
@@ -43,7 +45,7 @@ class _Desc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("p", C.c_int32), ("n", C.c_int32 * 3),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("warp", C.c_double), ("gamma", C.c_double),
-                ("vol_flux", C.c_int32), ("surf_flux", C.c_int32)]
+                ("vol_flux", C.c_int32), ("surf_flux", C.c_int32), ("nodes", C.c_int32)]
 
 
 def _load():
@@ -56,6 +58,9 @@ def _load():
         dp = C.POINTER(C.c_double)
         lib.orc_lgl.argtypes = [C.c_int, dp, dp, dp]
         lib.orc_lgl.restype = C.c_int
+        lib.orc_gauss.argtypes = [C.c_int, dp, dp, dp, dp, dp]
+        lib.orc_gauss.restype = C.c_int
+        lib.orc_cons_from_entropy.argtypes = [C.c_int, C.c_double, dp, dp]
         lib.orc_logmean.argtypes = [C.c_double, C.c_double]
         lib.orc_logmean.restype = C.c_double
         lib.orc_inv_logmean.argtypes = [C.c_double, C.c_double]
@@ -117,6 +122,25 @@ def lgl(p: int):
     return xi, w, D
 
 
+def gauss(p: int):
+    """Legendre-Gauss nodes, weights, derivative matrix D (N x N) and the
+    Lagrange basis values at -1 and +1 (rL, rR) for degree p (N = p+1 nodes)."""
+    lib = _load()
+    N = p + 1
+    xi, w, D, rL, rR = np.zeros(N), np.zeros(N), np.zeros((N, N)), np.zeros(N), np.zeros(N)
+    if lib.orc_gauss(p, _ptr(xi), _ptr(w), _ptr(D), _ptr(rL), _ptr(rR)) != 0:
+        raise ValueError("degree out of range")
+    return xi, w, D, rL, rR
+
+
+def cons_from_entropy(dim: int, gamma: float, w) -> np.ndarray:
+    """Conservative variables of entropy variables w (inverse of entropy_vars)."""
+    w = _f64(w)
+    u = np.zeros(dim + 2)
+    _load().orc_cons_from_entropy(dim, gamma, _ptr(w), _ptr(u))
+    return u
+
+
 def logmean(a, b) -> float:
     """Algorithm 2 of Sec. 3.1, arguments (a_-, a_+)."""
     return _load().orc_logmean(float(a), float(b))
@@ -165,10 +189,11 @@ def entropy(dim: int, gamma: float, u, n):
 # --------------------------------------------------------------------------
 
 class Mesh:
-    """Periodic box mesh of n[0] x ... elements of degree p (plain CPU)."""
+    """Periodic box mesh of n[0] x ... elements of degree p (plain CPU);
+    nodes = "lgl" (Sec. 2) or "gauss" (Sec. 5, affine meshes only)."""
 
     def __init__(self, dim, p, n, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), warp=0.0,
-                 gamma=1.4, vol_flux="ranocha", surf_flux="llf", coords=None):
+                 gamma=1.4, vol_flux="ranocha", surf_flux="llf", coords=None, nodes="lgl"):
         lib = _load()
         d = _Desc()
         d.dim, d.p = dim, p
@@ -180,6 +205,8 @@ class Mesh:
         d.warp, d.gamma = warp, gamma
         d.vol_flux = FLUX_NAMES[vol_flux] if isinstance(vol_flux, str) else vol_flux
         d.surf_flux = FLUX_NAMES[surf_flux] if isinstance(surf_flux, str) else surf_flux
+        d.nodes = {"lgl": 0, "gauss": 1}[nodes]
+        self.node_kind = nodes
         self._coords = None if coords is None else _f64(coords)
         h = lib.orc_mesh_new(C.byref(d), None if coords is None else _ptr(self._coords))
         if not h:

@@ -36,6 +36,13 @@
  *   R14 warp: x_m = xhat_m + warp*prod_j sin(pi*s_j), s_j in [-1,1] the
  *       global box coordinate.
  *   R17 CFL: dt = cfl*2/((p+1)*max_i sum_n (|v.Ja^n| + c|Ja^n|)/J_i).
+ *
+ * Legendre-Gauss collocation (Sec. 5, hybridised form with the entropy
+ * projection) is evaluated on affine meshes by assembling, for every line of
+ * an element, the dense hybridised operator of the paper's formulation over
+ * the line's volume nodes and its two face points and summing
+ * 2 Q_h f(u~_a, u~_b) over all pairs of that combined set, with the face
+ * states u~ = u(R w(u)) of the element and of its neighbour.
  */
 #include <math.h>
 #include <omp.h>
@@ -52,6 +59,7 @@ typedef struct {
   double lo[3], hi[3];
   double warp, gamma;
   int32_t vol_flux, surf_flux;
+  int32_t nodes; /* 0: Legendre-Gauss-Lobatto, 1: Legendre-Gauss (affine only) */
 } orc_desc;
 
 typedef struct {
@@ -61,6 +69,7 @@ typedef struct {
   int64_t ne;   /* elements */
   int nv;       /* conserved variables */
   double xi[ORC_MAXN], w[ORC_MAXN], D[ORC_MAXN * ORC_MAXN];
+  double rL[ORC_MAXN], rR[ORC_MAXN]; /* Gauss: Lagrange basis at -1 and +1 */
   double *x;    /* [ne][dim][nn] physical node coordinates */
   double *Ja;   /* [ne][3][3][nn]: Ja[e][n][m][i] = (Ja)^n_m at node i */
   double *J;    /* [ne][nn] */
@@ -133,6 +142,56 @@ int orc_lgl(int p, double *xi, double *w, double *D) {
       else v = 0.0L;
       D[i * N + j] = (double)v;
     }
+  return 0;
+}
+
+/* Legendre-Gauss nodes xi (roots of P_N, N = p+1, ascending), weights
+ * 2/((1-x^2) P_N'(x)^2), the textbook collocation derivative matrix
+ * D_ij = P_N'(x_i) / (P_N'(x_j) (x_i - x_j)), D_ii = x_i / (1 - x_i^2), and
+ * the values rL, rR of the Lagrange basis at -1 and +1 (Sec. 5 operators
+ * R: volume nodes -> face points). */
+int orc_gauss(int p, double *xi, double *w, double *D, double *rL, double *rR) {
+  if (p < 0 || p + 1 >= ORC_MAXN) return -1;
+  const int N = p + 1;
+  long double x[ORC_MAXN], dP[ORC_MAXN];
+  for (int i = 0; i < N; ++i) {
+    long double t = -cosl(3.14159265358979323846264338327950288L * (i + 0.5L) / N);
+    for (int it = 0; it < 100; ++it) {
+      long double P, d1, d2;
+      legendre(N, t, &P, &d1, &d2);
+      long double dt = P / d1;
+      t -= dt;
+      if (fabsl(dt) < 1e-19L) break;
+    }
+    x[i] = t;
+  }
+  for (int i = 0; i < N / 2; ++i) {
+    long double s = 0.5L * (x[N - 1 - i] - x[i]);
+    x[i] = -s; x[N - 1 - i] = s;
+  }
+  if (N % 2 == 1) x[N / 2] = 0.0L;
+  for (int i = 0; i < N; ++i) {
+    long double P, d1, d2;
+    legendre(N, x[i], &P, &d1, &d2);
+    dP[i] = d1;
+    xi[i] = (double)x[i];
+    w[i] = (double)(2.0L / ((1.0L - x[i] * x[i]) * d1 * d1));
+  }
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      long double v = (i != j) ? dP[i] / (dP[j] * (x[i] - x[j])) : x[i] / (1.0L - x[i] * x[i]);
+      D[i * N + j] = (double)v;
+    }
+  for (int k = 0; k < N; ++k) {
+    long double a = 1.0L, b = 1.0L;
+    for (int j = 0; j < N; ++j) {
+      if (j == k) continue;
+      a *= (-1.0L - x[j]) / (x[k] - x[j]);
+      b *= (1.0L - x[j]) / (x[k] - x[j]);
+    }
+    rL[k] = (double)a;
+    rR[k] = (double)b;
+  }
   return 0;
 }
 
@@ -279,6 +338,24 @@ void orc_entropy_vars(int dim, double g, const double *u, double *w) {
   w[0] = (g - s) / (g - 1.0) - 0.5 * rho * v2 / p;
   for (int m = 0; m < dim; ++m) w[1 + m] = rho * v[m] / p;
   w[dim + 1] = -rho / p;
+}
+
+/* inverse of orc_entropy_vars: u(w) for the same entropy (R2).  With
+ * beta = -w_E = rho/p: v = w_m/beta, s = gamma - (gamma-1)(w_0 + beta|v|^2/2),
+ * ln p = (s + gamma ln beta)/(1 - gamma), rho = beta p. */
+void orc_cons_from_entropy(int dim, double g, const double *w, double *u) {
+  double beta = -w[dim + 1];
+  double v[3] = {0.0, 0.0, 0.0}, v2 = 0.0;
+  for (int m = 0; m < dim; ++m) {
+    v[m] = w[1 + m] / beta;
+    v2 += v[m] * v[m];
+  }
+  double s = g - (g - 1.0) * (w[0] + 0.5 * beta * v2);
+  double p = exp((s + g * log(beta)) / (1.0 - g));
+  double rho = beta * p;
+  u[0] = rho;
+  for (int m = 0; m < dim; ++m) u[1 + m] = rho * v[m];
+  u[dim + 1] = p / (g - 1.0) + 0.5 * rho * v2;
 }
 
 /* entropy U and entropy flux in direction n: F.n = U (v.n) (R2) */
@@ -445,7 +522,12 @@ orc_mesh *orc_mesh_new(const orc_desc *desc, const double *coords) {
   m->nn = ipow(m->N, desc->dim);
   m->ne = (int64_t)m->d.n[0] * m->d.n[1] * m->d.n[2];
   m->nv = desc->dim + 2;
-  orc_lgl(desc->p, m->xi, m->w, m->D);
+  if (desc->nodes == 1) {
+    if (desc->warp != 0.0 || coords) { free(m); return NULL; } /* affine only */
+    orc_gauss(desc->p, m->xi, m->w, m->D, m->rL, m->rR);
+  } else {
+    orc_lgl(desc->p, m->xi, m->w, m->D);
+  }
   m->x = (double *)malloc(sizeof(double) * m->ne * desc->dim * m->nn);
   m->Ja = (double *)malloc(sizeof(double) * m->ne * 9 * m->nn);
   m->J = (double *)malloc(sizeof(double) * m->ne * m->nn);
@@ -566,16 +648,123 @@ static void rhs_element(const orc_mesh *m, const double *u, double *du, int64_t 
   }
 }
 
+/* Entropy-projected state at the face point of a line (Sec. 5): w along the
+ * line of element e through the multi-index idx in direction n, interpolated
+ * to the end `side` (0: -1, 1: +1), mapped back to conservative variables. */
+static void projected_face_state(const orc_mesh *m, const double *u, int64_t e, const int idx[3], int n,
+                                 int side, double *ut) {
+  const int dim = m->d.dim, N = m->N, nv = m->nv;
+  double wf[5] = {0, 0, 0, 0, 0};
+  for (int k = 0; k < N; ++k) {
+    int jdx[3];
+    memcpy(jdx, idx, 3 * sizeof(int));
+    jdx[n] = k;
+    double uk[5], wk[5];
+    gather(m, u, e, node_of(N, dim, jdx), uk);
+    orc_entropy_vars(dim, m->d.gamma, uk, wk);
+    const double r = side ? m->rR[k] : m->rL[k];
+    for (int v = 0; v < nv; ++v) wf[v] += r * wk[v];
+  }
+  orc_cons_from_entropy(dim, m->d.gamma, wf, ut);
+}
+
+/* Legendre-Gauss collocation, hybridised form (Sec. 5):
+ *   du/dt = -(1/J) [ M^-1 [I; R]^T f_hyb + M^-1 R^T B f_num ],
+ *   f_hyb_a = sum_n sum_b 2 (Q_h,n)_ab f(u~_a, u~_b),
+ *   Q_h = 1/2 [[M D - (M D)^T, R^T B], [-B R, 0]],  u~ = [u; u(R w(u))],
+ * per line of an affine element (the tensor-product factors of M, B and the
+ * face weights cancel line by line), B = diag(-1, +1) for the face points at
+ * -1 and +1.  With abs_mode the magnitudes of all terms are summed instead
+ * (rounding scale of the result). */
+static void rhs_element_gauss(const orc_mesh *m, const double *u, double *out, int64_t e, int abs_mode) {
+  const int dim = m->d.dim, N = m->N, nn = m->nn, nv = m->nv;
+  const double g = m->d.gamma;
+  const int NH = N + 2;
+  double acc[5 * 4096];
+  memset(acc, 0, sizeof(double) * nv * nn);
+  double Q[(ORC_MAXN + 2) * (ORC_MAXN + 2)];
+  for (int a = 0; a < NH * NH; ++a) Q[a] = 0.0;
+  for (int i = 0; i < N; ++i)
+    for (int k = 0; k < N; ++k)
+      Q[i * NH + k] = 0.5 * (m->w[i] * m->D[i * N + k] - m->w[k] * m->D[k * N + i]);
+  for (int k = 0; k < N; ++k) {
+    Q[k * NH + N] = 0.5 * (-m->rL[k]);      /* (R^T B)_{k,L} / 2 */
+    Q[k * NH + N + 1] = 0.5 * (m->rR[k]);   /* (R^T B)_{k,R} / 2 */
+    Q[N * NH + k] = 0.5 * (m->rL[k]);       /* (-B R)_{L,k} / 2 */
+    Q[(N + 1) * NH + k] = 0.5 * (-m->rR[k]); /* (-B R)_{R,k} / 2 */
+  }
+  for (int n = 0; n < dim; ++n) {
+    double a[3];
+    ja_row(m, e, n, 0, a); /* affine: one contravariant vector per direction */
+    /* every line in direction n: the nodes with idx[n] = 0 start one */
+    for (int i0 = 0; i0 < nn; ++i0) {
+      int idx[3];
+      node_index(N, dim, i0, idx);
+      if (idx[n] != 0) continue;
+      double ut[ORC_MAXN + 2][5];
+      int node[ORC_MAXN];
+      for (int k = 0; k < N; ++k) {
+        int jdx[3];
+        memcpy(jdx, idx, sizeof(jdx));
+        jdx[n] = k;
+        node[k] = node_of(N, dim, jdx);
+        gather(m, u, e, node[k], ut[k]);
+      }
+      projected_face_state(m, u, e, idx, n, 0, ut[N]);
+      projected_face_state(m, u, e, idx, n, 1, ut[N + 1]);
+      /* neighbours' face states at the same two points */
+      double un_L[5], un_R[5];
+      projected_face_state(m, u, neighbour(&m->d, e, n, -1), idx, n, 1, un_L);
+      projected_face_state(m, u, neighbour(&m->d, e, n, +1), idx, n, 0, un_R);
+      double fh[ORC_MAXN + 2][5];
+      for (int x = 0; x < NH; ++x) {
+        for (int v = 0; v < nv; ++v) fh[x][v] = 0.0;
+        for (int y = 0; y < NH; ++y) {
+          if (Q[x * NH + y] == 0.0) continue;
+          double f[5];
+          orc_two_point(m->d.vol_flux, dim, g, ut[x], ut[y], a, f);
+          for (int v = 0; v < nv; ++v) {
+            const double t = 2.0 * Q[x * NH + y] * f[v];
+            fh[x][v] += abs_mode ? fabs(t) : t;
+          }
+        }
+      }
+      double fL[5], fR[5];
+      orc_two_point(m->d.surf_flux, dim, g, un_L, ut[N], a, fL);     /* face at -1: (neighbour, own) */
+      orc_two_point(m->d.surf_flux, dim, g, ut[N + 1], un_R, a, fR); /* face at +1: (own, neighbour) */
+      for (int k = 0; k < N; ++k)
+        for (int v = 0; v < nv; ++v) {
+          double t[5] = {fh[k][v], m->rL[k] * fh[N][v], m->rR[k] * fh[N + 1][v], -m->rL[k] * fL[v],
+                         m->rR[k] * fR[v]};
+          double sum = 0.0;
+          for (int q = 0; q < 5; ++q) sum += abs_mode ? fabs(t[q]) : t[q];
+          acc[v * nn + node[k]] += sum / m->w[k];
+        }
+    }
+  }
+  for (int i = 0; i < nn; ++i) {
+    const double Ji = m->J[e * nn + i];
+    for (int v = 0; v < nv; ++v)
+      out[(e * nv + v) * nn + i] = abs_mode ? acc[v * nn + i] / fabs(Ji) : -acc[v * nn + i] / Ji;
+  }
+}
+
 void orc_rhs(const orc_mesh *m, const double *u, double *du) {
 #pragma omp parallel for schedule(static)
-  for (int64_t e = 0; e < m->ne; ++e) rhs_element(m, u, du, e);
+  for (int64_t e = 0; e < m->ne; ++e) {
+    if (m->d.nodes == 1) rhs_element_gauss(m, u, du, e, 0);
+    else rhs_element(m, u, du, e);
+  }
 }
 
 /* RHS of the listed elements only (du has the full layout; other elements
  * are left untouched) -- for sampled checks of large meshes */
 void orc_rhs_elements(const orc_mesh *m, const double *u, double *du, const int64_t *elems, int64_t count) {
 #pragma omp parallel for schedule(dynamic)
-  for (int64_t q = 0; q < count; ++q) rhs_element(m, u, du, elems[q]);
+  for (int64_t q = 0; q < count; ++q) {
+    if (m->d.nodes == 1) rhs_element_gauss(m, u, du, elems[q], 0);
+    else rhs_element(m, u, du, elems[q]);
+  }
 }
 
 /* Rounding scale of RHS_i: the same sums as orc_rhs with every term replaced
@@ -631,12 +820,18 @@ static void scale_element(const orc_mesh *m, const double *u, double *sc, int64_
 
 void orc_rhs_scale(const orc_mesh *m, const double *u, double *sc) {
 #pragma omp parallel for schedule(static)
-  for (int64_t e = 0; e < m->ne; ++e) scale_element(m, u, sc, e);
+  for (int64_t e = 0; e < m->ne; ++e) {
+    if (m->d.nodes == 1) rhs_element_gauss(m, u, sc, e, 1);
+    else scale_element(m, u, sc, e);
+  }
 }
 
 void orc_rhs_scale_elements(const orc_mesh *m, const double *u, double *sc, const int64_t *elems, int64_t count) {
 #pragma omp parallel for schedule(dynamic)
-  for (int64_t q = 0; q < count; ++q) scale_element(m, u, sc, elems[q]);
+  for (int64_t q = 0; q < count; ++q) {
+    if (m->d.nodes == 1) rhs_element_gauss(m, u, sc, elems[q], 1);
+    else scale_element(m, u, sc, elems[q]);
+  }
 }
 
 /* ------------------------------------------------------------------------ */
