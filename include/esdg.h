@@ -81,7 +81,21 @@ typedef struct {
   int32_t surface_flux;     /* esdg_flux: any */
   int32_t precision;        /* esdg_precision of the internal state and fluxes */
   void *stream;             /* hipStream_t for all device work; NULL = default */
+  int32_t nodes;            /* esdg_nodes: LGL (flux-differencing DGSEM, Sec. 2) or
+                               GAUSS (Legendre-Gauss collocation with entropy
+                               projection, Sec. 5; affine meshes only: warp = 0,
+                               coords = NULL) */
+  int32_t pad;
 } esdg_mesh_desc;
+
+/* Nodes of the element: Legendre-Gauss-Lobatto (the volume nodes include the
+ * element boundary) or Legendre-Gauss collocation in the hybridised form of
+ * Sec. 5: du/dt = -[M^-1 [I; R]^T f_h + M^-1 R^T B f*] with
+ * f_h = sum_n 2 Q_h,n o F(u~, u~) over the volume nodes and the face points,
+ * Q_h the hybridised SBP operator and u~ = [u; u(R w(u))] the entropy
+ * projection (face states from the interpolated entropy variables).  The state
+ * layout is the same; node coordinates are the Gauss points. */
+typedef enum { ESDG_NODES_LGL = 0, ESDG_NODES_GAUSS = 1 } esdg_nodes;
 
 #define ESDG_PMAX 7
 
@@ -150,8 +164,9 @@ esdg_status esdg_sync(esdg_problem *prob);
  * every launch of the listed kernels is bracketed by an event pair.
  * esdg_timing_read returns the summed duration (ms) and launch count since
  * the last reset, synchronising the stream.  STAGE is the fused
- * right-hand-side / RK-stage kernel, REDUCE the FP64 reductions. */
-typedef enum { ESDG_KERNEL_STAGE = 1, ESDG_KERNEL_REDUCE = 2 } esdg_kernel;
+ * right-hand-side / RK-stage kernel, REDUCE the FP64 reductions, PROJECT the
+ * entropy projection of Gauss problems. */
+typedef enum { ESDG_KERNEL_STAGE = 1, ESDG_KERNEL_REDUCE = 2, ESDG_KERNEL_PROJECT = 3 } esdg_kernel;
 esdg_status esdg_timing_enable(esdg_problem *prob, int32_t enable);
 esdg_status esdg_timing_read(esdg_problem *prob, int32_t kernel, double *total_ms,
                              int64_t *launches);
@@ -160,8 +175,8 @@ esdg_status esdg_timing_reset(esdg_problem *prob);
 /* Tile variants of the fused stage kernel (workgroup shapes: elements per
  * workgroup and lanes per direction).  Every variant computes bit-identical
  * results; only the speed differs.  The variant in use is chosen per
- * (dim, p, volume flux, mesh kind, precision) in a process-wide table,
- * variant 0 until changed.  2D problems have variant 0 only.
+ * (dim, p, volume flux, mesh kind, precision, node kind) in a process-wide
+ * table, variant 0 until changed.  2D and Gauss problems have variant 0 only.
  *   esdg_autotune: times every variant on the problem's current state (reps
  *     right-hand-side launches each, written to internal scratch; the state
  *     is unchanged), stores the fastest in the table and returns it in *best
@@ -183,7 +198,8 @@ esdg_status esdg_footprint(const esdg_mesh_desc *desc, int64_t *bytes);
 
 /* ---- batches: several problems advanced together ------------------------
  * A batch groups problems by (dim, p, volume and surface flux, mesh kind,
- * precision, gamma); each RK stage is one launch per group over the
+ * precision, node kind, gamma); each RK stage is one launch per group (two
+ * for Gauss groups: projection, then stage) over the
  * element tiles of all its problems.  Every problem computes exactly what it
  * computes alone (same kernels, same per-element arithmetic): states, times
  * and CFL steps are bit-identical to esdg_step on the problem by itself.

@@ -318,7 +318,7 @@ esdg_status esdg_batch_create(esdg_problem* const* probs, int32_t count, const d
     for (auto& g : b->groups) {
       const esdg_problem* R = g.rep;
       if (R->dim == P->dim && R->p == P->p && R->vf == P->vf && R->sf == P->sf && R->mesh == P->mesh &&
-          R->prec == P->prec && R->gamma == P->gamma) {
+          R->prec == P->prec && R->gamma == P->gamma && R->nodes == P->nodes) {
         hit = &g;
         break;
       }

@@ -65,11 +65,11 @@ esdg_status launch_kernel(const Launcher& L, int kind, const void* fn, dim3 grid
 // ---- tile-variant table (autotuner results), keyed by the kernel parameters
 namespace {
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int>, int> g_tune;
+std::map<std::tuple<int, int, int, int, int, int>, int> g_tune;
 int g_tune_version = 0;
 
-std::tuple<int, int, int, int, int> tune_key(const esdg_problem* P) {
-  return std::make_tuple(P->dim, P->N, P->vf, P->mesh, P->prec);
+std::tuple<int, int, int, int, int, int> tune_key(const esdg_problem* P) {
+  return std::make_tuple(P->dim, P->N, P->vf, P->mesh, P->prec, P->nodes);
 }
 }  // namespace
 
@@ -91,8 +91,19 @@ static void set_tile_variant(const esdg_problem* P, int v) {
   cur = v;
 }
 
+// stage kernel of tile variant v for P (Gauss collocation has variant 0 only)
+static VolKernel kernel_of_variant(const esdg_problem* P, int v) {
+  if (P->nodes == NODES_GAUSS) return v == 0 ? gauss_kernel_for(P->prec, P->dim, P->N, P->vf, false) : VolKernel{};
+  return stage_kernel_for(P->prec, P->dim, P->N, P->vf, P->mesh, v);
+}
+
 VolKernel pick_stage_kernel(const esdg_problem* P) {
-  return stage_kernel_for(P->prec, P->dim, P->N, P->vf, P->mesh, tile_variant_of(P));
+  return kernel_of_variant(P, P->nodes == NODES_GAUSS ? 0 : tile_variant_of(P));
+}
+
+VolKernel pick_projection_kernel(const esdg_problem* P) {
+  if (P->nodes != NODES_GAUSS) return VolKernel{};
+  return gauss_kernel_for(P->prec, P->dim, P->N, P->vf, true);
 }
 
 template <typename Real>
@@ -195,8 +206,8 @@ esdg_status set_time(esdg_problem* P, double t) {
 }
 
 void free_buffers(esdg_problem* P) {
-  void* bufs[] = {P->U, P->Y, P->Y2, P->R, P->DU, P->STAGE64, P->METRIC, P->NFACE, P->PARTIAL, P->SCAL, P->LAM, P->FLAG,
-                  P->DESC};
+  void* bufs[] = {P->U,       P->Y,    P->Y2,   P->R,   P->DU,   P->STAGE64, P->METRIC,
+                  P->NFACE,   P->PARTIAL, P->SCAL, P->LAM, P->FLAG, P->DESC,    P->FACEB};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& t : P->launches) {
@@ -244,6 +255,9 @@ static esdg_status check_desc(const esdg_mesh_desc* d) {
   if (d->surface_flux < 0 || d->surface_flux > 3) return fail(nullptr, ESDG_EINVAL, "unknown surface flux");
   if (d->precision != ESDG_FP64 && d->precision != ESDG_FP32)
     return fail(nullptr, ESDG_EINVAL, "unknown precision");
+  if (d->nodes != ESDG_NODES_LGL && d->nodes != ESDG_NODES_GAUSS) return fail(nullptr, ESDG_EINVAL, "unknown node kind");
+  if (d->nodes == ESDG_NODES_GAUSS && (d->warp != 0.0 || d->coords))
+    return fail(nullptr, ESDG_EINVAL, "Gauss collocation is available on affine meshes only (warp 0, no coords)");
   int64_t ne = 1;
   for (int j = 0; j < d->dim; ++j) {
     if (d->n[j] < 1) return fail(nullptr, ESDG_EINVAL, "element counts must be >= 1");
@@ -275,6 +289,7 @@ esdg_status esdg_footprint(const esdg_mesh_desc* d, int64_t* bytes) {
   int64_t b = 5 * ns * rs;
   if (d->precision == ESDG_FP32) b += ns * 8;
   if (d->warp != 0.0 || d->coords) b += (E * (d->dim * d->dim + 1) * nn + (int64_t)d->dim * E * d->dim * nf) * rs;
+  if (d->nodes == ESDG_NODES_GAUSS) b += E * 2 * d->dim * (d->dim + 4) * nf * rs;
   int blocks;
   int64_t per;
   reduction_blocks(E * nn, &blocks, &per);
@@ -308,8 +323,11 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
   P->rsize = P->prec == PREC_FP32 ? 4 : 8;
   P->gamma = d->gamma;
   P->stream = (hipStream_t)d->stream;
+  P->nodes = d->nodes == ESDG_NODES_GAUSS ? NODES_GAUSS : NODES_LGL;
   std::string err;
-  if (!make_operators(d->p, &P->ops, &err) || !make_geometry(P->spec, P->ops, &P->geo, &err)) {
+  const bool ops_ok =
+      P->nodes == NODES_GAUSS ? make_gauss_operators(d->p, &P->ops, &err) : make_operators(d->p, &P->ops, &err);
+  if (!ops_ok || !make_geometry(P->spec, P->ops, &P->geo, &err)) {
     esdg_status st = fail(nullptr, ESDG_EINVAL, "%s", err.c_str());
     delete P;
     return st;
@@ -347,6 +365,12 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
       delete P;
       return fail(nullptr, ESDG_ENOMEM, "device allocation of %zu bytes failed", a.bytes);
     }
+  }
+  if (P->nodes == NODES_GAUSS &&
+      hipMalloc(&P->FACEB, (size_t)P->E * 2 * P->dim * (P->dim + 4) * P->nf * P->rsize) != hipSuccess) {
+    free_buffers(P);
+    delete P;
+    return fail(nullptr, ESDG_ENOMEM, "device allocation of the face states failed");
   }
   if (P->prec == PREC_FP32 && hipMalloc((void**)&P->STAGE64, state_count(P) * sizeof(double)) != hipSuccess) {
     free_buffers(P);
@@ -588,7 +612,7 @@ esdg_status esdg_get_tile_variant(const esdg_problem* P, int32_t* variant, int32
 
 esdg_status esdg_set_tile_variant(esdg_problem* P, int32_t variant) {
   if (!P) return fail(nullptr, ESDG_EINVAL, "NULL problem handle");
-  if (!stage_kernel_for(P->prec, P->dim, P->N, P->vf, P->mesh, variant).fn)
+  if (!kernel_of_variant(P, variant).fn)
     return fail(P, ESDG_EINVAL, "tile variant %d does not exist for dim=%d p=%d", variant, P->dim, P->p);
   set_tile_variant(P, variant);
   return ESDG_OK;
@@ -612,7 +636,7 @@ esdg_status esdg_autotune(esdg_problem* P, int32_t reps, int32_t* best, double* 
   for (int v = 0; v < ESDG_TILE_VARIANTS && st == ESDG_OK; ++v) {
     us[v] = -1.0;
     epb[v] = 0;
-    const VolKernel k = stage_kernel_for(P->prec, P->dim, P->N, P->vf, P->mesh, v);
+    const VolKernel k = kernel_of_variant(P, v);
     if (!k.fn) continue;
     epb[v] = k.epb;
     int same = -1;

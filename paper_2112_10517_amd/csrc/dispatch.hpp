@@ -22,6 +22,11 @@ VolKernel stage_kernel_3d_f64(int N, int vf, int mesh, int variant);
 VolKernel stage_kernel_3d_f32(int N, int vf, int mesh, int variant);
 VolKernel stage_kernel_3d_f64_tuned(int N, int vf, int mesh, int variant);
 VolKernel stage_kernel_3d_f32_tuned(int N, int vf, int mesh, int variant);
+// Legendre-Gauss collocation (affine meshes): the stage kernel, or with
+// project = true the entropy-projection kernel that precedes it
+VolKernel gauss_kernel_for(int prec, int dim, int N, int vf, bool project);
+VolKernel gauss_kernel_f64(int dim, int N, int vf, bool project);
+VolKernel gauss_kernel_f32(int dim, int N, int vf, bool project);
 const void* reduce_partial_for(int prec, int dim, int mesh, int op);
 const void* reduce_final_for(int op);
 const void* convert_kernel_for(int to_fp64);  // elementwise precision casts

@@ -46,6 +46,11 @@ VolKernel stage_kernel_for(int prec, int dim, int N, int vf, int mesh, int varia
   return VolKernel{};
 }
 
+VolKernel gauss_kernel_for(int prec, int dim, int N, int vf, bool project) {
+  if (dim != 2 && dim != 3) return VolKernel{};
+  return prec == PREC_FP32 ? gauss_kernel_f32(dim, N, vf, project) : gauss_kernel_f64(dim, N, vf, project);
+}
+
 const void* reduce_partial_for(int prec, int dim, int mesh, int op) {
   if (prec == PREC_FP32) return dim == 2 ? reduce_pick<2, float>(mesh, op) : reduce_pick<3, float>(mesh, op);
   return dim == 2 ? reduce_pick<2, double>(mesh, op) : reduce_pick<3, double>(mesh, op);

@@ -118,6 +118,84 @@ bool make_operators(int p, Operators* ops, std::string* err) {
   return true;
 }
 
+bool make_gauss_operators(int p, Operators* ops, std::string* err) {
+  if (p < 1 || p + 1 > kMaxN) {
+    *err = "polynomial degree must be in [1, 7]";
+    return false;
+  }
+  const int N = p + 1;
+  // Gauss nodes = roots of P_N: eigenvalues of the Jacobi matrix of the
+  // Legendre recurrence (zero diagonal, off-diagonal k/sqrt(4k^2-1)), by
+  // bisection on the Sturm count, polished by Newton on P_N.
+  long double e[kMaxN];
+  for (int k = 1; k < N; ++k) e[k - 1] = (long double)k / sqrtl(4.0L * k * k - 1.0L);
+  long double x[kMaxN];
+  for (int r = 0; r < N; ++r) {
+    long double a = -1.0L, b = 1.0L;
+    for (int it = 0; it < 200 && b - a > 1e-19L; ++it) {
+      long double c = 0.5L * (a + b);
+      if (sturm_count(e, N, c) > r) b = c; else a = c;
+    }
+    long double t = 0.5L * (a + b);
+    for (int it = 0; it < 3; ++it) {
+      long double d1, d2;
+      legendre_derivs(N, t, &d1, &d2);
+      const long double P = legendre_p(N, t);
+      if (d1 != 0.0L) t -= P / d1;
+    }
+    x[r] = t;
+  }
+  for (int i = 0; i < N / 2; ++i) {
+    long double h = 0.5L * (x[N - 1 - i] - x[i]);
+    x[i] = -h;
+    x[N - 1 - i] = h;
+  }
+  if (N % 2) x[N / 2] = 0.0L;
+  long double bw[kMaxN], wl[kMaxN];
+  for (int i = 0; i < N; ++i) {
+    long double d1, d2;
+    legendre_derivs(N, x[i], &d1, &d2);
+    wl[i] = 2.0L / ((1.0L - x[i] * x[i]) * d1 * d1);
+    ops->x[i] = (double)x[i];
+    ops->w[i] = (double)wl[i];
+    long double prod = 1.0L;
+    for (int j = 0; j < N; ++j)
+      if (j != i) prod *= (x[i] - x[j]);
+    bw[i] = 1.0L / prod;
+  }
+  long double Dl[kMaxN * kMaxN];
+  for (int i = 0; i < N; ++i) {
+    long double diag = 0.0L;
+    for (int j = 0; j < N; ++j) {
+      if (j == i) continue;
+      const long double v = (bw[j] / bw[i]) / (x[i] - x[j]);
+      Dl[i * N + j] = v;
+      diag -= v;
+    }
+    Dl[i * N + i] = diag;
+  }
+  // Lagrange basis at the ends, barycentric form l_k(s) = (bw_k/(s-x_k)) / sum_j bw_j/(s-x_j)
+  for (int side = 0; side < 2; ++side) {
+    const long double s = side ? 1.0L : -1.0L;
+    long double den = 0.0L;
+    for (int j = 0; j < N; ++j) den += bw[j] / (s - x[j]);
+    for (int k = 0; k < N; ++k) (side ? ops->rR : ops->rL)[k] = (double)((bw[k] / (s - x[k])) / den);
+  }
+  // T = M^-1 (M D - (M D)^T) with an exact zero diagonal; M^-1 R^T B
+  for (int i = 0; i < N; ++i) {
+    for (int k = 0; k < N; ++k) {
+      ops->D[i * N + k] = (double)Dl[i * N + k];
+      ops->Dt[i * N + k] = i == k ? 0.0 : (double)((wl[i] * Dl[i * N + k] - wl[k] * Dl[k * N + i]) / wl[i]);
+    }
+    ops->cL[i] = (double)(-(long double)ops->rL[i] / wl[i]);
+    ops->cR[i] = (double)((long double)ops->rR[i] / wl[i]);
+  }
+  ops->p = p;
+  ops->N = N;
+  ops->gauss = true;
+  return true;
+}
+
 namespace {
 
 inline int ipow(int b, int k) {

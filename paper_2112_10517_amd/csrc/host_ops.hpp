@@ -12,14 +12,24 @@ constexpr int kMaxN = 8;  // nodes per line: degree <= 7
 
 // 1D Legendre-Gauss-Lobatto operators of degree p (Sec. 2, LGL-DGSEM example)
 // and the flux-differencing operator D~ = 2D - M^-1 B of Sec. 2.1.
+//
+// Legendre-Gauss collocation (Sec. 5) uses the Gauss nodes and weights, D on
+// them, the Lagrange basis at the element ends rL, rR (operator R) and, in the
+// slot of D~, T = M^-1 (M D - (M D)^T): the volume block of the hybridised
+// operator 2 Q_h scaled by M^-1 (zero diagonal), with the face coefficients
+// cL = -rL / w and cR = rR / w (M^-1 R^T B).
 struct Operators {
   int p = 0, N = 0;
+  bool gauss = false;
   double x[kMaxN] = {}, w[kMaxN] = {};
   double D[kMaxN * kMaxN] = {};   // row-major D[i*N+j]
-  double Dt[kMaxN * kMaxN] = {};  // D~, exact zero diagonal
+  double Dt[kMaxN * kMaxN] = {};  // LGL: D~; Gauss: T; exact zero diagonal
+  double rL[kMaxN] = {}, rR[kMaxN] = {};  // Gauss: Lagrange basis at -1, +1
+  double cL[kMaxN] = {}, cR[kMaxN] = {};  // Gauss: -rL/w, rR/w
 };
 
 bool make_operators(int p, Operators* ops, std::string* err);
+bool make_gauss_operators(int p, Operators* ops, std::string* err);
 
 // Mesh description as the library sees it (a copy of the ABI descriptor).
 struct MeshSpec {

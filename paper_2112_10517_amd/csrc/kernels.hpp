@@ -40,10 +40,16 @@ constexpr int kLamSlots = 64;  // CFL maxima are spread over this many slots (at
 
 template <typename Real>
 struct StageOps {
-  Real Dt[kDevMaxN * kDevMaxN];  // D~ row-major
+  Real Dt[kDevMaxN * kDevMaxN];  // LGL: D~; Gauss: T = M^-1 (M D - (M D)^T); row-major
   Real inv_w0, inv_wp;           // 1/w_0, 1/w_p
   Real gamma, inv_gm1;           // gamma, 1/(gamma-1)
+  // Gauss collocation: Lagrange basis at -1 / +1 (R) and M^-1 R^T B, and R
+  // in FP64 for the entropy projection
+  Real rL[kDevMaxN], rR[kDevMaxN], cL[kDevMaxN], cR[kDevMaxN];
+  double r64[2][kDevMaxN];
 };
+
+enum NodeKind { NODES_LGL = 0, NODES_GAUSS = 1 };
 
 // One problem of a launch (device memory).  A launch covers the tiles of one
 // or more problems of equal degree, flux, mesh kind and precision; a problem
@@ -56,6 +62,7 @@ struct ProbDesc {
   unsigned long long* lam;   // CFL: 2 x kLamSlots slots by step parity (bit patterns of non-negative doubles)
   double* time;              // time of the state, 2 slots by step parity
   int* flag;                 // non-physical state flag
+  Real* faceb;               // Gauss: entropy-projected face states [E][2 dim][dim+4][nf] (rho, v, p, log rho, log p)
   double t_end;              // a step never passes t_end: dt = min(dt, t_end - t)
   int E, n0, n1, n2;         // elements, per direction
   int tile0;                 // first tile of this problem in the launch
@@ -105,6 +112,8 @@ template <> struct LogMeanEps<float> { static constexpr float value = 2.0e-2f; }
 
 __device__ __forceinline__ double dev_log(double x) { return log(x); }
 __device__ __forceinline__ float dev_log(float x) { return logf(x); }
+__device__ __forceinline__ double dev_exp(double x) { return exp(x); }
+__device__ __forceinline__ float dev_exp(float x) { return expf(x); }
 
 // Reciprocal: hardware estimate refined by Newton's iteration r <- r(2 - q r)
 // written as two fused multiply-adds (two steps in FP64; the FP32 estimate
@@ -248,6 +257,35 @@ __device__ __forceinline__ void surface_flux(int sf, const Real* uL, const Real*
   }
 }
 
+// f*(u_L, u_R, n) of kind sf from primitive states with their logarithms
+// (Gauss collocation: the face states are entropy projections, Sec. 5)
+template <int DIM, typename Real>
+__device__ __forceinline__ void surface_flux_prim(int sf, const Prim<Real>& PL, const Prim<Real>& PR, Real nx,
+                                                  Real ny, Real nz, Real gamma, Real inv_gm1, Real* F) {
+  if (sf == SF_RANOCHA) {
+    volume_flux<VF_RANOCHA, DIM>(PL, PR, nx, ny, nz, inv_gm1, F);
+  } else if (sf == SF_SHIMA) {
+    volume_flux<VF_SHIMA, DIM>(PL, PR, nx, ny, nz, inv_gm1, F);
+  } else {
+    volume_flux<VF_CENTRAL, DIM>(PL, PR, nx, ny, nz, inv_gm1, F);
+    if (sf == SF_LLF) {
+      const Real vnL = PL.v0 * nx + PL.v1 * ny + PL.v2 * nz;
+      const Real vnR = PR.v0 * nx + PR.v1 * ny + PR.v2 * nz;
+      const Real cL = sqrt(gamma * PL.p * dev_rcp(PL.rho)), cR = sqrt(gamma * PR.p * dev_rcp(PR.rho));
+      const Real nn = sqrt(nx * nx + ny * ny + nz * nz);
+      const Real lam = fmax(fabs(vnL), fabs(vnR)) + fmax(cL, cR) * nn;
+      const Real h = Real(0.5) * lam;
+      F[0] -= h * (PR.rho - PL.rho);
+      F[1] -= h * (PR.rho * PR.v0 - PL.rho * PL.v0);
+      if (DIM > 1) F[DIM > 1 ? 2 : 0] -= h * (PR.rho * PR.v1 - PL.rho * PL.v1);
+      if (DIM > 2) F[DIM > 2 ? 3 : 0] -= h * (PR.rho * PR.v2 - PL.rho * PL.v2);
+      const Real eL = PL.p * inv_gm1 + Real(0.5) * PL.rho * (PL.v0 * PL.v0 + PL.v1 * PL.v1 + PL.v2 * PL.v2);
+      const Real eR = PR.p * inv_gm1 + Real(0.5) * PR.rho * (PR.v0 * PR.v0 + PR.v1 * PR.v1 + PR.v2 * PR.v2);
+      F[DIM + 1] -= h * (eR - eL);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // fused stage kernel
 // ---------------------------------------------------------------------------
@@ -330,15 +368,38 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
   return b < (q << 3) ? (b & 7) * q + (b >> 3) : b;
 }
 
+// primitive state (rho, v_1..v_d, p, log rho, log p) stored as dim+4 values
+template <int DIM, typename Real>
+__device__ __forceinline__ Prim<Real> unpack_prim(const Real* f) {
+  Prim<Real> P;
+  P.rho = f[0];
+  P.v0 = f[1];
+  P.v1 = DIM > 1 ? f[DIM > 1 ? 2 : 1] : Real(0);
+  P.v2 = DIM > 2 ? f[DIM > 2 ? 3 : 1] : Real(0);
+  P.p = f[DIM + 1];
+  P.lr = f[DIM + 2];
+  P.lp = f[DIM + 3];
+  return P;
+}
+
 // The i<k pairs of one line in direction DIR: the lane loads the line's
 // primitive variables (LDS) and averaged contravariant vectors, evaluates each
 // two-point flux once and scatters D~_ik F to node i and D~_ki F to node k in
 // registers (skew-symmetric D~ with zero diagonal, Sec. 2.2; all indices are
 // compile-time constants).
-template <int DIR, int DIM, int N, int VF, int MESH, typename Real>
+//
+// Gauss collocation (NODES_GAUSS, affine): the line is the volume block of
+// the hybridised operator and its two face points carry the entropy-projected
+// states fo[0] (end at -1) and fo[1] (end at +1); fn holds the neighbours'
+// states at the same points.  Besides the volume pairs (T in the D~ slot) the
+// lane evaluates f(u_k, u~_f) for every node k and both ends, adds
+// M^-1 R^T B (f(u_k, u~_f) - sum_j R_fj f(u_j, u~_f) + f*_f), i.e. the
+// face-point rows of 2 Q_h lifted by R^T and the surface term of Sec. 5.
+template <int DIR, int DIM, int N, int VF, int MESH, typename Real, int NODES = NODES_LGL>
 __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value], const Real (&nrm)[N][3], int base,
                                             const StageOps<Real>& ops, const Real* s_dt, Real scale,
-                                            Real (&A)[N][DIM + 2]) {
+                                            Real (&A)[N][DIM + 2], const Real (*fo)[DIM + 4] = nullptr,
+                                            const Real (*fn)[DIM + 4] = nullptr, int surf = 0) {
   constexpr int NV = DIM + 2;
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int stride = Pow<N, DIR>::value;
@@ -380,6 +441,36 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
       }
     }
   }
+  if constexpr (NODES == NODES_GAUSS) {
+    const Real nx = DIR == 0 ? Real(1) : Real(0), ny = DIR == 1 ? Real(1) : Real(0), nz = DIR == 2 ? Real(1) : Real(0);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const Prim<Real> Pf = unpack_prim<DIM>(fo[s]), Pn = unpack_prim<DIM>(fn[s]);
+      Real Fs[NV], G[NV];
+      // f* oriented along +DIR: at the -1 end the neighbour is on the left
+      if (s) surface_flux_prim<DIM>(surf, Pf, Pn, nx, ny, nz, ops.gamma, ops.inv_gm1, Fs);
+      else surface_flux_prim<DIM>(surf, Pn, Pf, nx, ny, nz, ops.gamma, ops.inv_gm1, Fs);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) G[v] = Real(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        Real F[NV];
+        volume_flux<VF, DIM>(P[k], Pf, nx, ny, nz, ops.inv_gm1, F);
+        const Real c = s ? ops.cR[k] : ops.cL[k], r = s ? ops.rR[k] : ops.rL[k];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          A[k][v] += c * F[v];
+          G[v] += r * F[v];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const Real c = s ? ops.cR[k] : ops.cL[k];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) A[k][v] += c * (Fs[v] - G[v]);
+      }
+    }
+  }
   if (MESH == MESH_AFFINE) {
 #pragma unroll
     for (int k = 0; k < N; ++k)
@@ -396,9 +487,10 @@ struct StageWaves {
   static constexpr int value = (sizeof(Real) == 4 && N == 8 && MESH == MESH_AFFINE) ? 3 : Tile<DIM, N, EPB_>::WPE;
 };
 
-template <int DIM, int N, int VF, int MESH, typename Real, int EPB_>
+template <int DIM, int N, int VF, int MESH, typename Real, int EPB_, int NODES = NODES_LGL>
 __global__ void __launch_bounds__((Tile<DIM, N, EPB_>::THREADS))
 __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))) stage_kernel(StageArgs<Real> a) {
+  static_assert(NODES == NODES_LGL || MESH == MESH_AFFINE, "Gauss collocation is built for affine meshes");
   using T = Tile<DIM, N, EPB_>;
   constexpr int NN = T::NN, NF = T::NF, L = T::L, EPB = T::EPB, NV = T::NV, NFACE = T::NFACE;
   constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, LANES_DIR = T::LANES_DIR;
@@ -482,8 +574,24 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
     for (int t = tid; t < N * N; t += THREADS) s_dt[t] = a.ops.Dt[t];
   __syncthreads();  // s_nbr, s_dt
   Real tL[FPT][NV], tR[FPT][NV], tn[FPT][3];
+  constexpr int NPF = DIM + 4;
+  Real fo[2][NPF], fnb[2][NPF];  // Gauss: own / neighbours' projected states at the line's ends
+  if constexpr (NODES == NODES_GAUSS) {
+    const auto fb = as_global((const Real*)P.faceb);
+    const int e = lactive ? e0 + lel : 0;
 #pragma unroll
-  for (int r = 0; r < FPT; ++r) {
+    for (int sd = 0; sd < 2; ++sd) {
+      const int fc = 2 * ldir + sd;
+      const int en = lactive ? s_nbr[lel][fc] : 0;
+#pragma unroll
+      for (int c = 0; c < NPF; ++c) {
+        fo[sd][c] = fb[(((size_t)e * (2 * DIM) + fc) * NPF + c) * NF + lline];
+        fnb[sd][c] = fb[(((size_t)en * (2 * DIM) + (fc ^ 1)) * NPF + c) * NF + lline];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < FPT && NODES == NODES_LGL; ++r) {
     const int t = tid + r * THREADS;
     const int el = t / NFACE, rr = t - el * NFACE;
     const bool ok = t < EPB * NFACE && e0 + el < E;
@@ -535,9 +643,9 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
     }
   }
 
-  // ---- surface fluxes of the element's faces
+  // ---- surface fluxes of the element's faces (LGL; Gauss lines handle their own ends)
 #pragma unroll
-  for (int r = 0; r < FPT; ++r) {
+  for (int r = 0; r < FPT && NODES == NODES_LGL; ++r) {
     const int t = tid + r * THREADS;
     const int el = t / NFACE, rr = t - el * NFACE;
     if (!(t < EPB * NFACE && e0 + el < E)) continue;
@@ -553,9 +661,11 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
   {
     const Real(*sp)[NN] = s_prim[lactive ? lel : 0];
     const Real sc = P.scale[ldir];
-    if (ldir == 0) line_fluxes<0, DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, s_dt, sc, A);
-    else if (DIM > 1 && ldir == 1) line_fluxes<(DIM > 1 ? 1 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, s_dt, sc, A);
-    else if (DIM > 2) line_fluxes<(DIM > 2 ? 2 : 0), DIM, N, VF, MESH>(sp, nrm, lbase, a.ops, s_dt, sc, A);
+    if (ldir == 0) line_fluxes<0, DIM, N, VF, MESH, Real, NODES>(sp, nrm, lbase, a.ops, s_dt, sc, A, fo, fnb, a.surf);
+    else if (DIM > 1 && ldir == 1)
+      line_fluxes<(DIM > 1 ? 1 : 0), DIM, N, VF, MESH, Real, NODES>(sp, nrm, lbase, a.ops, s_dt, sc, A, fo, fnb, a.surf);
+    else if (DIM > 2)
+      line_fluxes<(DIM > 2 ? 2 : 0), DIM, N, VF, MESH, Real, NODES>(sp, nrm, lbase, a.ops, s_dt, sc, A, fo, fnb, a.surf);
   }
   // RK registers of the owned nodes, in flight while the line sums are merged
   Real ru0[NPT][NV], racc[NPT][NV];
@@ -625,7 +735,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
 #pragma unroll
     for (int v = 0; v < NV; ++v) S[v] = s_acc[el][v][i];
 #pragma unroll
-    for (int dir = 0; dir < DIM; ++dir) {
+    for (int dir = 0; dir < DIM && NODES == NODES_LGL; ++dir) {
       const int id = dir == 0 ? ix : (dir == 1 ? iy : iz);
       if (id != 0 && id != N - 1) continue;
       const int f = dir == 0 ? (iy + N * iz) : (dir == 1 ? (ix + N * iz) : (ix + N * iy));
@@ -702,6 +812,98 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
     }
     if ((tid & 63) == 0)
       atomicMax(lam_next + (blockIdx.x & (kLamSlots - 1)), (unsigned long long)__double_as_longlong(lam_max));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gauss collocation: entropy projection to the face points (Sec. 5)
+// ---------------------------------------------------------------------------
+
+// u~ = u(R w(u)) at every face point of the tile's elements: entropy
+// variables w = ((gamma - s)/(gamma-1) - beta|v|^2/2, beta v, -beta),
+// beta = rho/p, s = ln p - gamma ln rho, at the nodes (LDS); their values at
+// the element ends along each line (rows of R); back to primitive variables
+// with beta = -w_E, v = w_m/beta, s = gamma - (gamma-1)(w_0 + beta|v|^2/2),
+// ln p = (s + gamma ln beta)/(1 - gamma), ln rho = ln beta + ln p.  Written
+// to faceb as (rho, v, p, ln rho, ln p) per face point; launched before each
+// Gauss stage on the same tiles and descriptors.  The projection is evaluated
+// in FP64 for both precisions: the map back from w cancels digits (ln p from
+// s and ln beta), which FP32 would expose at ~1e-6 relative.
+template <int DIM, int N, typename Real>
+__global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) gauss_project_kernel(StageArgs<Real> a) {
+  using T = Tile<DIM, N>;
+  constexpr int NN = T::NN, NF = T::NF, EPB = T::EPB, NV = T::NV, NFACE = T::NFACE;
+  constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT;
+  constexpr int NPF = DIM + 4;
+  __shared__ double s_w[EPB][NV][NN];
+  const int tid = threadIdx.x;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int pi = a.tile_prob ? a.tile_prob[tile] : 0;
+  const ProbDesc<Real>& P = a.probs[pi];
+  const auto uin = as_global((const Real*)P.buf[a.in_idx]);
+  const auto fb = as_global(P.faceb);
+  const int E = P.E;
+  const int e0 = (tile - P.tile0) * EPB;
+  const double g = (double)a.ops.gamma, gm1 = g - 1.0, inv_gm1 = 1.0 / gm1;
+#pragma unroll
+  for (int r = 0; r < NPT; ++r) {
+    const int q = tid + r * THREADS;
+    const int el = q / NN, i = q - el * NN;
+    if (!(q < EPB * NN && e0 + el < E)) continue;
+    const size_t o = (size_t)(e0 + el) * (NV * NN) + i;
+    double u[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = (double)uin[o + (size_t)v * NN];
+    const double ir = dev_rcp(u[0]);
+    double kin = 0.0;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) kin += u[1 + m] * u[1 + m];
+    kin *= ir;  // rho |v|^2
+    const double p = gm1 * (u[DIM + 1] - 0.5 * kin);
+    const double beta = u[0] * dev_rcp(p);
+    const double s = log(p) - g * log(u[0]);
+    s_w[el][0][i] = (g - s) * inv_gm1 - 0.5 * beta * (kin * ir);
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) s_w[el][1 + m][i] = beta * (u[1 + m] * ir);
+    s_w[el][DIM + 1][i] = -beta;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < FPT; ++r) {
+    const int t = tid + r * THREADS;
+    const int el = t / NFACE, rr = t - el * NFACE;
+    if (!(t < EPB * NFACE && e0 + el < E)) continue;
+    const int fc = rr / NF, f = rr - fc * NF, dir = fc >> 1, side = fc & 1;
+    double w[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = 0.0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const double rk = a.ops.r64[side][k];
+      const int q = face_node<N>(dir, f, k);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) w[v] += rk * s_w[el][v][q];
+    }
+    const double beta = -w[DIM + 1], ib = dev_rcp(beta);
+    double vel[3] = {0.0, 0.0, 0.0}, v2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) {
+      vel[m] = w[1 + m] * ib;
+      v2 += vel[m] * vel[m];
+    }
+    const double s = g - gm1 * (w[0] + 0.5 * beta * v2);
+    const double lb = log(beta);
+    const double lp = (s + g * lb) / (1.0 - g);
+    const double lr = lb + lp;
+    const double rho = exp(lr), p = exp(lp);
+    if (!(beta > 0.0) || !isfinite(rho + p)) atomicOr(P.flag, 1);
+    const size_t o = (((size_t)(e0 + el) * (2 * DIM) + fc) * NPF) * NF + f;
+    fb[o] = (Real)rho;
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) fb[o + (size_t)(1 + m) * NF] = (Real)vel[m];
+    fb[o + (size_t)(DIM + 1) * NF] = (Real)p;
+    fb[o + (size_t)(DIM + 2) * NF] = (Real)lr;
+    fb[o + (size_t)(DIM + 3) * NF] = (Real)lp;
   }
 }
 

@@ -29,6 +29,7 @@ struct esdg_problem {
   int dim = 3, p = 3, N = 4, nn = 64, nv = 5, nf = 16;
   int64_t E = 0;
   int vf = esdg::VF_RANOCHA, sf = esdg::SF_LLF, prec = esdg::PREC_FP64, mesh = esdg::MESH_AFFINE;
+  int nodes = esdg::NODES_LGL;
   double gamma = 1.4;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -48,6 +49,7 @@ struct esdg_problem {
   unsigned long long* LAM = nullptr;  // CFL slots: 2 x kLamSlots by step parity (bit patterns of doubles)
   void* DESC = nullptr;               // ProbDesc<Real> of this problem (device)
   int* FLAG = nullptr;                // non-physical flag
+  void* FACEB = nullptr;              // Gauss: entropy-projected face states
   int red_blocks = 1;
   int64_t red_per_block = 256;
 
@@ -122,6 +124,14 @@ StageOps<Real> stage_ops(const esdg_problem* P) {
   o.inv_wp = (Real)(1.0 / P->ops.w[P->N - 1]);
   o.gamma = (Real)P->gamma;
   o.inv_gm1 = (Real)(1.0 / (P->gamma - 1.0));
+  for (int i = 0; i < P->N; ++i) {
+    o.rL[i] = (Real)P->ops.rL[i];
+    o.rR[i] = (Real)P->ops.rR[i];
+    o.cL[i] = (Real)P->ops.cL[i];
+    o.cR[i] = (Real)P->ops.cR[i];
+    o.r64[0][i] = P->ops.rL[i];
+    o.r64[1][i] = P->ops.rR[i];
+  }
   return o;
 }
 
@@ -139,6 +149,7 @@ ProbDesc<Real> prob_desc(const esdg_problem* P, int tile0, double t_end) {
   d.lam = P->LAM;
   d.time = P->SCAL;
   d.flag = P->FLAG;
+  d.faceb = (Real*)P->FACEB;
   d.t_end = t_end;
   d.E = (int)P->E;
   d.n0 = P->spec.n[0];
@@ -149,16 +160,24 @@ ProbDesc<Real> prob_desc(const esdg_problem* P, int tile0, double t_end) {
   return d;
 }
 
+// Legendre-Gauss problems: the entropy-projection kernel that must precede
+// every stage launch (same tiles and descriptors); fn == NULL for LGL
+VolKernel pick_projection_kernel(const esdg_problem* P);
+
 // One fused stage launch of kernel k over `tiles` tiles of the problems whose
 // descriptors (device memory) are `probs`, all with the parameters of `rep`:
 // right-hand side of buf[in_idx] (surface and volume terms) and, for the RK
 // modes, the stage update into buf[out_idx] / R; RHS mode writes buf[out_idx]
-// or out_ext.
+// or out_ext.  Gauss problems first run the entropy projection of buf[in_idx].
+
 template <typename Real>
 esdg_status run_stage_on(const esdg_problem* rep, const Launcher& L, const VolKernel& k, const void* probs,
                          const int* tile_prob, int64_t tiles, int in_idx, int out_idx, void* out_ext, int mode,
                          double coef_b, double coef_a, const StepCtl& ctl) {
   if (!k.fn) return report(L.err, ESDG_EINVAL, "no stage kernel for dim=%d p=%d flux=%d", rep->dim, rep->p, rep->vf);
+  const VolKernel proj = pick_projection_kernel(rep);
+  if (rep->nodes == NODES_GAUSS && (!proj.fn || proj.epb != k.epb))
+    return report(L.err, ESDG_EINVAL, "no projection kernel for dim=%d p=%d", rep->dim, rep->p);
   StageArgs<Real> a{};
   a.probs = (const ProbDesc<Real>*)probs;
   a.tile_prob = tile_prob;
@@ -175,6 +194,7 @@ esdg_status run_stage_on(const esdg_problem* rep, const Launcher& L, const VolKe
   a.lam_update = ctl.lam_update;
   a.ops = stage_ops<Real>(rep);
   void* args[] = {&a};
+  if (proj.fn) ESDG_TRY(launch_kernel(L, ESDG_KERNEL_PROJECT, proj.fn, dim3((unsigned)tiles), dim3(proj.threads), args));
   return launch_kernel(L, ESDG_KERNEL_STAGE, k.fn, dim3((unsigned)tiles), dim3(k.threads), args);
 }
 

@@ -21,7 +21,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONPHYSICAL, ESTATE = 0, -1, -2, -3, -4, -5
 FLUX = {"ranocha": 0, "shima": 1, "llf": 2, "central": 3}
 PRECISION = {"fp64": 0, "fp32": 1}
 HOST, DEVICE = 0, 1
-KERNEL_STAGE, KERNEL_REDUCE = 1, 2
+KERNEL_STAGE, KERNEL_REDUCE, KERNEL_PROJECT = 1, 2, 3
+NODES = {"lgl": 0, "gauss": 1}
 PMAX = 7
 TILE_VARIANTS = 3
 BATCH_GRAPHS, BATCH_CONCURRENT = 1, 2
@@ -43,7 +44,7 @@ class MeshDesc(C.Structure):
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("warp", C.c_double),
                 ("coords", C.POINTER(C.c_double)), ("gamma", C.c_double),
                 ("volume_flux", C.c_int32), ("surface_flux", C.c_int32),
-                ("precision", C.c_int32), ("stream", C.c_void_p)]
+                ("precision", C.c_int32), ("stream", C.c_void_p), ("nodes", C.c_int32), ("pad", C.c_int32)]
 
 
 class ServerConfig(C.Structure):
@@ -172,7 +173,8 @@ def _where_ptr(arr, shape, writable: bool):
 
 
 def mesh_desc(dim: int, p: int, n, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), warp: float = 0.0,
-              gamma: float = 1.4, volume_flux="ranocha", surface_flux="llf", precision="fp64") -> MeshDesc:
+              gamma: float = 1.4, volume_flux="ranocha", surface_flux="llf", precision="fp64",
+              nodes="lgl") -> MeshDesc:
     """esdg_mesh_desc of a periodic box (coords and stream unset)."""
     d = MeshDesc()
     d.dim, d.p = dim, p
@@ -185,6 +187,7 @@ def mesh_desc(dim: int, p: int, n, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), wa
     d.volume_flux = FLUX[volume_flux] if isinstance(volume_flux, str) else int(volume_flux)
     d.surface_flux = FLUX[surface_flux] if isinstance(surface_flux, str) else int(surface_flux)
     d.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    d.nodes = NODES[nodes] if isinstance(nodes, str) else int(nodes)
     return d
 
 
@@ -201,9 +204,10 @@ class Problem:
 
     def __init__(self, dim: int, p: int, n, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0),
                  warp: float = 0.0, gamma: float = 1.4, volume_flux: str = "ranocha",
-                 surface_flux: str = "llf", precision: str = "fp64", coords=None, stream=None):
+                 surface_flux: str = "llf", precision: str = "fp64", coords=None, stream=None,
+                 nodes: str = "lgl"):
         self._lib = load_library()
-        d = mesh_desc(dim, p, n, lo, hi, warp, gamma, volume_flux, surface_flux, precision)
+        d = mesh_desc(dim, p, n, lo, hi, warp, gamma, volume_flux, surface_flux, precision, nodes)
         keep = None
         if coords is not None:
             keep = np.ascontiguousarray(coords, dtype=np.float64)

@@ -106,3 +106,11 @@ def test_footprint_matches_buffer_sizes(E, kw):
         expect += (Ecount * (dim * dim + 1) * nn + dim * Ecount * dim * nf) * rs
     got = E.footprint(**kw)
     assert expect <= got <= expect + 64 * 1024 + 8 * 8 * 2048
+
+
+def test_footprint_of_gauss_problem(E):
+    base = E.footprint(3, 3, (4, 4, 4))
+    gauss = E.footprint(3, 3, (4, 4, 4), nodes="gauss")
+    assert gauss - base == 64 * 6 * 7 * 16 * 8  # entropy-projected face states
+    with pytest.raises(E.EsdgError):
+        E.footprint(3, 3, (4, 4, 4), warp=0.1, nodes="gauss")
