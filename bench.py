@@ -114,6 +114,28 @@ def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
     ms = time_steps(g, steps, 3, args.cfl, torch)
     g.close()
     out["shima_fp64"] = {"pid_ns": round(ms * 1e6 / (4 * nodes), 6), "ms_per_step": round(ms, 6)}
+    # Legendre-Gauss collocation with entropy projection against LGL, both on
+    # the affine box (Gauss collocation is built for affine meshes), FP64
+    res = {}
+    for kind in ("lgl", "gauss"):
+        g = esdg.Problem(dim, p, (n, n, n), volume_flux=args.flux, surface_flux="llf", nodes=kind)
+        xg = torch.from_numpy(g.coords()).to(u0_dev.device)
+        g.set_state(random_fourier_device(xg, 2, torch))
+        res[kind] = time_steps(g, steps, 3, args.cfl, torch)
+        if kind == "gauss":
+            g.timing(True)
+            g.timing_reset()
+            g.step(dt=0.0, nsteps=2, cfl=args.cfl)
+            st_ms, st_n = g.timing_read(esdg.KERNEL_STAGE)
+            pr_ms, pr_n = g.timing_read(esdg.KERNEL_PROJECT)
+            g.timing(False)
+        g.close()
+    out["gauss_vs_lgl_affine_fp64"] = {
+        "lgl_pid_ns": round(res["lgl"] * 1e6 / (4 * nodes), 6),
+        "gauss_pid_ns": round(res["gauss"] * 1e6 / (4 * nodes), 6),
+        "gauss_over_lgl": round(res["gauss"] / res["lgl"], 3),
+        "gauss_projection_share": round(pr_ms / (pr_ms + st_ms), 3),
+    }
     return out
 
 
