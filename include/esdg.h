@@ -83,14 +83,14 @@ typedef struct {
   void *stream;             /* hipStream_t for all device work; NULL = default */
   int32_t nodes;            /* esdg_nodes: LGL (flux-differencing DGSEM, Sec. 2) or
                                GAUSS (Legendre-Gauss collocation with entropy
-                               projection, Sec. 5; affine meshes only: warp = 0,
+                               projection, Sec. 6; affine meshes only: warp = 0,
                                coords = NULL) */
   int32_t pad;
 } esdg_mesh_desc;
 
 /* Nodes of the element: Legendre-Gauss-Lobatto (the volume nodes include the
  * element boundary) or Legendre-Gauss collocation in the hybridised form of
- * Sec. 5: du/dt = -[M^-1 [I; R]^T f_h + M^-1 R^T B f*] with
+ * Sec. 6: du/dt = -[M^-1 [I; R]^T f_h + M^-1 R^T B f*] with
  * f_h = sum_n 2 Q_h,n o F(u~, u~) over the volume nodes and the face points,
  * Q_h the hybridised SBP operator and u~ = [u; u(R w(u))] the entropy
  * projection (face states from the interpolated entropy variables).  The state

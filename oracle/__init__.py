@@ -9,7 +9,7 @@ library in ``paper_2112_10517_amd``.
 Every function follows the definitions of Ranocha et al. (arXiv:2112.10517):
 the flux-differencing DG form of Sec. 2, the Euler fluxes and log means of
 Sec. 3, the metric terms of Sec. 2.3, the hybridised Gauss collocation form of
-Sec. 5.  See the header of ``esdg_oracle.c`` for
+Sec. 6.  See the header of ``esdg_oracle.c`` for
 the readings taken where the paper is silent.
 """
 from __future__ import annotations
@@ -190,7 +190,7 @@ def entropy(dim: int, gamma: float, u, n):
 
 class Mesh:
     """Periodic box mesh of n[0] x ... elements of degree p (plain CPU);
-    nodes = "lgl" (Sec. 2) or "gauss" (Sec. 5, affine meshes only)."""
+    nodes = "lgl" (Sec. 2) or "gauss" (Sec. 6, affine meshes only)."""
 
     def __init__(self, dim, p, n, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), warp=0.0,
                  gamma=1.4, vol_flux="ranocha", surf_flux="llf", coords=None, nodes="lgl"):

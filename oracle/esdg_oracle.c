@@ -37,7 +37,7 @@
  *       global box coordinate.
  *   R17 CFL: dt = cfl*2/((p+1)*max_i sum_n (|v.Ja^n| + c|Ja^n|)/J_i).
  *
- * Legendre-Gauss collocation (Sec. 5, hybridised form with the entropy
+ * Legendre-Gauss collocation (Sec. 6, hybridised form with the entropy
  * projection) is evaluated on affine meshes by assembling, for every line of
  * an element, the dense hybridised operator of the paper's formulation over
  * the line's volume nodes and its two face points and summing
@@ -148,7 +148,7 @@ int orc_lgl(int p, double *xi, double *w, double *D) {
 /* Legendre-Gauss nodes xi (roots of P_N, N = p+1, ascending), weights
  * 2/((1-x^2) P_N'(x)^2), the textbook collocation derivative matrix
  * D_ij = P_N'(x_i) / (P_N'(x_j) (x_i - x_j)), D_ii = x_i / (1 - x_i^2), and
- * the values rL, rR of the Lagrange basis at -1 and +1 (Sec. 5 operators
+ * the values rL, rR of the Lagrange basis at -1 and +1 (Sec. 6 operators
  * R: volume nodes -> face points). */
 int orc_gauss(int p, double *xi, double *w, double *D, double *rL, double *rR) {
   if (p < 0 || p + 1 >= ORC_MAXN) return -1;
@@ -648,7 +648,7 @@ static void rhs_element(const orc_mesh *m, const double *u, double *du, int64_t 
   }
 }
 
-/* Entropy-projected state at the face point of a line (Sec. 5): w along the
+/* Entropy-projected state at the face point of a line (Sec. 6): w along the
  * line of element e through the multi-index idx in direction n, interpolated
  * to the end `side` (0: -1, 1: +1), mapped back to conservative variables. */
 static void projected_face_state(const orc_mesh *m, const double *u, int64_t e, const int idx[3], int n,
@@ -668,7 +668,7 @@ static void projected_face_state(const orc_mesh *m, const double *u, int64_t e, 
   orc_cons_from_entropy(dim, m->d.gamma, wf, ut);
 }
 
-/* Legendre-Gauss collocation, hybridised form (Sec. 5):
+/* Legendre-Gauss collocation, hybridised form (Sec. 6):
  *   du/dt = -(1/J) [ M^-1 [I; R]^T f_hyb + M^-1 R^T B f_num ],
  *   f_hyb_a = sum_n sum_b 2 (Q_h,n)_ab f(u~_a, u~_b),
  *   Q_h = 1/2 [[M D - (M D)^T, R^T B], [-B R, 0]],  u~ = [u; u(R w(u))],

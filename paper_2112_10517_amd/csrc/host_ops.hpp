@@ -13,7 +13,7 @@ constexpr int kMaxN = 8;  // nodes per line: degree <= 7
 // 1D Legendre-Gauss-Lobatto operators of degree p (Sec. 2, LGL-DGSEM example)
 // and the flux-differencing operator D~ = 2D - M^-1 B of Sec. 2.1.
 //
-// Legendre-Gauss collocation (Sec. 5) uses the Gauss nodes and weights, D on
+// Legendre-Gauss collocation (Sec. 6) uses the Gauss nodes and weights, D on
 // them, the Lagrange basis at the element ends rL, rR (operator R) and, in the
 // slot of D~, T = M^-1 (M D - (M D)^T): the volume block of the hybridised
 // operator 2 Q_h scaled by M^-1 (zero diagonal), with the face coefficients

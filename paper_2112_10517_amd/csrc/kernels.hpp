@@ -258,7 +258,7 @@ __device__ __forceinline__ void surface_flux(int sf, const Real* uL, const Real*
 }
 
 // f*(u_L, u_R, n) of kind sf from primitive states with their logarithms
-// (Gauss collocation: the face states are entropy projections, Sec. 5)
+// (Gauss collocation: the face states are entropy projections, Sec. 6)
 template <int DIM, typename Real>
 __device__ __forceinline__ void surface_flux_prim(int sf, const Prim<Real>& PL, const Prim<Real>& PR, Real nx,
                                                   Real ny, Real nz, Real gamma, Real inv_gm1, Real* F) {
@@ -394,7 +394,7 @@ __device__ __forceinline__ Prim<Real> unpack_prim(const Real* f) {
 // states at the same points.  Besides the volume pairs (T in the D~ slot) the
 // lane evaluates f(u_k, u~_f) for every node k and both ends, adds
 // M^-1 R^T B (f(u_k, u~_f) - sum_j R_fj f(u_j, u~_f) + f*_f), i.e. the
-// face-point rows of 2 Q_h lifted by R^T and the surface term of Sec. 5.
+// face-point rows of 2 Q_h lifted by R^T and the surface term of Sec. 6.
 template <int DIR, int DIM, int N, int VF, int MESH, typename Real, int NODES = NODES_LGL>
 __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value], const Real (&nrm)[N][3], int base,
                                             const StageOps<Real>& ops, const Real* s_dt, Real scale,
@@ -816,7 +816,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
 }
 
 // ---------------------------------------------------------------------------
-// Gauss collocation: entropy projection to the face points (Sec. 5)
+// Gauss collocation: entropy projection to the face points (Sec. 6)
 // ---------------------------------------------------------------------------
 
 // u~ = u(R w(u)) at every face point of the tile's elements: entropy

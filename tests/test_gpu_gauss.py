@@ -1,4 +1,4 @@
-"""Legendre-Gauss collocation with entropy projection (Sec. 5) on the GPU
+"""Legendre-Gauss collocation with entropy projection (Sec. 6) on the GPU
 against the oracle: right-hand sides to the FP64 parity bar of the LGL path
 (and the FP32 bar for FP32 bulk), RK4 states, the zero entropy production of
 the entropy-conservative flux pair, and Gauss problems in a batch

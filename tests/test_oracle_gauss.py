@@ -1,4 +1,4 @@
-"""Pins of the oracle's Legendre-Gauss collocation scheme (Sec. 5: hybridised
+"""Pins of the oracle's Legendre-Gauss collocation scheme (Sec. 6: hybridised
 SBP operators with the entropy projection), each against something other than
 the oracle: numpy's Gauss-Legendre rule, polynomial exactness, the
 generalised SBP identity, the entropy-variable round trip, free-stream
