@@ -50,23 +50,53 @@ def algorithmic_stage_bytes(dim: int, N: int, curved: bool, real_bytes: int = 8)
     return (state + metric + traces + normals) * real_bytes
 
 
+def recorded_counters(kernel_source: str, profile: str, tag: str):
+    """The `tag:` record of rocprofv3 counters in `profile` as a dict, if it
+    was taken on the current kernel source (else None)."""
+    import hashlib
+    try:
+        with open(kernel_source, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+        with open(profile) as f:
+            for line in f:
+                if line.startswith(tag + ":"):
+                    fl = line.split()
+                    rec = dict(zip(fl[1::2], fl[2::2]))
+                    if rec.get("kernels_sha256") != digest:
+                        return None
+                    return {k: float(v) for k, v in rec.items() if k != "kernels_sha256"}
+    except (OSError, ValueError, IndexError):
+        return None
+    return None
+
+
 def recorded_traffic(kernel_source: str, profile: str):
     """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE record
     in `profile`, if it was taken on the current kernel source (else None)."""
-    import hashlib
-    try:
-        digest = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
-        for line in open(profile):
-            if line.startswith("traffic-record:"):
-                f = line.split()
-                rec = dict(zip(f[1::2], f[2::2]))
-                if rec.get("kernels_sha256") != digest:
-                    return None
-                return (float(rec["fetch_kib"]) * float(rec["fetch_factor"]) +
-                        float(rec["write_kib"]) * float(rec["write_factor"])) * 1024.0
-    except (OSError, KeyError, ValueError, IndexError):
+    rec = recorded_counters(kernel_source, profile, "traffic-record")
+    if rec is None:
         return None
-    return None
+    try:
+        return (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"]) * 1024.0
+    except KeyError:
+        return None
+
+
+def recorded_valu(kernel_source: str, profile: str, launch_s: float):
+    """FP64 VALU rate of the stage kernel from the rocprofv3 instruction-count
+    record in `profile` (current kernel source only): hardware FP64 flops =
+    64 lanes x (ADD + MUL + TRANS + 2 FMA) wave instructions; issue fraction =
+    VALU wave instructions x 4 cycles / (1,024 SIMDs x 2.4 GHz x launch)."""
+    rec = recorded_counters(kernel_source, profile, "valu-record")
+    if rec is None or launch_s <= 0:
+        return None
+    try:
+        flops = 64.0 * (rec["fp64_add"] + rec["fp64_mul"] + rec["fp64_trans"] + 2.0 * rec["fp64_fma"])
+        tflops = flops / launch_s / 1e12
+        return {"fp64_tflops": round(tflops, 3), "fp64_frac_of_peak": round(tflops / FP64_VALU_PEAK_TF, 4),
+                "valu_issue_frac": round(rec["valu_insts"] * 4.0 / (1024 * 2.4e9 * launch_s), 4)}
+    except KeyError:
+        return None
 
 
 def time_steps(g, steps, warmup, cfl, torch):
@@ -164,6 +194,60 @@ def random_fourier_device(x, seed, torch, gamma=1.4):
         u[:, 1 + j] = rho * v[j]
     u[:, d + 1] = p / (gamma - 1.0) + 0.5 * rho * sum(vj * vj for vj in v)
     return u
+
+
+def precision_sweep(args, esdg, inputs, torch, dev):
+    """Density wave on the warped 32^3 box at p = 4 and 7, Ranocha + LLF: FP32
+    bulk against FP64.  PID of both (CFL-mode RK4 steps); relative L2 and Linf
+    differences of the FP32 right-hand side and of the FP32 state after a
+    fixed number of equal fixed-dt steps, against the FP64 ones (per
+    conserved variable; the FP64 path matches the oracle to 1e-12).  The
+    density wave's momentum and energy right-hand sides are O(|v|) remainders
+    of an O(p) pressure-flux divergence that cancels, so their FP32 relative
+    error is that of the cancelled terms, not of the result."""
+    import numpy as np
+    out = {}
+    n = args.sweep_n
+    for p in [int(q) for q in args.sweep_p.split(",") if q]:
+        res, u0 = {}, None
+        dt = None
+        for prec in ("fp64", "fp32"):
+            g = esdg.Problem(3, p, (n, n, n), warp=0.1, volume_flux="ranocha", surface_flux="llf", precision=prec)
+            if u0 is None:
+                u0 = torch.from_numpy(inputs.density_wave(g.coords())).to(dev)
+            g.set_state(u0)
+            res[prec + "_rhs"] = g.rhs()
+            if dt is None:
+                dt = 0.5 * g.max_dt(args.sweep_cfl)
+            g.step(dt=dt, nsteps=args.sweep_steps)
+            g.sync()
+            res[prec + "_u"] = g.get_state()
+            g.set_state(u0)
+            res[prec + "_ms"] = time_steps(g, args.sweep_steps, 2, args.sweep_cfl, torch)
+            nodes = g.n_dof
+            g.close()
+
+        def diff(a, b):
+            # per conserved variable (rho, rho v1..v3, rho e)
+            l2 = [float("%.3e" % (np.linalg.norm(a[:, v] - b[:, v]) / np.linalg.norm(b[:, v]))) for v in range(5)]
+            li = [float("%.3e" % (np.abs(a[:, v] - b[:, v]).max() / np.abs(b[:, v]).max())) for v in range(5)]
+            return l2, li
+
+        r2, ri = diff(res["fp32_rhs"], res["fp64_rhs"])
+        s2, si = diff(res["fp32_u"], res["fp64_u"])
+        out["p%d" % p] = {
+            "nodes": nodes,
+            "fp64_pid_ns": round(res["fp64_ms"] * 1e6 / (4 * nodes), 6),
+            "fp32_pid_ns": round(res["fp32_ms"] * 1e6 / (4 * nodes), 6),
+            "fp32_speedup": round(res["fp64_ms"] / res["fp32_ms"], 3),
+            "rhs_rel_l2": r2, "rhs_rel_linf": ri,
+            "state_rel_l2_after_steps": s2, "state_rel_linf_after_steps": si,
+            "steps": args.sweep_steps, "dt": float("%.4e" % dt),
+        }
+        del res
+    out["workload"] = ("density wave rho = 1 + 0.98 sin(pi(x+y+z)), v = (0.1,0.2,0.3), p = 20 on the warped %d^3 "
+                       "box, Ranocha + LLF, RK4 at CFL %.2f" % (n, args.sweep_cfl))
+    return out
 
 
 def batched(args, esdg, torch, dev, fp64_pid):
@@ -361,6 +445,15 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="budget of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-single-seconds", type=float, default=5.0,
+                    help="seconds of the oracle on one host thread (0: skip)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further timed runs of --steps steps from the initial state (PID mean and std)")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the FP32/FP64 precision sweep")
+    ap.add_argument("--sweep-n", type=int, default=32)
+    ap.add_argument("--sweep-p", default="4,7")
+    ap.add_argument("--sweep-steps", type=int, default=10)
+    ap.add_argument("--sweep-cfl", type=float, default=0.3)
     ap.add_argument("--timing-steps", type=int, default=10,
                     help="steps with per-kernel hipEvent timing (after the timed region)")
     ap.add_argument("--no-variants", action="store_true",
@@ -428,6 +521,19 @@ def main(argv=None):
     ms_per_step = 1e3 * wall / args.steps
     pid_ns = ms_per_step * 1e6 / (4 * nodes)
 
+    # the paper's PID protocol (Sec. 4.1): mean and standard deviation over
+    # five runs, each the same number of steps from the same initial state
+    runs = []
+    for _ in range(args.repeats):
+        g.set_state(u0_dev)
+        g.step(dt=0.0, nsteps=1, cfl=args.cfl)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run(args.steps)
+        torch.cuda.synchronize()
+        runs.append((time.perf_counter() - t1) * 1e9 / (args.steps * 4 * nodes))
+    g.sync()
+
     # per-kernel durations (hipEvents around each launch on the library's stream)
     g.timing(True)
     g.timing_reset()
@@ -463,6 +569,8 @@ def main(argv=None):
             "rhs_per_step": 4,
         },
         "pid_per_node_var_ns": round(pid_ns / g.n_var, 6),
+        "pid_runs_ns": {"mean": round(float(np.mean(runs)), 6), "std": round(float(np.std(runs, ddof=1)), 6),
+                        "runs": len(runs), "steps_per_run": args.steps} if len(runs) > 1 else None,
         "dof_per_s": 4 * nodes / (ms_per_step * 1e-3),
         "event_ms_per_step": round(ev_ms / args.steps, 6),
         "kernels_us": {
@@ -482,6 +590,9 @@ def main(argv=None):
             "algorithmic_bytes_per_node": bytes_per_node,
             "bytes_per_launch": traffic_bytes,
             "avg_launch_us": round(vol_avg_s * 1e6, 3),
+            "valu": recorded_valu(os.path.join(ROOT, "paper_2112_10517_amd", "csrc", "kernels.hpp"),
+                                  os.path.join(ROOT, "profiles", "stage_kernel_3d_p3_warped16_fp64.md"), vol_avg_s)
+            if (dim, p, n, args.flux) == (3, 3, 16, "ranocha") else None,
         },
         "cpu_baseline": None,
     }
@@ -489,6 +600,8 @@ def main(argv=None):
     if not args.no_variants:
         line["variants"] = variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n)
 
+    if not args.no_sweep:
+        line["precision_sweep"] = precision_sweep(args, esdg, inputs, torch, dev)
     if not args.no_batched:
         line["batched"] = batched(args, esdg, torch, dev, pid_ns)
     if not args.no_served:
@@ -524,6 +637,26 @@ def main(argv=None):
             "sample": "%d RK4 steps (CFL %.2f, %d RHS) of the same %d^3 p=%d workload, %.1f s"
                       % (steps, args.cfl, 4 * steps, n, p, el),
         }
+        if args.cpu_single_seconds > 0:
+            # one host thread: like for like with the paper's serial PIDs
+            nt = oracle.num_threads()
+            oracle.set_num_threads(1)
+            try:
+                uc = inputs.random_fourier(m.coords(), 2)
+                steps = 0
+                t0 = time.perf_counter()
+                while True:
+                    uc, _ = m.rk4(uc, 0.0, 1, cfl=args.cfl)
+                    steps += 1
+                    if time.perf_counter() - t0 >= args.cpu_single_seconds:
+                        break
+                el = time.perf_counter() - t0
+            finally:
+                oracle.set_num_threads(nt)
+            line["cpu_single_core"] = {
+                "value": round(el * 1e9 / (steps * 4 * nodes), 3), "unit": "ns/DOF/RHS", "cores": 1,
+                "kind": "oracle",
+                "sample": "%d RK4 steps (%d RHS) of the same workload, %.1f s" % (steps, 4 * steps, el)}
     print(json.dumps(line), flush=True)
     g.close()
     return 0

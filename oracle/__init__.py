@@ -90,6 +90,8 @@ def _load():
         lib.orc_rk4.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, C.c_double, dp]
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = C.c_int
+        lib.orc_set_num_threads.argtypes = [C.c_int]
+        lib.orc_set_num_threads.restype = None
         _lib = lib
         return lib
 
@@ -106,6 +108,11 @@ def _f64(a) -> np.ndarray:
 def num_threads() -> int:
     """OpenMP threads the oracle's element loops use."""
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Set the OpenMP threads of the oracle's element loops (for timing)."""
+    _load().orc_set_num_threads(int(n))
 
 
 # --------------------------------------------------------------------------

@@ -77,6 +77,7 @@ typedef struct {
 
 /* threads the element loops use (OpenMP) */
 int orc_num_threads(void) { return omp_get_max_threads(); }
+void orc_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 /* ------------------------------------------------------------------------ */
 /* 1D LGL operators (Sec. 2, LGL-DGSEM example; textbook closed forms)      */

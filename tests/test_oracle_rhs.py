@@ -275,3 +275,18 @@ def test_totals_and_max_dt(orc):
     c = np.sqrt(G * 20.0 / rho)
     lam = ((0.1 + c) + (0.2 + c)) * 2 / 0.5
     assert abs(dt - 2.0 / (4 * lam.max())) < 1e-12 * dt
+
+
+def test_thread_count_does_not_change_rhs(orc):
+    # element loops are independent: one thread and all threads agree bit for bit
+    m = orc.Mesh(3, 3, (3, 3, 3), warp=0.1, vol_flux="ranocha", surf_flux="llf")
+    u = inputs.random_fourier(m.coords(), 7)
+    n0 = orc.num_threads()
+    try:
+        orc.set_num_threads(1)
+        assert orc.num_threads() == 1
+        r1 = m.rhs(u)
+    finally:
+        orc.set_num_threads(n0)
+    assert orc.num_threads() == n0
+    assert np.array_equal(r1, m.rhs(u))
