@@ -25,8 +25,11 @@
  *     (rho, rho v_1 .. rho v_d, rho e), node index x-fastest
  *     (i + N j + N^2 k, N = p+1), element index x-fastest
  *     (ex + nx ey + nx ny ez);
- *   - caller-owned pointers are only read or written during the call and are
- *     never retained or freed by the library;
+ *   - caller-owned pointers are never retained or freed by the library; host
+ *     pointers are only read or written during the call; device pointers are
+ *     read or written by work enqueued on the handle's stream, so the caller
+ *     keeps them valid (and unmodified, for inputs) until that work is done,
+ *     in stream order;
  *   - every call returns an esdg_status; ESDG_OK == 0; on failure a message
  *     is available from esdg_last_error();
  *   - a handle is not thread-safe; distinct handles on distinct streams may

@@ -111,8 +111,12 @@ esdg_status upload_group(esdg_batch* b, BatchGroup& g) {
   g.tiles = tile0;
   ESDG_HIP(&b->err, hipMalloc(&g.desc, sizeof(ProbDesc<Real>) * descs.size()));
   ESDG_HIP(&b->err, hipMalloc((void**)&g.tile_prob, sizeof(int) * owner.size()));
-  ESDG_HIP(&b->err, hipMemcpy(g.desc, descs.data(), sizeof(ProbDesc<Real>) * descs.size(), hipMemcpyHostToDevice));
-  ESDG_HIP(&b->err, hipMemcpy(g.tile_prob, owner.data(), sizeof(int) * owner.size(), hipMemcpyHostToDevice));
+  // on the batch stream (the members' streams need not be ordered with the null stream)
+  ESDG_HIP(&b->err, hipMemcpyAsync(g.desc, descs.data(), sizeof(ProbDesc<Real>) * descs.size(), hipMemcpyHostToDevice,
+                                   b->stream));
+  ESDG_HIP(&b->err,
+           hipMemcpyAsync(g.tile_prob, owner.data(), sizeof(int) * owner.size(), hipMemcpyHostToDevice, b->stream));
+  ESDG_HIP(&b->err, hipStreamSynchronize(b->stream));
   return ESDG_OK;
 }
 
@@ -365,8 +369,9 @@ esdg_status esdg_batch_create(esdg_problem* const* probs, int32_t count, const d
       hipMalloc((void**)&b->t_out, sizeof(double) * count) != hipSuccess ||
       hipMalloc((void**)&b->f_out, sizeof(int) * count) != hipSuccess)
     return bail(bfail(b, ESDG_ENOMEM, "device allocation of the batch tables failed"));
-  if (hipMemcpy(b->time_ptrs, tp.data(), sizeof(double*) * count, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->flag_ptrs, fp.data(), sizeof(int*) * count, hipMemcpyHostToDevice) != hipSuccess)
+  if (hipMemcpyAsync(b->time_ptrs, tp.data(), sizeof(double*) * count, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      hipMemcpyAsync(b->flag_ptrs, fp.data(), sizeof(int*) * count, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
     return bail(bfail(b, ESDG_EDEVICE, "upload of the batch tables failed"));
   esdg_status st = refresh_groups(b);
   if (st != ESDG_OK) return bail(st);

@@ -386,8 +386,9 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
       delete P;
       return fail(nullptr, ESDG_ENOMEM, "device allocation of metric terms failed");
     }
-    if (hipMemcpy(P->METRIC, mf.data(), mf.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(P->NFACE, nf.data(), nf.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpyAsync(P->METRIC, mf.data(), mf.size() * 4, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+        hipMemcpyAsync(P->NFACE, nf.data(), nf.size() * 4, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+        hipStreamSynchronize(P->stream) != hipSuccess) {
       free_buffers(P);
       delete P;
       return fail(nullptr, ESDG_EDEVICE, "upload of metric terms failed");
@@ -401,8 +402,9 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
       delete P;
       return fail(nullptr, ESDG_ENOMEM, "device allocation of metric terms failed");
     }
-    hipError_t e1 = hipMemcpy(P->METRIC, P->geo.metric.data(), mb, hipMemcpyHostToDevice);
-    hipError_t e2 = hipMemcpy(P->NFACE, P->geo.nface.data(), fb, hipMemcpyHostToDevice);
+    hipError_t e1 = hipMemcpyAsync(P->METRIC, P->geo.metric.data(), mb, hipMemcpyHostToDevice, P->stream);
+    hipError_t e2 = hipMemcpyAsync(P->NFACE, P->geo.nface.data(), fb, hipMemcpyHostToDevice, P->stream);
+    if (e1 == hipSuccess && e2 == hipSuccess) e1 = hipStreamSynchronize(P->stream);
     if (e1 != hipSuccess || e2 != hipSuccess) {
       free_buffers(P);
       delete P;
@@ -419,10 +421,12 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
     if (e1 == hipSuccess) {
       if (P->prec == PREC_FP32) {
         ProbDesc<float> d = prob_desc<float>(P, 0, INFINITY);
-        e2 = hipMemcpy(P->DESC, &d, db, hipMemcpyHostToDevice);
+        e2 = hipMemcpyAsync(P->DESC, &d, db, hipMemcpyHostToDevice, P->stream);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(P->stream);
       } else {
         ProbDesc<double> d = prob_desc<double>(P, 0, INFINITY);
-        e2 = hipMemcpy(P->DESC, &d, db, hipMemcpyHostToDevice);
+        e2 = hipMemcpyAsync(P->DESC, &d, db, hipMemcpyHostToDevice, P->stream);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(P->stream);
       }
     }
     if (e1 != hipSuccess || e2 != hipSuccess) {
@@ -431,7 +435,10 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
       return fail(nullptr, ESDG_ENOMEM, "device problem descriptor failed");
     }
   }
-  if (hipMemset(P->FLAG, 0, sizeof(int)) != hipSuccess || hipMemset(P->SCAL, 0, sizeof(double) * 16) != hipSuccess) {
+  // cleared on the handle's stream (which need not be ordered with the null stream)
+  if (hipMemsetAsync(P->FLAG, 0, sizeof(int), P->stream) != hipSuccess ||
+      hipMemsetAsync(P->SCAL, 0, sizeof(double) * 16, P->stream) != hipSuccess ||
+      hipStreamSynchronize(P->stream) != hipSuccess) {
     free_buffers(P);
     delete P;
     return fail(nullptr, ESDG_EDEVICE, "device initialisation failed");
@@ -594,9 +601,11 @@ esdg_status esdg_sync(esdg_problem* P) {
   ESDG_TRY(check_handle(P, false));
   ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
   int flag = 0;
-  ESDG_HIP(&P->err, hipMemcpy(&flag, P->FLAG, sizeof(int), hipMemcpyDeviceToHost));
+  ESDG_HIP(&P->err, hipMemcpyAsync(&flag, P->FLAG, sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
   if (flag) {
-    ESDG_HIP(&P->err, hipMemset(P->FLAG, 0, sizeof(int)));
+    ESDG_HIP(&P->err, hipMemsetAsync(P->FLAG, 0, sizeof(int), P->stream));
+    ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
     return fail(P, ESDG_ENONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or non-finite) met by a kernel");
   }
   return ESDG_OK;
