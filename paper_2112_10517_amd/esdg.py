@@ -213,6 +213,7 @@ class Problem:
             keep = np.ascontiguousarray(coords, dtype=np.float64)
             d.coords = keep.ctypes.data_as(C.POINTER(C.c_double))
         d.stream = self._stream_ptr(stream)
+        self._stream = d.stream or 0
         h = C.c_void_p()
         st = self._lib.esdg_init_mesh(C.byref(d), C.byref(h))
         _check(self._lib, None, st)
@@ -260,7 +261,13 @@ class Problem:
         _check(self._lib, self._h, fn(self._h, *args))
 
     def set_stream(self, stream):
-        self._call(self._lib.esdg_set_stream, self._stream_ptr(stream))
+        sp = self._stream_ptr(stream)
+        self._call(self._lib.esdg_set_stream, sp)
+        self._stream = (sp.value if sp is not None else None) or 0
+
+    def stream_ptr(self) -> int:
+        """The hipStream_t the problem's device work is enqueued on (0: default)."""
+        return int(self._stream)
 
     def coords(self) -> np.ndarray:
         x = np.zeros((self.n_elem, self.dim, self.nodes))
