@@ -134,6 +134,8 @@ CASES_VARIANT = [
     (3, 5, (3, 2, 3), 0.1, "ranocha", "llf", "fp32"),
     (3, 6, (2, 3, 2), 0.1, "shima", "llf", "fp32"),
     (3, 7, (2, 2, 2), 0.0, "ranocha", "ranocha", "fp32"),
+    (3, 7, (2, 2, 2), 0.1, "ranocha", "llf", "fp32"),
+    (3, 7, (2, 1, 2), 0.1, "ranocha", "llf", "fp64"),
 ]
 
 

@@ -123,6 +123,9 @@ CASES = [
     (3, 5, (2, 3, 2), 0.0, "ranocha", "ranocha"),
     (3, 6, (2, 2, 2), 0.1, "shima", "shima"),
     (3, 7, (2, 1, 2), 0.1, "ranocha", "llf"),
+    (3, 7, (2, 2, 1), 0.0, "ranocha", "ranocha"),
+    (3, 7, (1, 2, 2), 0.1, "central", "central"),
+    (3, 7, (2, 2, 2), 0.0, "shima", "llf"),
     (3, 3, (1, 1, 1), 0.0, "ranocha", "llf"),   # element is its own neighbour
     (2, 3, (1, 7), 0.1, "ranocha", "llf"),
 ]
