@@ -162,6 +162,30 @@ def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
             pr_ms, pr_n = g.timing_read(esdg.KERNEL_PROJECT)
             g.timing(False)
         g.close()
+    # the paper's timing workload (Sec. 4.1): isentropic vortex of strength 20
+    # on [-5,5]^3 with 8 elements per direction, p = 3, the same two-point flux
+    # in the volume and at the faces; Cartesian, and a warped box standing in
+    # for the paper's curved mesh.  Context for its single-core CPU PIDs.
+    ctx = {}
+    for mesh, warp in (("cartesian", 0.0), ("warped", 0.5)):
+        for vf in ("shima", "ranocha"):
+            g = esdg.Problem(3, 3, (8, 8, 8), lo=(-5.0,) * 3, hi=(5.0,) * 3, warp=warp, volume_flux=vf,
+                             surface_flux=vf)
+            g.set_state(torch.from_numpy(inputs.isentropic_vortex(g.coords())).to(u0_dev.device))
+            g.step(dt=0.0, nsteps=20, cfl=args.cfl)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.step(dt=0.0, nsteps=100, cfl=args.cfl)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / 100
+            g.sync()
+            ctx["%s_%s_pid_ns" % (mesh, vf)] = round(ms * 1e6 / (4 * g.n_dof), 4)
+            g.close()
+    ctx["paper_cpu_one_core_pid_ns"] = {"cartesian_shima": 26, "curved_shima": 43, "cartesian_ranocha": 42,
+                                        "curved_ranocha": 65}
+    ctx["workload"] = ("isentropic vortex (strength 20) on [-5,5]^3, 8^3 elements (32,768 nodes), p = 3, FP64, "
+                       "RK4 steps at CFL %.2f, 100 steps in one call" % args.cfl)
+    out["paper_setup_vortex_8cubed"] = ctx
     out["gauss_vs_lgl_affine_fp64"] = {
         "lgl_pid_ns": round(res["lgl"] * 1e6 / (4 * nodes), 6),
         "gauss_pid_ns": round(res["gauss"] * 1e6 / (4 * nodes), 6),

@@ -127,22 +127,28 @@ def taylor_green(x, gamma: float = 1.4, mach: float = 0.1) -> np.ndarray:
     return prim_to_cons(np.ones_like(X), v, p, gamma)
 
 
-def isentropic_vortex(x, gamma: float = 1.4, eps: float = 20.0) -> np.ndarray:
-    """Isentropic vortex of Sec. 4.1 (rho0 = 1, v0 = (1,1,0), p0 = 10, domain [-5,5]^d).
+def isentropic_vortex(x, gamma: float = 1.4, eps: float = 20.0, t: float = 0.0) -> np.ndarray:
+    """Isentropic vortex of Sec. 4.1 (rho0 = 1, v0 = (1,1,0), p0 = 10, periodic
+    domain [-5,5]^d), centred at v0 t (wrapped into the domain).
 
-    In 3D the vortex is a tube: r is the distance from the x_3 axis.
+    r is the distance from the centre over all d coordinates, as the paper
+    states it; in 2D the state at time t is the exact solution (the initial
+    vortex translated with v0), in 3D the field is only a test state.
     """
     x = np.asarray(x, dtype=np.float64)
     E, d, n = x.shape
     rho0, p0 = 1.0, 10.0
     T0 = p0 / rho0
-    r2 = x[:, 0] ** 2 + x[:, 1] ** 2
+    v0 = np.array([1.0, 1.0, 0.0][:d])
+    xs = x - (v0 * t)[None, :, None]
+    xs = np.mod(xs + 5.0, 10.0) - 5.0
+    r2 = np.sum(xs * xs, axis=1)
     T = T0 - (gamma - 1.0) * eps ** 2 / (8.0 * gamma * np.pi ** 2) * np.exp(1.0 - r2)
     rho = rho0 * (T / T0) ** (1.0 / (gamma - 1.0))
     amp = eps / (2.0 * np.pi) * np.exp(0.5 * (1.0 - r2))
     v = np.zeros((E, d, n))
-    v[:, 0] = 1.0 - amp * x[:, 1]
-    v[:, 1] = 1.0 + amp * x[:, 0]
+    v[:, 0] = 1.0 - amp * xs[:, 1]
+    v[:, 1] = 1.0 + amp * xs[:, 0]
     return prim_to_cons(rho, v, rho * T, gamma)
 
 

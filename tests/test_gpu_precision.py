@@ -140,3 +140,19 @@ def test_precision_sweep_32cubed(orc, esdg, p):
     assert serr <= 1e-5
     g64.close()
     g32.close()
+
+
+@pytest.mark.parametrize("dim,warp", [(2, 0.0), (3, 0.1)])
+def test_fp32_isentropic_vortex(orc, esdg, dim, warp):
+    # Sec. 4.1 vortex (both log-mean branches) in FP32 bulk against the FP64 oracle
+    lo, hi = (-5.0,) * dim, (5.0,) * dim
+    n = (8,) * dim
+    m = orc.Mesh(dim, 3, n, lo=lo, hi=hi, warp=warp, vol_flux="ranocha", surf_flux="ranocha")
+    u = inputs.isentropic_vortex(m.coords())
+    ref, sigma = m.rhs(u), m.rhs_scale(u)
+    g = esdg.Problem(dim, 3, n, lo=lo, hi=hi, warp=warp, volume_flux="ranocha", surface_flux="ranocha",
+                     precision="fp32")
+    g.set_state(u)
+    ws, l2, linf = errors(g.rhs(), ref, sigma)
+    print("fp32 vortex %dD warp %.1f: err/sigma %.2e  L2 %.2e  Linf %.2e" % (dim, warp, ws, l2, linf))
+    assert ws <= TOL32

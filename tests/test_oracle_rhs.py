@@ -290,3 +290,37 @@ def test_thread_count_does_not_change_rhs(orc):
         orc.set_num_threads(n0)
     assert orc.num_threads() == n0
     assert np.array_equal(r1, m.rhs(u))
+
+
+def test_isentropic_vortex_convergence_and_logmean_branches(orc):
+    # Sec. 4.1: the vortex of strength 20 makes the log means take both
+    # branches; in 2D the vortex translated with v0 is the exact solution.
+    # RK4 to t = 0.2 on 8^2, 16^2, 32^2 elements, p = 3: order about p + 1
+    # with LLF, about p with the entropy-conservative surface flux.
+    N = 4
+    m0 = orc.Mesh(2, 3, (8, 8), lo=(-5, -5), hi=(5, 5))
+    rho, _, p = inputs.cons_to_prim(inputs.isentropic_vortex(m0.coords()), G)
+    u_lm, u_ilm = [], []
+    for a in range(N):
+        for b in range(a + 1, N):
+            for y in range(N):
+                i, k = a + N * y, b + N * y
+                u_lm.append(((rho[:, k] - rho[:, i]) / (rho[:, k] + rho[:, i])) ** 2)
+                A, B = rho[:, i] * p[:, k], rho[:, k] * p[:, i]
+                u_ilm.append(((B - A) / (B + A)) ** 2)
+    for uu in (np.concatenate(u_lm), np.concatenate(u_ilm)):
+        assert (uu < 1e-4).any() and (uu >= 1e-4).any()
+    for surf, order in (("llf", 3.5), ("ranocha", 2.5)):
+        errs = []
+        for n in (8, 16, 32):
+            m = orc.Mesh(2, 3, (n, n), lo=(-5, -5), hi=(5, 5), vol_flux="ranocha", surf_flux=surf)
+            x = m.coords()
+            u = inputs.isentropic_vortex(x)
+            T = 0.2
+            steps = int(np.ceil(T / m.max_dt(u, 0.25)))
+            uT, _ = m.rk4(u, T / steps, steps)
+            ue = inputs.isentropic_vortex(x, t=T)
+            W = m.weights()[None, None, :]
+            errs.append(np.sqrt(np.sum(W * (uT - ue) ** 2) / np.sum(W * ue ** 2)))
+        orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+        assert errs[-1] < 1e-4 and orders.min() > order, (surf, errs, orders)
