@@ -308,6 +308,14 @@ esdg_status esdg_server_fetch(esdg_server *server, int64_t job_id, double *u);
 /* Device memory held by admitted and finished-but-unfetched jobs. */
 esdg_status esdg_server_memory(esdg_server *server, int64_t *used, int64_t *budget);
 const char *esdg_server_last_error(const esdg_server *server);
+/* The server's admission rule as a pure host function (no device access):
+ * of n_queued jobs in arrival order with device footprints queued_bytes,
+ * how many are admitted now, given used bytes of admitted and unfetched
+ * jobs, the budget, the number of active jobs and the cap max_active
+ * (0: none).  Admission keeps arrival order: it stops at the first job that
+ * does not fit.  ESDG_EINVAL on negative sizes or a NULL output. */
+esdg_status esdg_server_plan(const int64_t *queued_bytes, int32_t n_queued, int64_t used, int64_t budget,
+                             int32_t active, int32_t max_active, int32_t *n_admit);
 
 /* Last error message of the handle (or of the calling thread if prob is NULL). */
 const char *esdg_last_error(const esdg_problem *prob);

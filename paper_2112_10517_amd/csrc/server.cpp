@@ -64,12 +64,18 @@ void release(esdg_server* S, Job& j) {
   }
 }
 
+// the admission rule: one more job of `bytes` fits beside `used` bytes and
+// `active` jobs
+bool admissible(int64_t bytes, int64_t used, int64_t budget, int64_t active, int64_t max_active) {
+  if (max_active > 0 && active >= max_active) return false;
+  return used + bytes <= budget;
+}
+
 // admit queued jobs in arrival order while they fit
 esdg_status admit(esdg_server* S) {
   while (!S->queue.empty()) {
-    if (S->cfg.max_active > 0 && (int64_t)S->active.size() >= S->cfg.max_active) break;
     Job& j = S->jobs[S->queue.front()];
-    if (S->used + j.bytes > S->budget) break;
+    if (!admissible(j.bytes, S->used, S->budget, (int64_t)S->active.size(), S->cfg.max_active)) break;
     esdg_mesh_desc d = j.mesh;
     d.coords = nullptr;
     d.stream = S->admit_stream;
@@ -277,5 +283,20 @@ esdg_status esdg_server_memory(esdg_server* S, int64_t* used, int64_t* budget) {
 }
 
 const char* esdg_server_last_error(const esdg_server* S) { return S ? S->err.c_str() : ""; }
+
+esdg_status esdg_server_plan(const int64_t* queued_bytes, int32_t n_queued, int64_t used, int64_t budget,
+                             int32_t active, int32_t max_active, int32_t* n_admit) {
+  if (!n_admit || n_queued < 0 || (n_queued > 0 && !queued_bytes) || used < 0 || budget < 0 || active < 0 ||
+      max_active < 0)
+    return ESDG_EINVAL;
+  int32_t k = 0;
+  for (; k < n_queued; ++k) {
+    if (queued_bytes[k] < 0) return ESDG_EINVAL;
+    if (!admissible(queued_bytes[k], used, budget, (int64_t)active + k, max_active)) break;
+    used += queued_bytes[k];
+  }
+  *n_admit = k;
+  return ESDG_OK;
+}
 
 }  // extern "C"

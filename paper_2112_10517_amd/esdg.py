@@ -107,6 +107,7 @@ SIGNATURES = {
     "esdg_server_fetch": (_st, [_vp, _i64, _dp]),
     "esdg_server_memory": (_st, [_vp, _pi64, _pi64]),
     "esdg_server_last_error": (_str, [_vp]),
+    "esdg_server_plan": (_st, [_pi64, _i32, _i64, _i64, _i32, _i32, _pi32]),
     "esdg_operators": (_st, [_i32, _dp, _dp, _dp, _dp]),
     "esdg_last_error": (_str, [_vp]),
     "esdg_version": (_str, []),
@@ -189,6 +190,17 @@ def mesh_desc(dim: int, p: int, n, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0), wa
     d.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     d.nodes = NODES[nodes] if isinstance(nodes, str) else int(nodes)
     return d
+
+
+def server_plan(queued_bytes, used: int, budget: int, active: int = 0, max_active: int = 0) -> int:
+    """How many of the queued jobs (device bytes, arrival order) the server's
+    admission rule admits now (esdg_server_plan)."""
+    lib = load_library()
+    q = (C.c_int64 * max(1, len(queued_bytes)))(*[int(b) for b in queued_bytes])
+    k = C.c_int32()
+    _check(lib, None, lib.esdg_server_plan(q, len(queued_bytes), int(used), int(budget), int(active),
+                                           int(max_active), C.byref(k)))
+    return k.value
 
 
 def footprint(dim: int, p: int, n, **kw) -> int:

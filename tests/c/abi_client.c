@@ -74,6 +74,12 @@ static void host_checks(void) {
   CHECK(esdg_init_mesh(&d, &prob) == ESDG_EINVAL && prob == (esdg_problem *)0, "dim 4 accepted");
   CHECK(strlen(esdg_last_error(NULL)) > 0, "no error message for dim 4");
   CHECK(esdg_rhs((esdg_problem *)0, (double *)0, ESDG_HOST) == ESDG_EINVAL, "NULL handle accepted");
+  {
+    const int64_t q[3] = {10, 20, 30};
+    int32_t k = -1;
+    OK(esdg_server_plan(q, 3, 0, 35, 0, 0, &k));
+    CHECK(k == 2, "admission of 10, 20, 30 bytes in a budget of 35: %d", (int)k);
+  }
   esdg_destroy((esdg_problem *)0);
 }
 

@@ -114,3 +114,24 @@ def test_footprint_of_gauss_problem(E):
     assert gauss - base == 64 * 6 * 7 * 16 * 8  # entropy-projected face states
     with pytest.raises(E.EsdgError):
         E.footprint(3, 3, (4, 4, 4), warp=0.1, nodes="gauss")
+
+
+def test_server_admission_rule(E):
+    # arrival order, budget, cap; no device involved
+    plan = E.server_plan
+    assert plan([10, 20, 30], used=0, budget=35) == 2
+    assert plan([10, 20, 5], used=0, budget=35) == 3          # exactly at the budget
+    assert plan([40, 5], used=0, budget=35) == 0              # the head blocks: no overtaking
+    assert plan([10, 10, 10], used=20, budget=35) == 1        # memory of admitted jobs counts
+    assert plan([1, 1, 1, 1], used=0, budget=100, active=3, max_active=4) == 1
+    assert plan([1, 1], used=0, budget=100, active=4, max_active=4) == 0
+    assert plan([1, 1, 1], used=0, budget=100, active=50, max_active=0) == 3  # 0: no cap
+    assert plan([], used=0, budget=10) == 0
+    with pytest.raises(E.EsdgError):
+        plan([5, -1], used=0, budget=10)
+    with pytest.raises(E.EsdgError):
+        plan([5], used=-1, budget=10)
+    # the served workload's jobs: footprints in arrival order against a budget
+    sizes = [E.footprint(3, p, (n, n, n), precision="fp32") for n, p in ((8, 3), (32, 5), (16, 4), (8, 5))]
+    budget = sizes[0] + sizes[1] + sizes[2] // 2
+    assert plan(sizes, used=0, budget=budget) == 2
