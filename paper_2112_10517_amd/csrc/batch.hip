@@ -286,8 +286,8 @@ void destroy_batch(esdg_batch* b) {
 
 extern "C" {
 
-esdg_status esdg_batch_create(esdg_problem* const* probs, int32_t count, const double* t_end, void* stream,
-                              int32_t flags, esdg_batch** out) {
+static esdg_status batch_create_impl(esdg_problem* const* probs, int32_t count, const double* t_end, void* stream,
+                                      int32_t flags, esdg_batch** out) {
   if (!probs || !out || count < 1) return report(nullptr, ESDG_EINVAL, "need count >= 1 problems and an output pointer");
   *out = nullptr;
   if (flags & ~(ESDG_BATCH_GRAPHS | ESDG_BATCH_CONCURRENT)) return report(nullptr, ESDG_EINVAL, "unknown batch flags");
@@ -299,12 +299,20 @@ esdg_status esdg_batch_create(esdg_problem* const* probs, int32_t count, const d
     if (t_end && std::isnan(t_end[i])) return report(nullptr, ESDG_EINVAL, "NaN end time");
   }
   esdg_batch* b = new esdg_batch();
+  // released on every early return or exception until the batch is complete
+  struct Owner {
+    esdg_batch* b;
+    ~Owner() {
+      if (b) destroy_batch(b);
+    }
+  } own{b};
   b->device = probs[0]->device;
   b->flags = flags;
   b->probs.assign(probs, probs + count);
   for (int i = 0; i < count; ++i) b->t_end.push_back(t_end ? t_end[i] : INFINITY);
   auto bail = [&](esdg_status st) {
     std::string msg = b->err;
+    own.b = nullptr;
     destroy_batch(b);
     return report(nullptr, st, "%s", msg.c_str());
   };
@@ -375,6 +383,7 @@ esdg_status esdg_batch_create(esdg_problem* const* probs, int32_t count, const d
     return bail(bfail(b, ESDG_EDEVICE, "upload of the batch tables failed"));
   esdg_status st = refresh_groups(b);
   if (st != ESDG_OK) return bail(st);
+  own.b = nullptr;
   *out = b;
   return ESDG_OK;
 }
@@ -385,7 +394,7 @@ void esdg_batch_destroy(esdg_batch* b) {
   destroy_batch(b);
 }
 
-esdg_status esdg_batch_step(esdg_batch* b, double dt, int32_t nsteps, double cfl) {
+static esdg_status batch_step_impl(esdg_batch* b, double dt, int32_t nsteps, double cfl) {
   ESDG_TRY(check_batch(b));
   if (nsteps < 0) return bfail(b, ESDG_EINVAL, "nsteps must be >= 0");
   const bool use_cfl = !(dt > 0.0);
@@ -427,7 +436,7 @@ esdg_status esdg_batch_step(esdg_batch* b, double dt, int32_t nsteps, double cfl
   return sync_out(b);
 }
 
-esdg_status esdg_batch_rhs(esdg_batch* b, double* const* du, int32_t where) {
+static esdg_status batch_rhs_impl(esdg_batch* b, double* const* du, int32_t where) {
   ESDG_TRY(check_batch(b));
   ESDG_TRY(refresh_groups(b));
   ESDG_TRY(sync_in(b));
@@ -459,7 +468,7 @@ esdg_status esdg_batch_rhs(esdg_batch* b, double* const* du, int32_t where) {
   return sync_out(b);
 }
 
-esdg_status esdg_batch_times(esdg_batch* b, double* t) {
+static esdg_status batch_times_impl(esdg_batch* b, double* t) {
   if (!b || !t) return report(b ? &b->err : nullptr, ESDG_EINVAL, "NULL argument");
   ESDG_HIP(&b->err, hipSetDevice(b->device));
   ESDG_TRY(sync_in(b));
@@ -471,7 +480,7 @@ esdg_status esdg_batch_times(esdg_batch* b, double* t) {
   return ESDG_OK;
 }
 
-esdg_status esdg_batch_sync(esdg_batch* b, int32_t* bad) {
+static esdg_status batch_sync_impl(esdg_batch* b, int32_t* bad) {
   if (!b) return report(nullptr, ESDG_EINVAL, "NULL batch handle");
   ESDG_HIP(&b->err, hipSetDevice(b->device));
   if (bad) *bad = -1;
@@ -492,7 +501,7 @@ esdg_status esdg_batch_sync(esdg_batch* b, int32_t* bad) {
   return ESDG_OK;
 }
 
-esdg_status esdg_batch_autotune(esdg_batch* b, int32_t reps) {
+static esdg_status batch_autotune_impl(esdg_batch* b, int32_t reps) {
   ESDG_TRY(check_batch(b));
   ESDG_HIP(&b->err, hipStreamSynchronize(b->stream));
   for (auto& g : b->groups) {
@@ -523,7 +532,7 @@ esdg_status esdg_batch_timing_enable(esdg_batch* b, int32_t enable) {
   return ESDG_OK;
 }
 
-esdg_status esdg_batch_timing_read(esdg_batch* b, double* total_ms, int64_t* steps) {
+static esdg_status batch_timing_read_impl(esdg_batch* b, double* total_ms, int64_t* steps) {
   if (!b) return report(nullptr, ESDG_EINVAL, "NULL batch handle");
   ESDG_HIP(&b->err, hipSetDevice(b->device));
   double sum = 0.0;
@@ -544,5 +553,34 @@ esdg_status esdg_batch_timing_read(esdg_batch* b, double* total_ms, int64_t* ste
 }
 
 const char* esdg_batch_last_error(const esdg_batch* b) { return b ? b->err.c_str() : ""; }
+
+esdg_status esdg_batch_create(esdg_problem* const* probs, int32_t count, const double* t_end, void* stream,
+                              int32_t flags, esdg_batch** out) {
+  return guarded(nullptr, [&] { return batch_create_impl(probs, count, t_end, stream, flags, out); });
+}
+
+esdg_status esdg_batch_step(esdg_batch* b, double dt, int32_t nsteps, double cfl) {
+  return guarded(b ? &b->err : nullptr, [&] { return batch_step_impl(b, dt, nsteps, cfl); });
+}
+
+esdg_status esdg_batch_rhs(esdg_batch* b, double* const* du, int32_t where) {
+  return guarded(b ? &b->err : nullptr, [&] { return batch_rhs_impl(b, du, where); });
+}
+
+esdg_status esdg_batch_times(esdg_batch* b, double* t) {
+  return guarded(b ? &b->err : nullptr, [&] { return batch_times_impl(b, t); });
+}
+
+esdg_status esdg_batch_sync(esdg_batch* b, int32_t* bad) {
+  return guarded(b ? &b->err : nullptr, [&] { return batch_sync_impl(b, bad); });
+}
+
+esdg_status esdg_batch_autotune(esdg_batch* b, int32_t reps) {
+  return guarded(b ? &b->err : nullptr, [&] { return batch_autotune_impl(b, reps); });
+}
+
+esdg_status esdg_batch_timing_read(esdg_batch* b, double* total_ms, int64_t* steps) {
+  return guarded(b ? &b->err : nullptr, [&] { return batch_timing_read_impl(b, total_ms, steps); });
+}
 
 }  // extern "C"

@@ -5,7 +5,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <map>
 #include <mutex>
 #include <string>
@@ -57,7 +60,13 @@ esdg_status launch_kernel(const Launcher& L, int kind, const void* fn, dim3 grid
   ESDG_HIP(L.err, hipLaunchKernel(fn, grid, block, args, 0, L.stream));
   if (L.timed) {
     ESDG_HIP(L.err, hipEventRecord(tl.stop, L.stream));
-    L.timed->push_back(tl);
+    try {
+      L.timed->push_back(tl);
+    } catch (const std::bad_alloc&) {
+      (void)hipEventDestroy(tl.start);
+      (void)hipEventDestroy(tl.stop);
+      return report(L.err, ESDG_ENOMEM, "host memory exhausted (timing record)");
+    }
   }
   return ESDG_OK;
 }
@@ -121,6 +130,7 @@ static esdg_status reduce_t(esdg_problem* P, const Launcher& L, int op, double c
   for (int j = 0; j < 3; ++j) a.inv_half_h[j] = P->geo.inv_half_h[j];
   for (int i = 0; i < P->N; ++i) a.w[i] = P->ops.w[i];
   a.gamma = P->gamma;
+  for (int j = 0; j < 3; ++j) a.scale[j] = (Real)(P->mesh == MESH_AFFINE ? P->geo.inv_half_h[j] : 1.0);
   int64_t per_block = P->red_per_block;
   void* args[] = {&a, &per_block};
   ESDG_TRY(launch_kernel(L, ESDG_KERNEL_REDUCE, reduce_partial_for(P->prec, P->dim, P->mesh, op),
@@ -298,12 +308,31 @@ esdg_status esdg_footprint(const esdg_mesh_desc* d, int64_t* bytes) {
   return ESDG_OK;
 }
 
-esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
-  if (!d || !out) return fail(nullptr, ESDG_EINVAL, "NULL descriptor or output pointer");
-  *out = nullptr;
+static esdg_status init_mesh_impl(const esdg_mesh_desc* d, esdg_problem** out) {
   ESDG_TRY(check_desc(d));
+  // optional device budget (bytes) for every problem: a problem whose
+  // footprint exceeds it fails with ESDG_ENOMEM before any allocation
+  if (const char* env = std::getenv("ESDG_DEVICE_BUDGET")) {
+    int64_t need = 0;
+    ESDG_TRY(esdg_footprint(d, &need));
+    const long long budget = std::atoll(env);
+    if (budget > 0 && need > budget)
+      return fail(nullptr, ESDG_ENOMEM, "problem needs %lld device bytes, ESDG_DEVICE_BUDGET is %lld",
+                  (long long)need, budget);
+  }
 
-  esdg_problem* P = new esdg_problem();
+  // owned until the handle is complete: every early return (and exception)
+  // releases what was allocated so far
+  struct Owner {
+    esdg_problem* P = new esdg_problem();
+    ~Owner() {
+      if (P) {
+        free_buffers(P);
+        delete P;
+      }
+    }
+  } own;
+  esdg_problem* P = own.P;
   P->spec.dim = d->dim;
   P->spec.p = d->p;
   for (int j = 0; j < 3; ++j) {
@@ -328,9 +357,7 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
   const bool ops_ok =
       P->nodes == NODES_GAUSS ? make_gauss_operators(d->p, &P->ops, &err) : make_operators(d->p, &P->ops, &err);
   if (!ops_ok || !make_geometry(P->spec, P->ops, &P->geo, &err)) {
-    esdg_status st = fail(nullptr, ESDG_EINVAL, "%s", err.c_str());
-    delete P;
-    return st;
+    return fail(nullptr, ESDG_EINVAL, "%s", err.c_str());
   }
   P->spec.coords = nullptr;  // never retained
   P->E = P->geo.E;
@@ -340,9 +367,7 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
 
   hipError_t he = hipGetDevice(&P->device);
   if (he != hipSuccess) {
-    esdg_status st = fail(nullptr, ESDG_EDEVICE, "hipGetDevice: %s", hipGetErrorString(he));
-    delete P;
-    return st;
+    return fail(nullptr, ESDG_EDEVICE, "hipGetDevice: %s", hipGetErrorString(he));
   }
   reduction_blocks(P->E * P->nn, &P->red_blocks, &P->red_per_block);
 
@@ -361,20 +386,14 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
                 {(void**)&P->FLAG, sizeof(int)}};
   for (auto& a : allocs) {
     if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
-      free_buffers(P);
-      delete P;
       return fail(nullptr, ESDG_ENOMEM, "device allocation of %zu bytes failed", a.bytes);
     }
   }
   if (P->nodes == NODES_GAUSS &&
       hipMalloc(&P->FACEB, (size_t)P->E * 2 * P->dim * (P->dim + 4) * P->nf * P->rsize) != hipSuccess) {
-    free_buffers(P);
-    delete P;
     return fail(nullptr, ESDG_ENOMEM, "device allocation of the face states failed");
   }
   if (P->prec == PREC_FP32 && hipMalloc((void**)&P->STAGE64, state_count(P) * sizeof(double)) != hipSuccess) {
-    free_buffers(P);
-    delete P;
     return fail(nullptr, ESDG_ENOMEM, "device allocation of the FP64 staging buffer failed");
   }
   if (P->mesh == MESH_CURVED && P->prec == PREC_FP32) {
@@ -382,15 +401,11 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
     std::vector<float> mf(P->geo.metric.begin(), P->geo.metric.end());
     std::vector<float> nf(P->geo.nface.begin(), P->geo.nface.end());
     if (hipMalloc(&P->METRIC, mf.size() * 4) != hipSuccess || hipMalloc(&P->NFACE, nf.size() * 4) != hipSuccess) {
-      free_buffers(P);
-      delete P;
       return fail(nullptr, ESDG_ENOMEM, "device allocation of metric terms failed");
     }
     if (hipMemcpyAsync(P->METRIC, mf.data(), mf.size() * 4, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
         hipMemcpyAsync(P->NFACE, nf.data(), nf.size() * 4, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
         hipStreamSynchronize(P->stream) != hipSuccess) {
-      free_buffers(P);
-      delete P;
       return fail(nullptr, ESDG_EDEVICE, "upload of metric terms failed");
     }
     std::vector<double>().swap(P->geo.metric);
@@ -398,16 +413,12 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
   } else if (P->mesh == MESH_CURVED) {
     const size_t mb = P->geo.metric.size() * P->rsize, fb = P->geo.nface.size() * P->rsize;
     if (hipMalloc(&P->METRIC, mb) != hipSuccess || hipMalloc(&P->NFACE, fb) != hipSuccess) {
-      free_buffers(P);
-      delete P;
       return fail(nullptr, ESDG_ENOMEM, "device allocation of metric terms failed");
     }
     hipError_t e1 = hipMemcpyAsync(P->METRIC, P->geo.metric.data(), mb, hipMemcpyHostToDevice, P->stream);
     hipError_t e2 = hipMemcpyAsync(P->NFACE, P->geo.nface.data(), fb, hipMemcpyHostToDevice, P->stream);
     if (e1 == hipSuccess && e2 == hipSuccess) e1 = hipStreamSynchronize(P->stream);
     if (e1 != hipSuccess || e2 != hipSuccess) {
-      free_buffers(P);
-      delete P;
       return fail(nullptr, ESDG_EDEVICE, "upload of metric terms failed");
     }
     // the device copy is authoritative; keep the host copy small
@@ -430,8 +441,6 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
       }
     }
     if (e1 != hipSuccess || e2 != hipSuccess) {
-      free_buffers(P);
-      delete P;
       return fail(nullptr, ESDG_ENOMEM, "device problem descriptor failed");
     }
   }
@@ -439,12 +448,23 @@ esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
   if (hipMemsetAsync(P->FLAG, 0, sizeof(int), P->stream) != hipSuccess ||
       hipMemsetAsync(P->SCAL, 0, sizeof(double) * 16, P->stream) != hipSuccess ||
       hipStreamSynchronize(P->stream) != hipSuccess) {
-    free_buffers(P);
-    delete P;
     return fail(nullptr, ESDG_EDEVICE, "device initialisation failed");
   }
+  own.P = nullptr;
   *out = P;
   return ESDG_OK;
+}
+
+esdg_status esdg_init_mesh(const esdg_mesh_desc* d, esdg_problem** out) {
+  if (!d || !out) return fail(nullptr, ESDG_EINVAL, "NULL descriptor or output pointer");
+  *out = nullptr;
+  try {
+    return init_mesh_impl(d, out);
+  } catch (const std::bad_alloc&) {
+    return fail(nullptr, ESDG_ENOMEM, "host memory exhausted while building the problem");
+  } catch (const std::exception& e) {
+    return fail(nullptr, ESDG_EDEVICE, "%s", e.what());
+  }
 }
 
 void esdg_destroy(esdg_problem* P) {

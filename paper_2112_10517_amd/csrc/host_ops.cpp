@@ -214,7 +214,14 @@ void parallel_for(int64_t n, Fn fn) {
     return;
   }
   std::vector<std::thread> th;
-  for (int64_t t = 0; t < nt; ++t) th.emplace_back(fn, n * t / nt, n * (t + 1) / nt);
+  th.reserve((size_t)nt);
+  int64_t t = 0;
+  try {
+    for (; t < nt; ++t) th.emplace_back(fn, n * t / nt, n * (t + 1) / nt);
+  } catch (...) {
+    // a thread could not be started: the remaining ranges run here
+    for (int64_t r = t; r < nt; ++r) fn(n * r / nt, n * (r + 1) / nt);
+  }
   for (auto& x : th) x.join();
 }
 

@@ -368,6 +368,39 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
   return b < (q << 3) ? (b & 7) * q + (b >> 3) : b;
 }
 
+// CFL wave-speed sum of one node, sum_n (|v.Ja^n| + c |Ja^n|) / J (affine:
+// sum_n (|v_n| + c) 2/h_n), from its conservative state.  me points at the
+// node's first metric entry (stride nn between entries; curved meshes).  The
+// last RK stage and the CFL reduction both use this one expression, so the
+// step size of a state is the same whichever of them computed it.
+template <int DIM, int MESH, typename Real, typename MP>
+__device__ __forceinline__ Real cfl_rate(const Real (&u)[DIM + 2], MP me, int64_t nn, Real rinvj,
+                                         const Real* scale, Real gamma) {
+  const Real gm1 = gamma - Real(1);
+  const Real rho = u[0], ir = dev_rcp(rho);
+  const Real w0 = u[1] * ir;
+  const Real w1 = DIM > 1 ? u[DIM > 1 ? 2 : 1] * ir : Real(0);
+  const Real w2 = DIM > 2 ? u[DIM > 2 ? 3 : 1] * ir : Real(0);
+  const Real pr = gm1 * (u[DIM + 1] - Real(0.5) * rho * (w0 * w0 + w1 * w1 + w2 * w2));
+  const Real c = sqrt(gamma * pr * ir);
+  Real lam = Real(0);
+  if (MESH == MESH_CURVED) {
+#pragma unroll
+    for (int n = 0; n < DIM; ++n) {
+      const Real j0 = me[(n * DIM) * nn];
+      const Real j1 = DIM > 1 ? me[(n * DIM + (DIM > 1 ? 1 : 0)) * nn] : Real(0);
+      const Real j2 = DIM > 2 ? me[(n * DIM + (DIM > 2 ? 2 : 0)) * nn] : Real(0);
+      lam += fabs(w0 * j0 + w1 * j1 + w2 * j2) + c * sqrt(j0 * j0 + j1 * j1 + j2 * j2);
+    }
+    lam *= rinvj;
+  } else {
+    lam = (fabs(w0) + c) * scale[0];
+    if (DIM > 1) lam += (fabs(w1) + c) * scale[DIM > 1 ? 1 : 0];
+    if (DIM > 2) lam += (fabs(w2) + c) * scale[DIM > 2 ? 2 : 0];
+  }
+  return lam;
+}
+
 // primitive state (rho, v_1..v_d, p, log rho, log p) stored as dim+4 values
 template <int DIM, typename Real>
 __device__ __forceinline__ Prim<Real> unpack_prim(const Real* f) {
@@ -775,29 +808,9 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
       }
     }
     if (lam_out) {
-      // sum_n (|v.Ja^n| + c |Ja^n|) / J of the new state at this node
-      const Real rho = unew[0], ir = dev_rcp(rho);
-      const Real w0 = unew[1] * ir;
-      const Real w1 = DIM > 1 ? unew[DIM > 1 ? 2 : 1] * ir : Real(0);
-      const Real w2 = DIM > 2 ? unew[DIM > 2 ? 3 : 1] * ir : Real(0);
-      const Real pr = gm1 * (unew[DIM + 1] - Real(0.5) * rho * (w0 * w0 + w1 * w1 + w2 * w2));
-      const Real c = sqrt(a.ops.gamma * pr * ir);
-      Real lam = Real(0);
-      if (MESH == MESH_CURVED) {
-        const auto me = metric + (size_t)ee * (NM * NN) + i;
-#pragma unroll
-        for (int n = 0; n < DIM; ++n) {
-          const Real j0 = me[(n * DIM) * NN];
-          const Real j1 = DIM > 1 ? me[(n * DIM + (DIM > 1 ? 1 : 0)) * NN] : Real(0);
-          const Real j2 = DIM > 2 ? me[(n * DIM + (DIM > 2 ? 2 : 0)) * NN] : Real(0);
-          lam += fabs(w0 * j0 + w1 * j1 + w2 * j2) + c * sqrt(j0 * j0 + j1 * j1 + j2 * j2);
-        }
-        lam *= rinvj[r];
-      } else {
-        lam = (fabs(w0) + c) * P.scale[0];
-        if (DIM > 1) lam += (fabs(w1) + c) * P.scale[DIM > 1 ? 1 : 0];
-        if (DIM > 2) lam += (fabs(w2) + c) * P.scale[DIM > 2 ? 2 : 0];
-      }
+      // CFL wave-speed sum of the new state at this node
+      const auto me = MESH == MESH_CURVED ? metric + (size_t)ee * (NM * NN) + i : metric;
+      const Real lam = cfl_rate<DIM, MESH, Real>(unew, me, (int64_t)NN, rinvj[r], P.scale, a.ops.gamma);
       const double ld = (double)lam;
       if (!(ld <= lam_max)) lam_max = ld;  // a NaN wins and poisons dt (flagged anyway)
     }
@@ -922,6 +935,7 @@ struct RedArgs {
   double J_affine, inv_half_h[3];
   double w[kDevMaxN];
   double gamma;
+  Real scale[3];        // 2/h_n of the affine box in the state's precision (CFL)
 };
 
 constexpr int kRedThreads = 256;
@@ -974,24 +988,13 @@ __global__ void __launch_bounds__(kRedThreads) reduce_partial_kernel(RedArgs<Rea
         dot -= beta * (double)a.du[(e * NV + DIM + 1) * nn + i];
         accv[0] += J * W * dot;
       } else {
-        const double c = sqrt(a.gamma * p / rho);
-        double lam = 0.0;
+        // the expression of the last RK stage, in the state's precision
+        Real ur[NV];
 #pragma unroll
-        for (int n = 0; n < DIM; ++n) {
-          if (MESH == MESH_CURVED) {
-            double vn = 0.0, an = 0.0;
-#pragma unroll
-            for (int m = 0; m < DIM; ++m) {
-              const double jm = (double)a.metric[(e * NM + n * DIM + m) * nn + i];
-              vn += vel[m] * jm;
-              an += jm * jm;
-            }
-            lam += fabs(vn) + c * sqrt(an);
-          } else {
-            lam += (fabs(vel[n]) + c) * a.inv_half_h[n] * a.J_affine;
-          }
-        }
-        lam /= J;
+        for (int v = 0; v < NV; ++v) ur[v] = a.u[(e * NV + v) * nn + i];
+        const Real* me = MESH == MESH_CURVED ? a.metric + e * NM * nn + i : a.metric;
+        const Real rinvj = MESH == MESH_CURVED ? a.metric[(e * NM + DIM * DIM) * nn + i] : Real(1);
+        const double lam = (double)cfl_rate<DIM, MESH, Real>(ur, me, (int64_t)nn, rinvj, a.scale, (Real)a.gamma);
         if (!(lam <= accv[0])) accv[0] = lam;  // NaN propagates
       }
     }

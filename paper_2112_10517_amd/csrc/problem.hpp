@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -82,6 +84,19 @@ esdg_status fail(esdg_problem* P, esdg_status st, const char* fmt, ...);
     if (e_ != hipSuccess)                                                                             \
       return ::esdg::report((errp), ESDG_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));            \
   } while (0)
+
+// Runs f, turning C++ exceptions into status codes so that none crosses the
+// C ABI: host allocation failures become ESDG_ENOMEM, others ESDG_EDEVICE.
+template <typename F>
+esdg_status guarded(std::string* err, F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return report(err, ESDG_ENOMEM, "host memory exhausted");
+  } catch (const std::exception& e) {
+    return report(err, ESDG_EDEVICE, "%s", e.what());
+  }
+}
 
 // Where and how a kernel is launched: stream, optional event bracketing, error slot.
 struct Launcher {

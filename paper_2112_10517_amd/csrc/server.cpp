@@ -8,6 +8,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <deque>
+#include <exception>
+#include <new>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -54,6 +56,18 @@ esdg_status sfail(esdg_server* S, esdg_status st, const char* fmt, ...) {
   va_end(ap);
   if (S) S->err = buf;
   return st;
+}
+
+// Runs f, turning C++ exceptions into status codes (none crosses the C ABI).
+template <typename F>
+esdg_status sguard(esdg_server* S, F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return sfail(S, ESDG_ENOMEM, "host memory exhausted");
+  } catch (const std::exception& e) {
+    return sfail(S, ESDG_EDEVICE, "%s", e.what());
+  }
 }
 
 void release(esdg_server* S, Job& j) {
@@ -126,7 +140,7 @@ esdg_status rebuild_batch(esdg_server* S) {
 
 extern "C" {
 
-esdg_status esdg_server_create(const esdg_server_config* cfg, esdg_server** out) {
+static esdg_status server_create_impl(const esdg_server_config* cfg, esdg_server** out) {
   if (!cfg || !out) return ESDG_EINVAL;
   *out = nullptr;
   if (cfg->steps_per_tick < 1 || !(cfg->cfl > 0.0) || cfg->max_active < 0 || cfg->hbm_budget < 0) return ESDG_EINVAL;
@@ -161,7 +175,7 @@ void esdg_server_destroy(esdg_server* S) {
   delete S;
 }
 
-esdg_status esdg_server_submit(esdg_server* S, const esdg_job_desc* job, int64_t* job_id) {
+static esdg_status server_submit_impl(esdg_server* S, const esdg_job_desc* job, int64_t* job_id) {
   if (!S || !job || !job->u0) return sfail(S, ESDG_EINVAL, "NULL argument");
   if (!(job->t_end > job->t0)) return sfail(S, ESDG_EINVAL, "need t_end > t0");
   if (job->mesh.coords) return sfail(S, ESDG_EINVAL, "jobs take box meshes (coords must be NULL)");
@@ -187,7 +201,7 @@ esdg_status esdg_server_submit(esdg_server* S, const esdg_job_desc* job, int64_t
   return ESDG_OK;
 }
 
-esdg_status esdg_server_tick(esdg_server* S, int32_t* finished, int32_t* active, int32_t* queued) {
+static esdg_status server_tick_impl(esdg_server* S, int32_t* finished, int32_t* active, int32_t* queued) {
   if (!S) return ESDG_EINVAL;
   if (hipSetDevice(S->device) != hipSuccess) return sfail(S, ESDG_EDEVICE, "hipSetDevice failed");
   S->finished.clear();
@@ -260,7 +274,7 @@ esdg_status esdg_server_job(esdg_server* S, int64_t id, int32_t* status, double*
   return ESDG_OK;
 }
 
-esdg_status esdg_server_fetch(esdg_server* S, int64_t id, double* u) {
+static esdg_status server_fetch_impl(esdg_server* S, int64_t id, double* u) {
   if (!S) return ESDG_EINVAL;
   auto it = S->jobs.find(id);
   if (it == S->jobs.end()) return sfail(S, ESDG_EINVAL, "unknown job %lld", (long long)id);
@@ -283,6 +297,22 @@ esdg_status esdg_server_memory(esdg_server* S, int64_t* used, int64_t* budget) {
 }
 
 const char* esdg_server_last_error(const esdg_server* S) { return S ? S->err.c_str() : ""; }
+
+esdg_status esdg_server_create(const esdg_server_config* cfg, esdg_server** out) {
+  return sguard(nullptr, [&] { return server_create_impl(cfg, out); });
+}
+
+esdg_status esdg_server_submit(esdg_server* S, const esdg_job_desc* job, int64_t* job_id) {
+  return sguard(S, [&] { return server_submit_impl(S, job, job_id); });
+}
+
+esdg_status esdg_server_tick(esdg_server* S, int32_t* finished, int32_t* active, int32_t* queued) {
+  return sguard(S, [&] { return server_tick_impl(S, finished, active, queued); });
+}
+
+esdg_status esdg_server_fetch(esdg_server* S, int64_t id, double* u) {
+  return sguard(S, [&] { return server_fetch_impl(S, id, u); });
+}
 
 esdg_status esdg_server_plan(const int64_t* queued_bytes, int32_t n_queued, int64_t used, int64_t budget,
                              int32_t active, int32_t max_active, int32_t* n_admit) {

@@ -268,3 +268,28 @@ def test_isentropic_vortex_parity(orc, esdg, dim, warp, vol):
         escale = np.sum((J * m.weights()[None, :])[:, None, :] * np.abs(w * du))
         rate = g.entropy_rate()
         assert abs(rate) < 1e-13 * escale and abs(rate - m.entropy_rate(u, du)) < 1e-13 * escale
+
+
+@pytest.mark.parametrize("prec,cfl", [("fp64", False), ("fp32", False), ("fp64", True), ("fp32", True)])
+def test_checkpoint_resume_bitwise(esdg, prec, cfl):
+    # the state and time read through the ABI (FP64, canonical layout) are the
+    # checkpoint: 10 steps equal 5 steps, checkpoint, a new handle restored
+    # from it, 5 more steps -- bit for bit, with fixed dt and in CFL mode
+    kw = dict(warp=0.1, volume_flux="ranocha", surface_flux="llf", precision=prec)
+    a = esdg.Problem(3, 3, (3, 4, 2), **kw)
+    u = noisy(inputs.random_fourier(a.coords(), 3), 4)
+    a.set_state(u)
+    dt = 0.0 if cfl else 0.5 * a.max_dt(0.5)
+    a.step(dt=dt, nsteps=10, cfl=0.5, t=0.0)
+    u10, t10 = a.get_state(), a.get_time()
+    b = esdg.Problem(3, 3, (3, 4, 2), **kw)
+    b.set_state(u)
+    b.step(dt=dt, nsteps=5, cfl=0.5, t=0.0)
+    ck_u, ck_t = b.get_state(), b.get_time()
+    b.close()
+    c = esdg.Problem(3, 3, (3, 4, 2), **kw)
+    c.set_state(ck_u)
+    c.set_time(ck_t)
+    c.step(dt=dt, nsteps=5, cfl=0.5)
+    assert c.get_time() == t10
+    assert np.array_equal(c.get_state(), u10)
