@@ -582,6 +582,21 @@ def main(argv=None):
     traffic_bytes = bytes_per_node * nodes
     achieved_gbs = traffic_bytes / vol_avg_s / 1e9
 
+    # the bandwidth a plain streaming copy reaches on this device (512 MiB
+    # device to device, read + write bytes, five copies between events)
+    cb = 512 << 20
+    src = torch.ones(cb // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * cb / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
+
     line = {
         "metric": "PID (ns per DOF per RHS) FP64 plain vs FP32 batched; served jobs/s + p99 latency",
         "value": round(pid_ns, 6),
@@ -626,6 +641,8 @@ def main(argv=None):
             "algorithmic_bytes_per_node": bytes_per_node,
             "bytes_per_launch": traffic_bytes,
             "avg_launch_us": round(vol_avg_s * 1e6, 3),
+            "copy_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved_gbs / copy_gbs, 4),
             "valu": recorded_valu(os.path.join(ROOT, "paper_2112_10517_amd", "csrc", "kernels.hpp"),
                                   os.path.join(ROOT, "profiles", "stage_kernel_3d_p3_warped16_fp64.md"), vol_avg_s)
             if (dim, p, n, args.flux) == (3, 3, 16, "ranocha") else None,
