@@ -296,7 +296,7 @@ def batched(args, esdg, torch, dev, fp64_pid):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     nodes = sum(q.n_dof for q in probs)
-    B = esdg.Batch(probs, graphs=True)
+    B = esdg.Batch(probs, graphs=True, concurrent=args.batch_concurrent)
     t0 = time.perf_counter()
     B.autotune(args.batch_tune_reps)
     tune_s = time.perf_counter() - t0
@@ -337,6 +337,7 @@ def batched(args, esdg, torch, dev, fp64_pid):
         "nodes": nodes,
         "groups": groups,
         "tiles": tiles,
+        "concurrent_groups": bool(args.batch_concurrent),
         "pid_ns": round(pid, 6),
         "ms_per_step": round(ms, 4),
         "event_ms_per_step": round(ev_ms / max(ev_n, 1), 4),
@@ -491,6 +492,8 @@ def main(argv=None):
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--batch-seq-steps", type=int, default=2)
     ap.add_argument("--batch-tune-reps", type=int, default=5)
+    ap.add_argument("--batch-concurrent", action="store_true",
+                    help="run the groups of a batch step on concurrent streams")
     ap.add_argument("--batch-cfl", type=float, default=0.3,
                     help="CFL number of the batched workload (classical RK4 with this CFL definition is "
                          "unstable at 0.5 for p >= 6)")
