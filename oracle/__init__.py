@@ -88,6 +88,8 @@ def _load():
         lib.orc_max_dt.argtypes = [C.c_void_p, dp, C.c_double]
         lib.orc_max_dt.restype = C.c_double
         lib.orc_rk4.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, C.c_double, dp]
+        lib.orc_ck45.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, C.c_double, dp]
+        lib.orc_ck45_coefficients.argtypes = [dp, dp]
         lib.orc_num_threads.argtypes = []
         lib.orc_num_threads.restype = C.c_int
         lib.orc_set_num_threads.argtypes = [C.c_int]
@@ -108,6 +110,13 @@ def _f64(a) -> np.ndarray:
 def num_threads() -> int:
     """OpenMP threads the oracle's element loops use."""
     return _load().orc_num_threads()
+
+
+def ck45_coefficients():
+    """(A, B) of the oracle's 2N-storage scheme (Carpenter and Kennedy)."""
+    A, B = np.zeros(5), np.zeros(5)
+    _load().orc_ck45_coefficients(_ptr(A), _ptr(B))
+    return A, B
 
 
 def set_num_threads(n: int) -> None:
@@ -311,4 +320,12 @@ class Mesh:
         u = self._state(u).copy()
         tt = C.c_double(t)
         self._lib.orc_rk4(self._h, _ptr(u), dt, nsteps, cfl, C.byref(tt))
+        return u, tt.value
+
+    def ck45(self, u, dt: float, nsteps: int, cfl: float = 0.0, t: float = 0.0):
+        """Return (u_new, t_new) after nsteps steps of the five-stage, fourth-order
+        2N-storage scheme of Carpenter and Kennedy (Williamson form)."""
+        u = self._state(u).copy()
+        tt = C.c_double(t)
+        self._lib.orc_ck45(self._h, _ptr(u), dt, nsteps, cfl, C.byref(tt))
         return u, tt.value

@@ -941,3 +941,43 @@ void orc_rk4(const orc_mesh *m, double *u, double dt, int nsteps, double cfl,
   }
   free(k1); free(k2); free(k3); free(k4); free(y);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Five-stage, fourth-order 2N-storage RK of Carpenter and Kennedy (1994),   */
+/* the scheme of the paper's FLUXO runs (Sec. 4.1), in Williamson's form:    */
+/*   du <- A_i du + h RHS(u);  u <- u + B_i du,   i = 1..5, A_1 = 0          */
+/* ------------------------------------------------------------------------ */
+
+static const double CK_A[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+static const double CK_B[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+
+void orc_ck45_coefficients(double *A, double *B) {
+  for (int i = 0; i < 5; ++i) {
+    A[i] = CK_A[i];
+    B[i] = CK_B[i];
+  }
+}
+
+/* As orc_rk4, with the 2N scheme (dt <= 0: CFL step size at the start of
+ * every step). */
+void orc_ck45(const orc_mesh *m, double *u, double dt, int nsteps, double cfl,
+              double *t) {
+  size_t len = (size_t)m->ne * m->nv * m->nn;
+  double *k = (double *)malloc(sizeof(double) * len);
+  double *du = (double *)calloc(len, sizeof(double));
+  for (int s = 0; s < nsteps; ++s) {
+    double h = dt > 0.0 ? dt : orc_max_dt(m, u, cfl);
+    for (int i = 0; i < 5; ++i) {
+      orc_rhs(m, u, k);
+      for (size_t q = 0; q < len; ++q) {
+        du[q] = CK_A[i] * du[q] + h * k[q];
+        u[q] = u[q] + CK_B[i] * du[q];
+      }
+    }
+    if (t) *t += h;
+  }
+  free(k); free(du);
+}
