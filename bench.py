@@ -146,6 +146,12 @@ def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
     ms = time_steps(g, steps, 3, args.cfl, torch)
     g.close()
     out["shima_fp64"] = {"pid_ns": round(ms * 1e6 / (4 * nodes), 6), "ms_per_step": round(ms, 6)}
+    # the five-stage 2N-storage integrator (five fused stage launches per step)
+    g = esdg.Problem(dim, p, (n, n, n), warp=0.1, volume_flux=args.flux, surface_flux="llf", integrator="ck45")
+    g.set_state(u0_dev)
+    ms = time_steps(g, steps, 3, args.cfl, torch)
+    g.close()
+    out["ck45_fp64"] = {"pid_ns": round(ms * 1e6 / (5 * nodes), 6), "ms_per_step": round(ms, 6), "rhs_per_step": 5}
     # Legendre-Gauss collocation with entropy projection against LGL, both on
     # the affine box (Gauss collocation is built for affine meshes), FP64
     res = {}

@@ -131,9 +131,10 @@ esdg_status esdg_get_state(esdg_problem *prob, double *u, int32_t where);
  * du has the state layout, FP64, host or device memory. */
 esdg_status esdg_rhs(esdg_problem *prob, double *du, int32_t where);
 
-/* step!: advance the state by nsteps steps of classical RK4 (Butcher
- * a = 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6) in low-storage form (state,
- * accumulator and two alternating stage buffers), each stage one fused
+/* step!: advance the state by nsteps steps of the problem's integrator
+ * (esdg_set_integrator): classical RK4 (Butcher a = 1/2, 1/2, 1; b = 1/6, 1/3,
+ * 1/3, 1/6) in low-storage form (state, accumulator and two alternating stage
+ * buffers), or the five-stage 2N-storage scheme; each stage one fused
  * launch (surface flux + volume term + lifting + stage update).  dt > 0: fixed step; dt <= 0:
  * dt = cfl*2/((p+1) max_i sum_n (|v.Ja^n|+c|Ja^n|)/J_i) recomputed at the start
  * of every step on the device.  The problem's time (device, FP64) advances by
@@ -141,6 +142,19 @@ esdg_status esdg_rhs(esdg_problem *prob, double *du, int32_t where);
  * return the time reached (this synchronises the stream). */
 esdg_status esdg_step(esdg_problem *prob, double dt, int32_t nsteps, double cfl,
                       double *t_inout);
+
+/* Time integrators of esdg_step (and of a batch's members). */
+typedef enum {
+  ESDG_RK4 = 0,  /* classical four-stage RK4 (default) */
+  ESDG_CK45 = 1  /* five-stage, fourth-order 2N-storage RK of Carpenter and Kennedy,
+                    du <- A_i du + dt RHS(u), u <- u + B_i du (the scheme of the
+                    paper's FLUXO runs, Sec. 4.1); R holds du */
+} esdg_integrator;
+
+/* Select / read the integrator of later esdg_step calls (ESDG_EINVAL for an
+ * unknown one).  A batch records its members' integrators when created. */
+esdg_status esdg_set_integrator(esdg_problem *prob, int32_t integrator);
+esdg_status esdg_get_integrator(const esdg_problem *prob, int32_t *integrator);
 
 /* The problem's time (0 after esdg_init_mesh); esdg_get_time synchronises. */
 esdg_status esdg_set_time(esdg_problem *prob, double t);

@@ -23,6 +23,7 @@ struct BatchGroup {
   int64_t tiles = 0;
   void* desc = nullptr;       // device ProbDesc<Real>[members]
   int* tile_prob = nullptr;   // device: member index (within the group) of every tile
+  int integrator = ESDG_RK4;  // of every member, recorded when the batch is created
 };
 
 struct GraphEntry {
@@ -142,14 +143,12 @@ esdg_status group_step(esdg_batch* b, BatchGroup& g, hipStream_t s, const StepCt
   const Launcher L = launcher_on(b, s);
   StepCtl last = ctl;
   last.lam_update = ctl.cfl > 0.0 ? 1 : 0;
-  ESDG_TRY(run_stage_on<Real>(g.rep, L, g.k, g.desc, g.tile_prob, g.tiles, BUF_U, BUF_Y, nullptr, MODE_RK_FIRST,
-                              1.0 / 6.0, 0.5, ctl));
-  ESDG_TRY(run_stage_on<Real>(g.rep, L, g.k, g.desc, g.tile_prob, g.tiles, BUF_Y, BUF_Y2, nullptr, MODE_RK_MID,
-                              1.0 / 3.0, 0.5, ctl));
-  ESDG_TRY(run_stage_on<Real>(g.rep, L, g.k, g.desc, g.tile_prob, g.tiles, BUF_Y2, BUF_Y, nullptr, MODE_RK_MID,
-                              1.0 / 3.0, 1.0, ctl));
-  return run_stage_on<Real>(g.rep, L, g.k, g.desc, g.tile_prob, g.tiles, BUF_Y, BUF_U, nullptr, MODE_RK_LAST,
-                            1.0 / 6.0, 0.0, last);
+  StagePlan plan[kCkStages];
+  const int nst = step_plan(g.integrator, plan);
+  for (int i = 0; i < nst; ++i)
+    ESDG_TRY(run_stage_on<Real>(g.rep, L, g.k, g.desc, g.tile_prob, g.tiles, plan[i].in, plan[i].out, nullptr,
+                                plan[i].mode, plan[i].b, plan[i].a, i == nst - 1 ? last : ctl));
+  return ESDG_OK;
 }
 
 esdg_status enqueue_step(esdg_batch* b, const StepCtl& ctl) {
@@ -245,6 +244,10 @@ esdg_status check_batch(esdg_batch* b) {
   ESDG_HIP(&b->err, hipSetDevice(b->device));
   for (esdg_problem* P : b->probs)
     if (!P->have_state) return bfail(b, ESDG_ESTATE, "a member of the batch has no state");
+  for (const BatchGroup& g : b->groups)
+    for (int m : g.members)
+      if (b->probs[m]->integrator != g.integrator)
+        return bfail(b, ESDG_EINVAL, "a member's integrator changed after the batch was created");
   return ESDG_OK;
 }
 
@@ -330,7 +333,7 @@ static esdg_status batch_create_impl(esdg_problem* const* probs, int32_t count, 
     for (auto& g : b->groups) {
       const esdg_problem* R = g.rep;
       if (R->dim == P->dim && R->p == P->p && R->vf == P->vf && R->sf == P->sf && R->mesh == P->mesh &&
-          R->prec == P->prec && R->gamma == P->gamma && R->nodes == P->nodes) {
+          R->prec == P->prec && R->gamma == P->gamma && R->nodes == P->nodes && R->integrator == P->integrator) {
         hit = &g;
         break;
       }
@@ -339,6 +342,7 @@ static esdg_status batch_create_impl(esdg_problem* const* probs, int32_t count, 
       b->groups.emplace_back();
       hit = &b->groups.back();
       hit->rep = P;
+      hit->integrator = P->integrator;
     }
     hit->members.push_back(i);
     if (P->stream != b->stream && std::find(b->mstreams.begin(), b->mstreams.end(), P->stream) == b->mstreams.end())

@@ -556,9 +556,10 @@ esdg_status esdg_step(esdg_problem* P, double dt, int32_t nsteps, double cfl, do
   if (use_cfl && !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "dt <= 0 needs cfl > 0");
   if (t_inout) ESDG_TRY(set_time(P, *t_inout));
   if (nsteps > 0) {
-    // classical RK4 in low-storage form: U (state), R (accumulator) and the
-    // stage state, alternating between Y and Y2 (stage inputs are read across
-    // element faces, so a stage never writes its own input)
+    // classical RK4 in low-storage form (U state, R accumulator) or the 2N
+    // scheme (R holds du); stage states alternate between Y and Y2 (stage
+    // inputs are read across element faces, so a stage never writes its own
+    // input)
     StepCtl ctl;
     if (!use_cfl) {
       ctl.dt_fixed = dt;
@@ -568,19 +569,33 @@ esdg_status esdg_step(esdg_problem* P, double dt, int32_t nsteps, double cfl, do
       // last stage; otherwise from one reduction
       if (!P->lam_valid) ESDG_TRY(run_reduce(P, launcher_of(P), RED_MAXLAMBDA, cfl, lam_slot(P, P->par)));
     }
+    StagePlan plan[kCkStages];
+    const int nst = step_plan(P->integrator, plan);
     for (int s = 0; s < nsteps; ++s) {
       ctl.par = P->par;
       StepCtl last = ctl;
       last.lam_update = use_cfl ? 1 : 0;
-      ESDG_TRY(BY_PREC(P, run_stage, P, BUF_U, BUF_Y, nullptr, MODE_RK_FIRST, 1.0 / 6.0, 0.5, ctl));
-      ESDG_TRY(BY_PREC(P, run_stage, P, BUF_Y, BUF_Y2, nullptr, MODE_RK_MID, 1.0 / 3.0, 0.5, ctl));
-      ESDG_TRY(BY_PREC(P, run_stage, P, BUF_Y2, BUF_Y, nullptr, MODE_RK_MID, 1.0 / 3.0, 1.0, ctl));
-      ESDG_TRY(BY_PREC(P, run_stage, P, BUF_Y, BUF_U, nullptr, MODE_RK_LAST, 1.0 / 6.0, 0.0, last));
+      for (int i = 0; i < nst; ++i)
+        ESDG_TRY(BY_PREC(P, run_stage, P, plan[i].in, plan[i].out, nullptr, plan[i].mode, plan[i].b, plan[i].a,
+                         i == nst - 1 ? last : ctl));
       P->par = 1 - P->par;
     }
     P->lam_valid = use_cfl;
   }
   if (t_inout) ESDG_TRY(read_scalars(P, P->par, 1, t_inout));
+  return ESDG_OK;
+}
+
+esdg_status esdg_set_integrator(esdg_problem* P, int32_t integrator) {
+  if (!P) return fail(nullptr, ESDG_EINVAL, "NULL problem handle");
+  if (integrator != ESDG_RK4 && integrator != ESDG_CK45) return fail(P, ESDG_EINVAL, "unknown integrator %d", integrator);
+  P->integrator = integrator;
+  return ESDG_OK;
+}
+
+esdg_status esdg_get_integrator(const esdg_problem* P, int32_t* integrator) {
+  if (!P || !integrator) return fail(const_cast<esdg_problem*>(P), ESDG_EINVAL, "NULL argument");
+  *integrator = P->integrator;
   return ESDG_OK;
 }
 

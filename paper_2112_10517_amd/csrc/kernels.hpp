@@ -32,7 +32,17 @@ namespace esdg {
 enum VolFlux { VF_RANOCHA = 0, VF_SHIMA = 1, VF_CENTRAL = 3 };
 enum SurfFlux { SF_RANOCHA = 0, SF_SHIMA = 1, SF_LLF = 2, SF_CENTRAL = 3 };
 enum MeshKind { MESH_AFFINE = 0, MESH_CURVED = 1 };
-enum StageMode { MODE_RHS = 0, MODE_RK_FIRST = 1, MODE_RK_MID = 2, MODE_RK_LAST = 3 };
+// RK4 stages (classical scheme in low-storage form) and the stages of the
+// 2N-storage scheme (du <- A du + dt k; u <- u + B du; A = coef_a, B = coef_b)
+enum StageMode {
+  MODE_RHS = 0,
+  MODE_RK_FIRST = 1,
+  MODE_RK_MID = 2,
+  MODE_RK_LAST = 3,
+  MODE_LS_FIRST = 4,
+  MODE_LS_MID = 5,
+  MODE_LS_LAST = 6
+};
 enum RedOp { RED_TOTALS = 0, RED_ENTROPY = 1, RED_MAXLAMBDA = 2 };
 
 constexpr int kDevMaxN = 8;
@@ -550,7 +560,9 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
   const bool cfl_mode = a.cfl > 0.0;
   const auto lam_in = as_global((const unsigned long long*)P.lam + a.par * kLamSlots);
   unsigned long long* lam_next = P.lam + (1 - a.par) * kLamSlots;
-  const bool lam_out = a.mode == MODE_RK_LAST && cfl_mode && a.lam_update;
+  const bool first_stage = a.mode == MODE_RK_FIRST || a.mode == MODE_LS_FIRST;
+  const bool last_stage = a.mode == MODE_RK_LAST || a.mode == MODE_LS_LAST;
+  const bool lam_out = last_stage && cfl_mode && a.lam_update;
   const Real gm1 = a.ops.gamma - Real(1);
   if (tid < EPB) {
     const int e = e0 + tid;
@@ -703,7 +715,8 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
   // RK registers of the owned nodes, in flight while the line sums are merged
   Real ru0[NPT][NV], racc[NPT][NV];
   const bool need_u0 = a.mode == MODE_RK_MID;
-  const bool need_acc = a.mode == MODE_RK_MID || a.mode == MODE_RK_LAST;
+  const bool need_acc =
+      a.mode == MODE_RK_MID || a.mode == MODE_RK_LAST || a.mode == MODE_LS_MID || a.mode == MODE_LS_LAST;
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
@@ -751,8 +764,8 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
     const double t0 = time[a.par];
     const double rem = P.t_end - t0;
     if (dt > rem) dt = rem > 0.0 ? rem : 0.0;  // a NaN dt stays NaN
-    if (e0 == 0 && a.mode == MODE_RK_FIRST && cfl_mode && tid < kLamSlots) lam_next[tid] = 0ull;
-    if (e0 == 0 && a.mode == MODE_RK_LAST && tid == 0) time[1 - a.par] = t0 + dt;
+    if (e0 == 0 && first_stage && cfl_mode && tid < kLamSlots) lam_next[tid] = 0ull;
+    if (e0 == 0 && last_stage && tid == 0) time[1 - a.par] = t0 + dt;
   }
   double lam_max = 0.0;  // CFL wave-speed sum of the new state (LAST stage)
 #pragma unroll
@@ -802,6 +815,12 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
       } else if (a.mode == MODE_RK_MID) {
         racc_buf[o] = racc[r][v] + a.coef_b * (Real)dt * k;
         out[o] = ru0[r][v] + a.coef_a * (Real)dt * k;
+      } else if (a.mode >= MODE_LS_FIRST) {
+        // 2N storage: the accumulator holds du
+        const Real d = a.mode == MODE_LS_FIRST ? (Real)dt * k : a.coef_a * racc[r][v] + (Real)dt * k;
+        racc_buf[o] = d;
+        unew[v] = uin[o] + a.coef_b * d;
+        out[o] = unew[v];
       } else {
         unew[v] = racc[r][v] + a.coef_b * (Real)dt * k;
         out[o] = unew[v];

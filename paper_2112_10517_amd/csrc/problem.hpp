@@ -32,6 +32,7 @@ struct esdg_problem {
   int64_t E = 0;
   int vf = esdg::VF_RANOCHA, sf = esdg::SF_LLF, prec = esdg::PREC_FP64, mesh = esdg::MESH_AFFINE;
   int nodes = esdg::NODES_LGL;
+  int integrator = ESDG_RK4;  // esdg_integrator of esdg_step
   double gamma = 1.4;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -225,5 +226,36 @@ esdg_status convert_state(esdg_problem* P, const Launcher& L, const void* src, v
 esdg_status copy_parity(esdg_problem* P, const Launcher& L, int from);
 
 inline size_t state_count(const esdg_problem* P) { return (size_t)P->E * P->nv * P->nn; }
+
+// Coefficients of the five-stage, fourth-order 2N-storage scheme of Carpenter
+// and Kennedy (1994): du <- A_i du + dt RHS(u), u <- u + B_i du, A_1 = 0.
+constexpr int kCkStages = 5;
+constexpr double kCkA[kCkStages] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                                    -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+constexpr double kCkB[kCkStages] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                                    1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                                    2277821191437.0 / 14882151754819.0};
+
+// The stage launches of one step of P's integrator: (input buffer, output
+// buffer, mode, coef_b, coef_a) in order; the last one writes BUF_U.
+struct StagePlan {
+  int in, out, mode;
+  double b, a;
+};
+inline int step_plan(int integrator, StagePlan* s) {
+  if (integrator == ESDG_CK45) {
+    const int bufs[kCkStages + 1] = {BUF_U, BUF_Y, BUF_Y2, BUF_Y, BUF_Y2, BUF_U};
+    for (int i = 0; i < kCkStages; ++i)
+      s[i] = StagePlan{bufs[i], bufs[i + 1], i == 0 ? MODE_LS_FIRST : (i == kCkStages - 1 ? MODE_LS_LAST : MODE_LS_MID),
+                       kCkB[i], kCkA[i]};
+    return kCkStages;
+  }
+  // classical RK4 (a = 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6) in low-storage form
+  s[0] = StagePlan{BUF_U, BUF_Y, MODE_RK_FIRST, 1.0 / 6.0, 0.5};
+  s[1] = StagePlan{BUF_Y, BUF_Y2, MODE_RK_MID, 1.0 / 3.0, 0.5};
+  s[2] = StagePlan{BUF_Y2, BUF_Y, MODE_RK_MID, 1.0 / 3.0, 1.0};
+  s[3] = StagePlan{BUF_Y, BUF_U, MODE_RK_LAST, 1.0 / 6.0, 0.0};
+  return 4;
+}
 
 }  // namespace esdg

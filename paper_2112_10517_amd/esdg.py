@@ -23,6 +23,7 @@ PRECISION = {"fp64": 0, "fp32": 1}
 HOST, DEVICE = 0, 1
 KERNEL_STAGE, KERNEL_REDUCE, KERNEL_PROJECT = 1, 2, 3
 NODES = {"lgl": 0, "gauss": 1}
+INTEGRATORS = {"rk4": 0, "ck45": 1}
 PMAX = 7
 TILE_VARIANTS = 3
 BATCH_GRAPHS, BATCH_CONCURRENT = 1, 2
@@ -75,6 +76,8 @@ SIGNATURES = {
     "esdg_rhs": (_st, [_vp, _vp, _i32]),
     "esdg_step": (_st, [_vp, _d, _i32, _d, _dp]),
     "esdg_set_time": (_st, [_vp, _d]),
+    "esdg_set_integrator": (_st, [_vp, _i32]),
+    "esdg_get_integrator": (_st, [_vp, _pi32]),
     "esdg_get_time": (_st, [_vp, _dp]),
     "esdg_entropy_rate": (_st, [_vp, _dp]),
     "esdg_totals": (_st, [_vp, _dp]),
@@ -217,7 +220,7 @@ class Problem:
     def __init__(self, dim: int, p: int, n, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0),
                  warp: float = 0.0, gamma: float = 1.4, volume_flux: str = "ranocha",
                  surface_flux: str = "llf", precision: str = "fp64", coords=None, stream=None,
-                 nodes: str = "lgl"):
+                 nodes: str = "lgl", integrator: str = "rk4"):
         self._lib = load_library()
         d = mesh_desc(dim, p, n, lo, hi, warp, gamma, volume_flux, surface_flux, precision, nodes)
         keep = None
@@ -236,6 +239,8 @@ class Problem:
         self.n_elem, self.nodes, self.n_var = ne.value, nn.value, nv.value
         self.shape = (self.n_elem, self.n_var, self.nodes)
         self.n_dof = self.n_elem * self.nodes
+        if integrator != "rk4":
+            self.set_integrator(integrator)
 
     @staticmethod
     def _stream_ptr(stream):
@@ -308,6 +313,16 @@ class Problem:
         self._call(self._lib.esdg_step, float(dt), int(nsteps), float(cfl),
                    C.byref(tt) if t is not None else None)
         return tt.value if t is not None else None
+
+    def set_integrator(self, integrator):
+        """Integrator of later steps: "rk4" (classical, default) or "ck45" (five-stage 2N-storage)."""
+        k = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+        self._call(self._lib.esdg_set_integrator, k)
+
+    def integrator(self) -> str:
+        k = C.c_int32()
+        self._call(self._lib.esdg_get_integrator, C.byref(k))
+        return {v: n for n, v in INTEGRATORS.items()}[k.value]
 
     def set_time(self, t: float):
         self._call(self._lib.esdg_set_time, float(t))
