@@ -129,7 +129,7 @@ def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
         g.step(dt=dt, nsteps=10)
         res[prec] = g.get_state()
         g.set_state(u0_dev)
-        ms = time_steps(g, steps, 3, args.cfl, torch)
+        ms = time_steps(g, steps, 200, args.cfl, torch)
         res[prec + "_ms"] = ms
         g.close()
     err = max(np.abs(res["fp32"][:, v] - res["fp64"][:, v]).max() / np.abs(res["fp64"][:, v]).max()
@@ -143,13 +143,13 @@ def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
     # Shima (KEP, no log means) volume flux, FP64
     g = esdg.Problem(dim, p, (n, n, n), warp=0.1, volume_flux="shima", surface_flux="llf")
     g.set_state(u0_dev)
-    ms = time_steps(g, steps, 3, args.cfl, torch)
+    ms = time_steps(g, steps, 200, args.cfl, torch)
     g.close()
     out["shima_fp64"] = {"pid_ns": round(ms * 1e6 / (4 * nodes), 6), "ms_per_step": round(ms, 6)}
     # the five-stage 2N-storage integrator (five fused stage launches per step)
     g = esdg.Problem(dim, p, (n, n, n), warp=0.1, volume_flux=args.flux, surface_flux="llf", integrator="ck45")
     g.set_state(u0_dev)
-    ms = time_steps(g, steps, 3, args.cfl, torch)
+    ms = time_steps(g, steps, 200, args.cfl, torch)
     g.close()
     out["ck45_fp64"] = {"pid_ns": round(ms * 1e6 / (5 * nodes), 6), "ms_per_step": round(ms, 6), "rhs_per_step": 5}
     # Legendre-Gauss collocation with entropy projection against LGL, both on
@@ -159,7 +159,7 @@ def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
         g = esdg.Problem(dim, p, (n, n, n), volume_flux=args.flux, surface_flux="llf", nodes=kind)
         xg = torch.from_numpy(g.coords()).to(u0_dev.device)
         g.set_state(random_fourier_device(xg, 2, torch))
-        res[kind] = time_steps(g, steps, 3, args.cfl, torch)
+        res[kind] = time_steps(g, steps, 200, args.cfl, torch)
         if kind == "gauss":
             g.timing(True)
             g.timing_reset()
@@ -255,7 +255,7 @@ def precision_sweep(args, esdg, inputs, torch, dev):
             g.sync()
             res[prec + "_u"] = g.get_state()
             g.set_state(u0)
-            res[prec + "_ms"] = time_steps(g, args.sweep_steps, 2, args.sweep_cfl, torch)
+            res[prec + "_ms"] = time_steps(g, args.sweep_steps, 10, args.sweep_cfl, torch)
             nodes = g.n_dof
             g.close()
 
