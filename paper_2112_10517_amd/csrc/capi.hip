@@ -82,10 +82,21 @@ std::tuple<int, int, int, int, int, int> tune_key(const esdg_problem* P) {
 }
 }  // namespace
 
+// Variant used until the table holds one for the parameters: the node
+// layout (3) for 3D LGL problems of degree >= 4, where one lane per node
+// keeps enough waves per SIMD to hide the flux latencies and outruns the
+// line layout (measured at p = 4..7 in FP64, p = 4, 5, 7 in FP32); the line
+// layout (0) elsewhere.
+static int default_tile_variant(const esdg_problem* P) {
+  if (P->dim != 3 || P->nodes != NODES_LGL || P->N < 5) return 0;
+  if (P->prec == PREC_FP32 && P->N == 7) return 0;
+  return 3;
+}
+
 int tile_variant_of(const esdg_problem* P) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   auto it = g_tune.find(tune_key(P));
-  return it == g_tune.end() ? 0 : it->second;
+  return it == g_tune.end() ? default_tile_variant(P) : it->second;
 }
 
 int tile_table_version() {
@@ -95,9 +106,10 @@ int tile_table_version() {
 
 static void set_tile_variant(const esdg_problem* P, int v) {
   std::lock_guard<std::mutex> g(g_tune_mu);
-  int& cur = g_tune[tune_key(P)];
+  auto it = g_tune.find(tune_key(P));
+  const int cur = it == g_tune.end() ? default_tile_variant(P) : it->second;
   if (cur != v) ++g_tune_version;
-  cur = v;
+  g_tune[tune_key(P)] = v;
 }
 
 // stage kernel of tile variant v for P (Gauss collocation has variant 0 only)
@@ -666,10 +678,11 @@ esdg_status esdg_autotune(esdg_problem* P, int32_t reps, int32_t* best, double* 
   ESDG_TRY(check_handle(P, true));
   if (reps < 1) return fail(P, ESDG_EINVAL, "reps must be >= 1");
   // every variant computes the right-hand side of the current state into DU
-  // (the state is not modified); variants with the same tile size share one
-  // measurement
+  // (the state is not modified); variants that resolve to the same kernel
+  // share one measurement
   double us[ESDG_TILE_VARIANTS];
   int epb[ESDG_TILE_VARIANTS];
+  const void* fns[ESDG_TILE_VARIANTS];
   int pick = -1;
   Launcher L = launcher_of(P);
   L.timed = nullptr;
@@ -680,12 +693,14 @@ esdg_status esdg_autotune(esdg_problem* P, int32_t reps, int32_t* best, double* 
   for (int v = 0; v < ESDG_TILE_VARIANTS && st == ESDG_OK; ++v) {
     us[v] = -1.0;
     epb[v] = 0;
+    fns[v] = nullptr;
     const VolKernel k = kernel_of_variant(P, v);
     if (!k.fn) continue;
     epb[v] = k.epb;
+    fns[v] = k.fn;
     int same = -1;
     for (int w = 0; w < v; ++w)
-      if (epb[w] == k.epb) same = w;
+      if (fns[w] == k.fn) same = w;
     if (same >= 0) {
       us[v] = us[same];
       continue;

@@ -11,9 +11,10 @@ namespace esdg {
 template <int DIM, typename Real, int N, int VF, int MESH, int V>
 VolKernel vol_kernel() {
   constexpr int EPB = tile_epb(DIM, N, PrimCount<VF, DIM>::value, (int)sizeof(Real), V);
-  using T = Tile<DIM, N, EPB>;
+  constexpr int LAY = V == 3 ? LAY_NODES : LAY_LINES;  // variant 3: node layout
+  using T = Tile<DIM, N, EPB, LAY>;
   VolKernel k;
-  k.fn = (const void*)&stage_kernel<DIM, N, VF, MESH, Real, EPB>;
+  k.fn = (const void*)&stage_kernel<DIM, N, VF, MESH, Real, EPB, NODES_LGL, LAY>;
   k.epb = T::EPB;
   k.threads = T::THREADS;
   return k;

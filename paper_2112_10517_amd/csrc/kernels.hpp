@@ -150,6 +150,16 @@ struct Prim {
 // two-point volume fluxes in direction n (Sec. 3.2), from primitive values
 // ---------------------------------------------------------------------------
 
+// a b + c with one rounding
+__device__ __forceinline__ double mad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float mad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// The two-point flux code below compiles with contraction off and states
+// every fused multiply-add explicitly: left to the compiler, which products
+// get fused depends on the code around an inlined call, and the kernel
+// layouts (which inline the flux into different loops) must give the same
+// bits.
+
 // Log mean and inverse log mean (Sec. 3.1, Algorithms 2 and 3) with the
 // node logarithms precomputed (Sec. 7.2).  The branch of the algorithms,
 // u = ((a+ - a-)/(a+ + a-))^2 < eps, is decided without a division as
@@ -157,50 +167,82 @@ struct Prim {
 //   LM : series (a- + a+)(1/2 - u/6 - 2u^2/45 - 22u^3/945)  [the division-free
 //        variant of Algorithm 2 given in Sec. 3.1]   or   (a+ - a-) / (la+ - la-)
 //   ILM: series (2 + 2u/3 + 2u^2/5 + 2u^3/7)/(a- + a+)   or   (la+ - la-)/(a+ - a-)
+// Swapping the two arguments (and their logarithms) flips the sign of d and
+// of the log difference together, so both means are bitwise symmetric.
 template <typename Real>
 __device__ __forceinline__ Real log_mean_pre(Real am, Real ap, Real lam, Real lap) {
+#pragma clang fp contract(off)
   const Real s = am + ap, d = ap - am;
   const bool series = d * d < LogMeanEps<Real>::value * (s * s);
   const Real r = dev_rcp(series ? s : (lap - lam));
   const Real f = d * r;
   const Real u = f * f;
-  const Real poly = Real(0.5) + u * (Real(-1.0 / 6.0) + u * (Real(-2.0 / 45.0) + u * Real(-22.0 / 945.0)));
+  Real poly;
+  {
+    // Horner's scheme with fused multiply-adds formed within the expression
+    // (the fmuladd form keeps the register use of the stage kernels low,
+    // where explicit fma calls make them spill)
+#pragma clang fp contract(on)
+    poly = Real(0.5) + u * (Real(-1.0 / 6.0) + u * (Real(-2.0 / 45.0) + u * Real(-22.0 / 945.0)));
+  }
   return series ? s * poly : f;
 }
 
 template <typename Real>
 __device__ __forceinline__ Real inv_log_mean_pre(Real am, Real ap, Real lam, Real lap) {
+#pragma clang fp contract(off)
   const Real s = am + ap, d = ap - am;
   const bool series = d * d < LogMeanEps<Real>::value * (s * s);
   const Real r = dev_rcp(series ? s : d);
   const Real f = d * r;
   const Real u = f * f;
-  const Real poly = Real(2) + u * (Real(2.0 / 3.0) + u * (Real(2.0 / 5.0) + u * Real(2.0 / 7.0)));
+  Real poly;
+  {
+#pragma clang fp contract(on)  // as in log_mean_pre
+    poly = Real(2) + u * (Real(2.0 / 3.0) + u * (Real(2.0 / 5.0) + u * Real(2.0 / 7.0)));
+  }
   return series ? r * poly : (lap - lam) * r;
 }
 
+// v . n of one state
+template <int DIM, typename Real>
+__device__ __forceinline__ Real dot_n(Real v0, Real v1, Real v2, Real nx, Real ny, Real nz) {
+#pragma clang fp contract(off)
+  Real r = v0 * nx;
+  if (DIM > 1) r = mad(v1, ny, r);
+  if (DIM > 2) r = mad(v2, nz, r);
+  return r;
+}
+
 // Directional volume flux f(u_i, u_k, n) into F[0..DIM+1].  NX/NY/NZ are the
-// normal components (compile-time constants for the affine mesh).
+// normal components (compile-time constants for the affine mesh).  Every
+// expression is symmetric in the two states down to the rounding (sums and
+// products of the two sides commute, fused products pair a value of one side
+// with the same value of the other, mixed products p_a (v.n)_b + p_b (v.n)_a
+// are rounded before their sum), so f(u_a, u_b, n) and f(u_b, u_a, n) are
+// bitwise equal: a kernel may evaluate a pair from either end and get the
+// bits of the other.
 template <int VF, int DIM, typename Real>
 __device__ __forceinline__ void volume_flux(const Prim<Real>& a, const Prim<Real>& b, Real nx, Real ny,
                                             Real nz, Real inv_gm1, Real* F) {
-  const Real vna = a.v0 * nx + (DIM > 1 ? a.v1 * ny : Real(0)) + (DIM > 2 ? a.v2 * nz : Real(0));
-  const Real vnb = b.v0 * nx + (DIM > 1 ? b.v1 * ny : Real(0)) + (DIM > 2 ? b.v2 * nz : Real(0));
+#pragma clang fp contract(off)
+  const Real vna = dot_n<DIM>(a.v0, a.v1, a.v2, nx, ny, nz);
+  const Real vnb = dot_n<DIM>(b.v0, b.v1, b.v2, nx, ny, nz);
   const Real vn_avg = Real(0.5) * (vna + vnb);
   const Real p_avg = Real(0.5) * (a.p + b.p);
-  const Real vv = a.v0 * b.v0 + (DIM > 1 ? a.v1 * b.v1 : Real(0)) + (DIM > 2 ? a.v2 * b.v2 : Real(0));
+  const Real vv = dot_n<DIM>(a.v0, a.v1, a.v2, b.v0, b.v1, b.v2);
   const Real pvn = Real(0.5) * (b.p * vna + a.p * vnb);  // ((p; v.n))
   if (VF == VF_CENTRAL) {
     // (f(u_a) + f(u_b)).n / 2 with f written in primitive variables
     const Real ka = a.rho * vna, kb = b.rho * vnb;
     F[0] = Real(0.5) * (ka + kb);
-    F[1] = Real(0.5) * (ka * a.v0 + kb * b.v0) + p_avg * nx;
-    if (DIM > 1) F[2] = Real(0.5) * (ka * a.v1 + kb * b.v1) + p_avg * ny;
-    if (DIM > 2) F[3] = Real(0.5) * (ka * a.v2 + kb * b.v2) + p_avg * nz;
-    const Real va2 = a.v0 * a.v0 + (DIM > 1 ? a.v1 * a.v1 : Real(0)) + (DIM > 2 ? a.v2 * a.v2 : Real(0));
-    const Real vb2 = b.v0 * b.v0 + (DIM > 1 ? b.v1 * b.v1 : Real(0)) + (DIM > 2 ? b.v2 * b.v2 : Real(0));
-    const Real ea = a.p * inv_gm1 + Real(0.5) * a.rho * va2 + a.p;
-    const Real eb = b.p * inv_gm1 + Real(0.5) * b.rho * vb2 + b.p;
+    F[1] = mad(p_avg, nx, Real(0.5) * (ka * a.v0 + kb * b.v0));
+    if (DIM > 1) F[2] = mad(p_avg, ny, Real(0.5) * (ka * a.v1 + kb * b.v1));
+    if (DIM > 2) F[3] = mad(p_avg, nz, Real(0.5) * (ka * a.v2 + kb * b.v2));
+    const Real va2 = dot_n<DIM>(a.v0, a.v1, a.v2, a.v0, a.v1, a.v2);
+    const Real vb2 = dot_n<DIM>(b.v0, b.v1, b.v2, b.v0, b.v1, b.v2);
+    const Real ea = mad(a.p, inv_gm1, Real(0.5) * a.rho * va2) + a.p;
+    const Real eb = mad(b.p, inv_gm1, Real(0.5) * b.rho * vb2) + b.p;
     F[DIM + 1] = Real(0.5) * (ea * vna + eb * vnb);
     return;
   }
@@ -214,11 +256,12 @@ __device__ __forceinline__ void volume_flux(const Prim<Real>& a, const Prim<Real
     frho = Real(0.5) * (a.rho + b.rho) * vn_avg;
     fe_int = p_avg * vn_avg * inv_gm1;
   }
+  const Real hf = Real(0.5) * frho;
   F[0] = frho;
-  F[1] = frho * Real(0.5) * (a.v0 + b.v0) + p_avg * nx;
-  if (DIM > 1) F[2] = frho * Real(0.5) * (a.v1 + b.v1) + p_avg * ny;
-  if (DIM > 2) F[3] = frho * Real(0.5) * (a.v2 + b.v2) + p_avg * nz;
-  F[DIM + 1] = Real(0.5) * frho * vv + fe_int + pvn;
+  F[1] = mad(hf, a.v0 + b.v0, p_avg * nx);
+  if (DIM > 1) F[2] = mad(hf, a.v1 + b.v1, p_avg * ny);
+  if (DIM > 2) F[3] = mad(hf, a.v2 + b.v2, p_avg * nz);
+  F[DIM + 1] = mad(hf, vv, fe_int) + pvn;
 }
 
 // ---------------------------------------------------------------------------
@@ -311,21 +354,35 @@ struct TileShape {
   static constexpr int EPB0 = (64 / L) > 0 ? 64 / L : 1;  // default elements per block: one wave per direction
 };
 
-template <int DIM, int N, int EPB_ = TileShape<DIM, N>::EPB0>
+// Work layout of the volume term.  LAY_LINES: one lane per (direction,
+// element, line) evaluates each i<k pair of its line once and scatters to
+// both nodes.  LAY_NODES: one lane per node sweeps its N-1 partners along
+// each direction in turn and accumulates its own row only; every pair is
+// evaluated from both ends (twice the flux evaluations), in exchange for a
+// register footprint of one node instead of one line, hence more waves per
+// SIMD at high degree.  Both layouts add the same terms in the same order, so
+// they give the same bits.
+enum Layout { LAY_LINES = 0, LAY_NODES = 1 };
+
+template <int DIM, int N, int EPB_ = TileShape<DIM, N>::EPB0, int LAY_ = LAY_LINES>
 struct Tile {
   static constexpr int NN = Pow<N, DIM>::value;   // nodes per element
   static constexpr int NF = NN / N;               // nodes per face
   static constexpr int L = NN / N;                // lines per direction
   static constexpr int NFACE = 2 * DIM * NF;      // face nodes per element
   static constexpr int EPB = EPB_;                // elements per block
-  static constexpr int LANES_DIR = ((EPB * L + 63) / 64) * 64;  // lanes per direction
-  static constexpr int THREADS = DIM * LANES_DIR;
+  static constexpr int LAY = LAY_;
+  // lanes per direction (line layout); the node layout has one group of lanes
+  static constexpr int LANES_DIR = LAY == LAY_LINES ? ((EPB * L + 63) / 64) * 64 : ((EPB * NN + 63) / 64) * 64;
+  static constexpr int THREADS = LAY == LAY_LINES ? DIM * LANES_DIR : LANES_DIR;
   static constexpr int NPT = (EPB * NN + THREADS - 1) / THREADS;     // nodes per lane
   static constexpr int FPT = (EPB * NFACE + THREADS - 1) / THREADS;  // face nodes per lane
   static constexpr int NV = DIM + 2;
   // waves per SIMD the register allocation must allow: every workgroup of a
-  // typical launch resident at once (3 x 64-lane waves per SIMD for N <= 4)
-  static constexpr int WPE = N <= 4 ? 3 : (N <= 6 ? 2 : 1);
+  // typical launch resident at once (3 x 64-lane waves per SIMD for N <= 4);
+  // node layout: two workgroups of up to 8 waves per CU
+  static constexpr int WPE = LAY == LAY_NODES ? 4 : (N <= 4 ? 3 : (N <= 6 ? 2 : 1));
+  static_assert(LAY == LAY_LINES || NPT == 1, "node layout: one node per lane");
 };
 
 // LDS budget of one workgroup of a tile variant (two workgroups fit a CU)
@@ -350,6 +407,25 @@ constexpr int tile_epb(int dim, int N, int np, int rbytes, int variant) {
     return epb0;
   }
   if (variant == 2) return 2 * epb0 * per <= kTileLdsCap ? 2 * epb0 : epb0;
+  if (variant == 3) {
+    // node layout (LDS: primitives, two direction buffers of halved
+    // contravariant vectors, face fluxes): of the tiles of at least 128 and at
+    // most 1024 lanes within the LDS budget, the one that leaves the fewest
+    // lanes idle, the smaller on a tie
+    const int pn = ((np + 2 * dim) * nn + nv * nface) * rbytes + 2 * dim * 4;
+    int best = 1;
+    long best_num = 0, best_den = 1;
+    for (int e = 1; e <= 32 && e * nn <= 1024; ++e) {
+      const int lanes = (e * nn + 63) / 64 * 64;
+      if ((lanes < 128 && (e + 1) * nn <= 1024) || (e > 1 && e * pn > kTileLdsCap)) continue;
+      if ((long)e * nn * best_den > best_num * (long)lanes) {
+        best = e;
+        best_num = (long)e * nn;
+        best_den = lanes;
+      }
+    }
+    return best;
+  }
   return epb0;
 }
 
@@ -443,6 +519,9 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
                                             const StageOps<Real>& ops, const Real* s_dt, Real scale,
                                             Real (&A)[N][DIM + 2], const Real (*fo)[DIM + 4] = nullptr,
                                             const Real (*fn)[DIM + 4] = nullptr, int surf = 0) {
+  // contraction off: the affine scaling below must not fuse with the caller's
+  // sum over directions (the layouts sum them in different places)
+#pragma clang fp contract(off)
   constexpr int NV = DIM + 2;
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int stride = Pow<N, DIR>::value;
@@ -479,8 +558,8 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
       const Real dki = DtInLds<N, Real>::value ? s_dt[k * N + i] : ops.Dt[k * N + i];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        A[i][v] += dik * F[v];
-        A[k][v] += dki * F[v];
+        A[i][v] = mad(dik, F[v], A[i][v]);
+        A[k][v] = mad(dki, F[v], A[k][v]);
       }
     }
   }
@@ -502,15 +581,15 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
         const Real c = s ? ops.cR[k] : ops.cL[k], r = s ? ops.rR[k] : ops.rL[k];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          A[k][v] += c * F[v];
-          G[v] += r * F[v];
+          A[k][v] = mad(c, F[v], A[k][v]);
+          G[v] = mad(r, F[v], G[v]);
         }
       }
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         const Real c = s ? ops.cR[k] : ops.cL[k];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) A[k][v] += c * (Fs[v] - G[v]);
+        for (int v = 0; v < NV; ++v) A[k][v] = mad(c, Fs[v] - G[v], A[k][v]);
       }
     }
   }
@@ -522,28 +601,87 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
   }
 }
 
+// The partners of one node along direction DIR (node layout): the lane reads
+// each partner's primitive variables and halved contravariant vector from
+// LDS, evaluates f(u_i, u_k) (bitwise the pair's flux, see volume_flux) and
+// accumulates D~_ik F in increasing k, the order in which the line layout's
+// pair loop reaches node i.  sn holds the halved contravariant vectors of
+// direction DIR of the element ([DIM][NN]); no is the node's own.
+template <int DIR, int DIM, int N, int VF, int MESH, typename Real>
+__device__ __forceinline__ void node_fluxes(const Real (*sp)[Pow<N, DIM>::value], const Real (*sn)[Pow<N, DIM>::value],
+                                            const Prim<Real>& Po, const Real (&no)[3], int i, int id,
+                                            const Real* s_dt, Real scale, Real inv_gm1, Real (&A)[DIM + 2]) {
+#pragma clang fp contract(off)  // as in line_fluxes
+  constexpr int NV = DIM + 2;
+  constexpr int NP = PrimCount<VF, DIM>::value;
+  constexpr int stride = Pow<N, DIR>::value;
+  const int base = i - id * stride;
+  const Real* drow = s_dt + id * N;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) A[v] = Real(0);
+  // a rolled loop: unrolled, the partners' loads are hoisted ahead of the
+  // fluxes and the registers spill
+#pragma unroll 1
+  for (int j = 0; j < N - 1; ++j) {
+    const int k = j + (j >= id ? 1 : 0);
+    const int q = base + k * stride;
+    Prim<Real> Pk;
+    Pk.rho = sp[0][q];
+    Pk.v0 = sp[1][q];
+    Pk.v1 = DIM > 1 ? sp[DIM > 1 ? 2 : 0][q] : Real(0);
+    Pk.v2 = DIM > 2 ? sp[DIM > 2 ? 3 : 0][q] : Real(0);
+    Pk.p = sp[DIM + 1][q];
+    Pk.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][q] : Real(0);
+    Pk.lp = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][q] : Real(0);
+    Real F[NV];
+    if (MESH == MESH_CURVED) {
+      volume_flux<VF, DIM>(Po, Pk, no[0] + sn[0][q], DIM > 1 ? no[1] + sn[DIM > 1 ? 1 : 0][q] : Real(0),
+                           DIM > 2 ? no[2] + sn[DIM > 2 ? 2 : 0][q] : Real(0), inv_gm1, F);
+    } else {
+      volume_flux<VF, DIM>(Po, Pk, DIR == 0 ? Real(1) : Real(0), DIR == 1 ? Real(1) : Real(0),
+                           DIR == 2 ? Real(1) : Real(0), inv_gm1, F);
+    }
+    const Real dik = drow[k];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) A[v] = mad(dik, F[v], A[v]);
+  }
+  if (MESH == MESH_AFFINE) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) A[v] *= scale;
+  }
+}
+
 // Waves per SIMD the register allocation of a tile must allow: the tile's
-// default, except for the FP32 p = 7 affine tile, which fits three waves
-// without spilling (measured faster; the curved one would spill).
-template <int DIM, int N, int MESH, typename Real, int EPB_>
+// default, except for the FP32 p = 7 affine tile of the line layout, which
+// fits three waves without spilling (measured faster; the curved one would
+// spill).
+template <int DIM, int N, int MESH, typename Real, int EPB_, int LAY = LAY_LINES>
 struct StageWaves {
-  static constexpr int value = (sizeof(Real) == 4 && N == 8 && MESH == MESH_AFFINE) ? 3 : Tile<DIM, N, EPB_>::WPE;
+  static constexpr int value = (LAY == LAY_LINES && sizeof(Real) == 4 && N == 8 && MESH == MESH_AFFINE)
+                                   ? 3
+                                   : Tile<DIM, N, EPB_, LAY>::WPE;
 };
 
-template <int DIM, int N, int VF, int MESH, typename Real, int EPB_, int NODES = NODES_LGL>
-__global__ void __launch_bounds__((Tile<DIM, N, EPB_>::THREADS))
-__attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))) stage_kernel(StageArgs<Real> a) {
+template <int DIM, int N, int VF, int MESH, typename Real, int EPB_, int NODES = NODES_LGL, int LAY = LAY_LINES>
+__global__ void __launch_bounds__((Tile<DIM, N, EPB_, LAY>::THREADS))
+__attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::value))) stage_kernel(StageArgs<Real> a) {
   static_assert(NODES == NODES_LGL || MESH == MESH_AFFINE, "Gauss collocation is built for affine meshes");
-  using T = Tile<DIM, N, EPB_>;
+  static_assert(LAY == LAY_LINES || (NODES == NODES_LGL && DIM == 3), "node layout: 3D LGL");
+  using T = Tile<DIM, N, EPB_, LAY>;
+  constexpr bool NODEL = LAY == LAY_NODES;
+  constexpr bool CNODE = NODEL && MESH == MESH_CURVED;
   constexpr int NN = T::NN, NF = T::NF, L = T::L, EPB = T::EPB, NV = T::NV, NFACE = T::NFACE;
   constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, LANES_DIR = T::LANES_DIR;
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int NM = DIM * DIM + 1;
   __shared__ Real s_prim[EPB][NP][NN];     // primitive variables (and logs)
   __shared__ Real s_face[EPB][NV][NFACE];  // surface fluxes of the element's faces
-  __shared__ Real s_acc[EPB][NV][NN];      // volume term, summed over directions in order
+  __shared__ Real s_acc[NODEL ? 1 : EPB][NV][NODEL ? 1 : NN];  // volume term, summed over directions in order
   __shared__ int s_nbr[EPB][2 * DIM];      // neighbour across face (2 dir + side), side 1 = +
-  __shared__ Real s_dt[DtInLds<N, Real>::value ? N * N : 1];  // D~ when it stays out of scalar registers
+  __shared__ Real s_dt[(NODEL || DtInLds<N, Real>::value) ? N * N : 1];  // D~ when it stays out of scalar registers
+  // node layout, curved: halved contravariant vectors of two directions
+  // (directions 0 and 1, then 2 in the first buffer)
+  __shared__ Real s_nrm[CNODE ? EPB : 1][2][DIM][CNODE ? NN : 1];
 
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -608,14 +746,24 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
                                    : Real(1);
   }
   Real nrm[N][3];
-  if (MESH == MESH_CURVED) {
+  Real hm[DIM][3];  // node layout, curved: the node's halved contravariant vectors
+  if constexpr (CNODE) {
+    const int el = tid / NN, i = tid - el * NN;
+    const bool ok = tid < EPB * NN && e0 + el < E;
+    const auto me = metric + (ok ? (size_t)(e0 + el) * (NM * NN) + i : 0);
+#pragma unroll
+    for (int n = 0; n < DIM; ++n)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) hm[n][m] = m < DIM ? Real(0.5) * me[(n * DIM + m) * NN] : Real(0);
+  }
+  if (MESH == MESH_CURVED && !NODEL) {
     const auto me = metric + (size_t)(lactive ? e0 + lel : 0) * (NM * NN);
 #pragma unroll
     for (int k = 0; k < N; ++k)
 #pragma unroll
       for (int m = 0; m < 3; ++m) nrm[k][m] = m < DIM ? Real(0.5) * me[(ldir * DIM + m) * NN + lbase + k * stride] : Real(0);
   }
-  if (DtInLds<N, Real>::value)
+  if (NODEL || DtInLds<N, Real>::value)
     for (int t = tid; t < N * N; t += THREADS) s_dt[t] = a.ops.Dt[t];
   __syncthreads();  // s_nbr, s_dt
   Real tL[FPT][NV], tR[FPT][NV], tn[FPT][3];
@@ -686,6 +834,12 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
       s_prim[el][(NP > DIM + 2) ? DIM + 2 : 0][i] = dev_log(rho);
       s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][i] = dev_log(p);
     }
+    if constexpr (CNODE) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) s_nrm[el][b][m][i] = hm[b][m];
+    }
   }
 
   // ---- surface fluxes of the element's faces (LGL; Gauss lines handle their own ends)
@@ -701,9 +855,55 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
   }
   __syncthreads();
 
-  // ---- volume term: each lane sweeps the pairs of its line
+  // ---- volume term, node layout: each lane sweeps the partners of its node,
+  // direction by direction, and sums the directions in the line layout's order
+  Real Sn[NV];
+  if constexpr (NODEL) {
+    const bool ok = tid < EPB * NN && e0 + tid / NN < E;
+    const int el = ok ? tid / NN : 0, i = ok ? tid - el * NN : 0;  // idle lanes repeat node 0
+    const Real(*sp)[NN] = s_prim[el];
+    const int ix = i % N, iy = (i / N) % N, iz = i / (N * N);
+    Prim<Real> Po;
+    Po.rho = sp[0][i];
+    Po.v0 = sp[1][i];
+    Po.v1 = sp[2][i];
+    Po.v2 = sp[3][i];
+    Po.p = sp[4][i];
+    Po.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][i] : Real(0);
+    Po.lp = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][i] : Real(0);
+    Real no[3] = {Real(0), Real(0), Real(0)};
+    Real Ad[NV];
+    if constexpr (CNODE) { no[0] = hm[0][0]; no[1] = hm[0][1]; no[2] = hm[0][2]; }
+    // the two direction buffers (never read on affine meshes)
+    const Real(*sn0)[NN] = reinterpret_cast<const Real(*)[NN]>(&s_nrm[CNODE ? el : 0][0][0][0]);
+    const Real(*sn1)[NN] = reinterpret_cast<const Real(*)[NN]>(&s_nrm[CNODE ? el : 0][1][0][0]);
+    node_fluxes<0, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, ix, s_dt, P.scale[0],
+                                            a.ops.inv_gm1, Ad);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Sn[v] = Ad[v];
+    if constexpr (CNODE) { no[0] = hm[1][0]; no[1] = hm[1][1]; no[2] = hm[1][2]; }
+    node_fluxes<1, DIM, N, VF, MESH, Real>(sp, sn1, Po, no, i, iy, s_dt, P.scale[1],
+                                            a.ops.inv_gm1, Ad);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Sn[v] += Ad[v];
+    if constexpr (CNODE) {
+      // direction 2 replaces direction 0 in the first buffer
+      __syncthreads();
+      if (tid < EPB * NN && e0 + tid / NN < E)
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) s_nrm[el][0][m][i] = hm[2][m];
+      __syncthreads();
+      no[0] = hm[2][0]; no[1] = hm[2][1]; no[2] = hm[2][2];
+    }
+    node_fluxes<2, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, iz, s_dt, P.scale[2],
+                                            a.ops.inv_gm1, Ad);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Sn[v] += Ad[v];
+  }
+
+  // ---- volume term, line layout: each lane sweeps the pairs of its line
   Real A[N][NV];
-  {
+  if constexpr (!NODEL) {
     const Real(*sp)[NN] = s_prim[lactive ? lel : 0];
     const Real sc = P.scale[ldir];
     if (ldir == 0) line_fluxes<0, DIM, N, VF, MESH, Real, NODES>(sp, nrm, lbase, a.ops, s_dt, sc, A, fo, fnb, a.surf);
@@ -731,7 +931,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
   }
   // fixed summation order over directions: dir 0 writes, then dir 1, dir 2 add
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
+  for (int d = 0; d < (NODEL ? 0 : DIM); ++d) {
     if (ldir == d && lactive) {
 #pragma unroll
       for (int k = 0; k < N; ++k) {
@@ -779,7 +979,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_>::value))
     const int iz = DIM > 2 ? i / (N * N) : 0;
     Real S[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) S[v] = s_acc[el][v][i];
+    for (int v = 0; v < NV; ++v) S[v] = NODEL ? Sn[v] : s_acc[NODEL ? 0 : el][v][NODEL ? 0 : i];
 #pragma unroll
     for (int dir = 0; dir < DIM && NODES == NODES_LGL; ++dir) {
       const int id = dir == 0 ? ix : (dir == 1 ? iy : iz);
