@@ -2,9 +2,9 @@
 //
 // One launch per right-hand side or RK stage, stage_kernel<DIM,N,VF,MESH>:
 // a workgroup owns EPB elements (Tile<DIM,N>) and
-//   prologue  loads u coalesced and computes the primitive variables and
-//             log(rho), log(p) once per node into LDS (Sec. 7.1/7.2
-//             precomputation);
+//   prologue  loads u coalesced and computes the primitive variables,
+//             log(rho), beta = rho/p and log(beta) once per node into LDS
+//             (Sec. 7.1/7.2 precomputation);
 //   lines     one lane per (direction, element, line): the lane evaluates the
 //             N(N-1)/2 pairs i<k of its line once each, with the two-point
 //             volume flux in the direction of the averaged contravariant
@@ -72,7 +72,7 @@ struct ProbDesc {
   unsigned long long* lam;   // CFL: 2 x kLamSlots slots by step parity (bit patterns of non-negative doubles)
   double* time;              // time of the state, 2 slots by step parity
   int* flag;                 // non-physical state flag
-  Real* faceb;               // Gauss: entropy-projected face states [E][2 dim][dim+4][nf] (rho, v, p, log rho, log p)
+  Real* faceb;               // Gauss: entropy-projected face states [E][2 dim][dim+4][nf] (rho, v, p, log rho, log beta)
   double t_end;              // a step never passes t_end: dt = min(dt, t_end - t)
   int E, n0, n1, n2;         // elements, per direction
   int tile0;                 // first tile of this problem in the launch
@@ -116,9 +116,12 @@ struct Pow { static constexpr int value = B * Pow<B, K - 1>::value; };
 template <int B>
 struct Pow<B, 0> { static constexpr int value = 1; };
 
-template <typename Real> struct LogMeanEps;
-template <> struct LogMeanEps<double> { static constexpr double value = 1.0e-4; };
-template <> struct LogMeanEps<float> { static constexpr float value = 2.0e-2f; };
+// Series cutoff of the log means: u = ((a+ - a-)/(a+ + a-))^2 < eps, eps =
+// 1e-4 in FP64 (Sec. 3.1) and 2e-2 in FP32; tested as |a+ - a-| < sqrt(eps)
+// (a+ + a-) (both arguments positive)
+template <typename Real> struct LogMeanCut;
+template <> struct LogMeanCut<double> { static constexpr double value = 1.0e-2; };
+template <> struct LogMeanCut<float> { static constexpr float value = 0.14142135623730950f; };
 
 __device__ __forceinline__ double dev_log(double x) { return log(x); }
 __device__ __forceinline__ float dev_log(float x) { return logf(x); }
@@ -139,11 +142,11 @@ __device__ __forceinline__ float dev_rcp(float q) {
   return __builtin_amdgcn_rcpf(q);  // 1 ulp: below the FP32 parity bar, no refinement
 }
 
-// Primitive variables at one node, with log(rho) and log(p) when the volume
-// flux needs log means.
+// Primitive variables at one node, with log(rho), beta = rho/p and log(beta)
+// when the volume flux needs log means.
 template <typename Real>
 struct Prim {
-  Real rho, v0, v1, v2, p, lr, lp;
+  Real rho, v0, v1, v2, p, lr, b, lb;
 };
 
 // ---------------------------------------------------------------------------
@@ -163,7 +166,7 @@ __device__ __forceinline__ float mad(float a, float b, float c) { return __built
 // Log mean and inverse log mean (Sec. 3.1, Algorithms 2 and 3) with the
 // node logarithms precomputed (Sec. 7.2).  The branch of the algorithms,
 // u = ((a+ - a-)/(a+ + a-))^2 < eps, is decided without a division as
-// (a+ - a-)^2 < eps (a+ + a-)^2; each mean then costs one reciprocal:
+// |a+ - a-| < sqrt(eps) (a+ + a-); each mean then costs one reciprocal:
 //   LM : series (a- + a+)(1/2 - u/6 - 2u^2/45 - 22u^3/945)  [the division-free
 //        variant of Algorithm 2 given in Sec. 3.1]   or   (a+ - a-) / (la+ - la-)
 //   ILM: series (2 + 2u/3 + 2u^2/5 + 2u^3/7)/(a- + a+)   or   (la+ - la-)/(a+ - a-)
@@ -173,7 +176,7 @@ template <typename Real>
 __device__ __forceinline__ Real log_mean_pre(Real am, Real ap, Real lam, Real lap) {
 #pragma clang fp contract(off)
   const Real s = am + ap, d = ap - am;
-  const bool series = d * d < LogMeanEps<Real>::value * (s * s);
+  const bool series = fabs(d) < LogMeanCut<Real>::value * s;
   const Real r = dev_rcp(series ? s : (lap - lam));
   const Real f = d * r;
   const Real u = f * f;
@@ -192,7 +195,7 @@ template <typename Real>
 __device__ __forceinline__ Real inv_log_mean_pre(Real am, Real ap, Real lam, Real lap) {
 #pragma clang fp contract(off)
   const Real s = am + ap, d = ap - am;
-  const bool series = d * d < LogMeanEps<Real>::value * (s * s);
+  const bool series = fabs(d) < LogMeanCut<Real>::value * s;
   const Real r = dev_rcp(series ? s : d);
   const Real f = d * r;
   const Real u = f * f;
@@ -249,9 +252,11 @@ __device__ __forceinline__ void volume_flux(const Prim<Real>& a, const Prim<Real
   Real frho, fe_int;
   if (VF == VF_RANOCHA) {
     frho = log_mean_pre(a.rho, b.rho, a.lr, b.lr) * vn_avg;
-    // 1/{{rho/p}}_log = p_a p_b / {{rho_a p_b, rho_b p_a}}_log (Sec. 3.2)
-    const Real ilm = inv_log_mean_pre(a.rho * b.p, b.rho * a.p, a.lr + b.lp, b.lr + a.lp);
-    fe_int = frho * (a.p * b.p) * ilm * inv_gm1;
+    // Sec. 3.2 writes 1/{{rho/p}}_log as p_a p_b / {{rho_a p_b, rho_b p_a}}_log;
+    // the log mean is homogeneous of degree one, so that is 1/{{beta}}_log
+    // with beta = rho/p taken once per node
+    const Real ilm = inv_log_mean_pre(a.b, b.b, a.lb, b.lb);
+    fe_int = frho * ilm * inv_gm1;
   } else {  // Shima et al.
     frho = Real(0.5) * (a.rho + b.rho) * vn_avg;
     fe_int = p_avg * vn_avg * inv_gm1;
@@ -277,7 +282,7 @@ __device__ __forceinline__ void cons_to_prim(const Real* u, Real gm1, Prim<Real>
   P.v2 = DIM > 2 ? u[3] * ir : Real(0);
   P.p = gm1 * (u[DIM + 1] - Real(0.5) * (u[1] * P.v0 + (DIM > 1 ? u[2] * P.v1 : Real(0)) +
                                           (DIM > 2 ? u[3] * P.v2 : Real(0))));
-  P.lr = P.lp = Real(0);
+  P.lr = P.b = P.lb = Real(0);
 }
 
 // f*(u_L, u_R, n) of kind sf (runtime, uniform across the launch)
@@ -290,9 +295,11 @@ __device__ __forceinline__ void surface_flux(int sf, const Real* uL, const Real*
   cons_to_prim<DIM>(uR, gm1, PR);
   if (sf == SF_RANOCHA) {
     PL.lr = dev_log(PL.rho);
-    PL.lp = dev_log(PL.p);
+    PL.b = PL.rho * dev_rcp(PL.p);
+    PL.lb = dev_log(PL.b);
     PR.lr = dev_log(PR.rho);
-    PR.lp = dev_log(PR.p);
+    PR.b = PR.rho * dev_rcp(PR.p);
+    PR.lb = dev_log(PR.b);
     volume_flux<VF_RANOCHA, DIM>(PL, PR, nx, ny, nz, inv_gm1, F);
   } else if (sf == SF_SHIMA) {
     volume_flux<VF_SHIMA, DIM>(PL, PR, nx, ny, nz, inv_gm1, F);
@@ -398,7 +405,7 @@ constexpr int tile_epb(int dim, int N, int np, int rbytes, int variant) {
   for (int j = 0; j < dim; ++j) nn *= N;
   const int L = nn / N, nv = dim + 2, nface = 2 * dim * L;
   const int epb0 = 64 / L > 0 ? 64 / L : 1;
-  const int per = ((np + nv) * nn + nv * nface) * rbytes + 2 * dim * 4;
+  const int per = (np * nn + nv * nface) * rbytes + 2 * dim * 4;  // primitives (volume sums alias them), face fluxes
   if (variant == 1) {
     for (int e = epb0; e <= 32; ++e) {
       const int lanes = (e * L + 63) / 64 * 64;
@@ -437,7 +444,7 @@ template <int N, typename Real>
 struct DtInLds { static constexpr bool value = N * N * (int)sizeof(Real) > 400; };
 
 template <int VF, int DIM>
-struct PrimCount { static constexpr int value = (VF == VF_RANOCHA) ? DIM + 4 : DIM + 2; };
+struct PrimCount { static constexpr int value = (VF == VF_RANOCHA) ? DIM + 5 : DIM + 2; };
 
 // node of face node f (other digits, lowest direction first) with digit `pos` in direction dir
 template <int N>
@@ -487,7 +494,7 @@ __device__ __forceinline__ Real cfl_rate(const Real (&u)[DIM + 2], MP me, int64_
   return lam;
 }
 
-// primitive state (rho, v_1..v_d, p, log rho, log p) stored as dim+4 values
+// primitive state from (rho, v_1..v_d, p, log rho, log beta) stored as dim+4 values
 template <int DIM, typename Real>
 __device__ __forceinline__ Prim<Real> unpack_prim(const Real* f) {
   Prim<Real> P;
@@ -497,7 +504,8 @@ __device__ __forceinline__ Prim<Real> unpack_prim(const Real* f) {
   P.v2 = DIM > 2 ? f[DIM > 2 ? 3 : 1] : Real(0);
   P.p = f[DIM + 1];
   P.lr = f[DIM + 2];
-  P.lp = f[DIM + 3];
+  P.b = P.rho * dev_rcp(P.p);
+  P.lb = f[DIM + 3];
   return P;
 }
 
@@ -535,7 +543,8 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
     P[k].v2 = DIM > 2 ? sp[DIM > 2 ? 3 : 0][q] : Real(0);
     P[k].p = sp[DIM + 1][q];
     P[k].lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][q] : Real(0);
-    P[k].lp = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][q] : Real(0);
+    P[k].b = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][q] : Real(0);
+    P[k].lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][q] : Real(0);
   }
 #pragma unroll
   for (int k = 0; k < N; ++k)
@@ -632,7 +641,8 @@ __device__ __forceinline__ void node_fluxes(const Real (*sp)[Pow<N, DIM>::value]
     Pk.v2 = DIM > 2 ? sp[DIM > 2 ? 3 : 0][q] : Real(0);
     Pk.p = sp[DIM + 1][q];
     Pk.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][q] : Real(0);
-    Pk.lp = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][q] : Real(0);
+    Pk.b = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][q] : Real(0);
+    Pk.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][q] : Real(0);
     Real F[NV];
     if (MESH == MESH_CURVED) {
       volume_flux<VF, DIM>(Po, Pk, no[0] + sn[0][q], DIM > 1 ? no[1] + sn[DIM > 1 ? 1 : 0][q] : Real(0),
@@ -675,8 +685,11 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int NM = DIM * DIM + 1;
   __shared__ Real s_prim[EPB][NP][NN];     // primitive variables (and logs)
+  // volume term, summed over directions in order (line layout): reuses the
+  // primitives' LDS, which every lane has read into registers by then
+  static_assert(NV <= NP, "volume sums fit in the primitives' LDS");
+  Real(*s_acc)[NV][NN] = reinterpret_cast<Real(*)[NV][NN]>(&s_prim[0][0][0]);
   __shared__ Real s_face[EPB][NV][NFACE];  // surface fluxes of the element's faces
-  __shared__ Real s_acc[NODEL ? 1 : EPB][NV][NODEL ? 1 : NN];  // volume term, summed over directions in order
   __shared__ int s_nbr[EPB][2 * DIM];      // neighbour across face (2 dir + side), side 1 = +
   __shared__ Real s_dt[(NODEL || DtInLds<N, Real>::value) ? N * N : 1];  // D~ when it stays out of scalar registers
   // node layout, curved: halved contravariant vectors of two directions
@@ -831,8 +844,10 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     if (DIM > 2) s_prim[el][DIM > 2 ? 3 : 0][i] = v2;
     s_prim[el][DIM + 1][i] = p;
     if (NP > DIM + 2) {
+      const Real beta = rho * dev_rcp(p);
       s_prim[el][(NP > DIM + 2) ? DIM + 2 : 0][i] = dev_log(rho);
-      s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][i] = dev_log(p);
+      s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][i] = beta;
+      s_prim[el][(NP > DIM + 2) ? DIM + 4 : 0][i] = dev_log(beta);
     }
     if constexpr (CNODE) {
 #pragma unroll
@@ -870,7 +885,8 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     Po.v2 = sp[3][i];
     Po.p = sp[4][i];
     Po.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][i] : Real(0);
-    Po.lp = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][i] : Real(0);
+    Po.b = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][i] : Real(0);
+    Po.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][i] : Real(0);
     Real no[3] = {Real(0), Real(0), Real(0)};
     Real Ad[NV];
     if constexpr (CNODE) { no[0] = hm[0][0]; no[1] = hm[0][1]; no[2] = hm[0][2]; }
@@ -930,6 +946,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     }
   }
   // fixed summation order over directions: dir 0 writes, then dir 1, dir 2 add
+  if constexpr (!NODEL) __syncthreads();  // every line's primitives are read
 #pragma unroll
   for (int d = 0; d < (NODEL ? 0 : DIM); ++d) {
     if (ldir == d && lactive) {
@@ -1057,7 +1074,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
 // the element ends along each line (rows of R); back to primitive variables
 // with beta = -w_E, v = w_m/beta, s = gamma - (gamma-1)(w_0 + beta|v|^2/2),
 // ln p = (s + gamma ln beta)/(1 - gamma), ln rho = ln beta + ln p.  Written
-// to faceb as (rho, v, p, ln rho, ln p) per face point; launched before each
+// to faceb as (rho, v, p, ln rho, ln beta) per face point; launched before each
 // Gauss stage on the same tiles and descriptors.  The projection is evaluated
 // in FP64 for both precisions: the map back from w cancels digits (ln p from
 // s and ln beta), which FP32 would expose at ~1e-6 relative.
@@ -1135,7 +1152,7 @@ __global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) gauss_project_kernel(
     for (int m = 0; m < DIM; ++m) fb[o + (size_t)(1 + m) * NF] = (Real)vel[m];
     fb[o + (size_t)(DIM + 1) * NF] = (Real)p;
     fb[o + (size_t)(DIM + 2) * NF] = (Real)lr;
-    fb[o + (size_t)(DIM + 3) * NF] = (Real)lp;
+    fb[o + (size_t)(DIM + 3) * NF] = (Real)lb;
   }
 }
 
