@@ -664,12 +664,14 @@ __device__ __forceinline__ void node_fluxes(const Real (*sp)[Pow<N, DIM>::value]
 // Waves per SIMD the register allocation of a tile must allow: the tile's
 // default, except for the FP32 p = 7 affine tile of the line layout, which
 // fits three waves without spilling (measured faster; the curved one would
-// spill).
+// spill), and the FP64 node tiles up to N = 5, whose prologue (two or three
+// face nodes per lane) spills at four waves (three measured 3% faster at
+// p = 4).
 template <int DIM, int N, int MESH, typename Real, int EPB_, int LAY = LAY_LINES>
 struct StageWaves {
-  static constexpr int value = (LAY == LAY_LINES && sizeof(Real) == 4 && N == 8 && MESH == MESH_AFFINE)
-                                   ? 3
-                                   : Tile<DIM, N, EPB_, LAY>::WPE;
+  static constexpr int value = (LAY == LAY_LINES && sizeof(Real) == 4 && N == 8 && MESH == MESH_AFFINE) ? 3
+                               : (LAY == LAY_NODES && sizeof(Real) == 8 && N <= 5)                   ? 3
+                                                                                                     : Tile<DIM, N, EPB_, LAY>::WPE;
 };
 
 template <int DIM, int N, int VF, int MESH, typename Real, int EPB_, int NODES = NODES_LGL, int LAY = LAY_LINES>
