@@ -416,15 +416,18 @@ constexpr int tile_epb(int dim, int N, int np, int rbytes, int variant) {
   if (variant == 2) return 2 * epb0 * per <= kTileLdsCap ? 2 * epb0 : epb0;
   if (variant == 3) {
     // node layout (LDS: primitives, two direction buffers of halved
-    // contravariant vectors, face fluxes): of the tiles of at least 128 and at
-    // most 1024 lanes within the LDS budget, the one that leaves the fewest
-    // lanes idle, the smaller on a tie
+    // contravariant vectors, face fluxes): the smallest tile of at least 128
+    // lanes (and at most 1024, within the LDS budget) that keeps >= 80% of its
+    // lanes busy -- small workgroups pack more of them per CU (measured: p = 5
+    // FP64 one element 7% faster than two); else the one that leaves the
+    // fewest lanes idle
     const int pn = ((np + 2 * dim) * nn + nv * nface) * rbytes + 2 * dim * 4;
     int best = 1;
     long best_num = 0, best_den = 1;
     for (int e = 1; e <= 32 && e * nn <= 1024; ++e) {
       const int lanes = (e * nn + 63) / 64 * 64;
       if ((lanes < 128 && (e + 1) * nn <= 1024) || (e > 1 && e * pn > kTileLdsCap)) continue;
+      if (5 * e * nn >= 4 * lanes) return e;
       if ((long)e * nn * best_den > best_num * (long)lanes) {
         best = e;
         best_num = (long)e * nn;
