@@ -764,15 +764,17 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
                                    : Real(1);
   }
   Real nrm[N][3];
-  Real hm[DIM][3];  // node layout, curved: the node's halved contravariant vectors
+  // node layout, curved: the node's halved contravariant vectors of
+  // directions 0 and 1 (direction 2 is loaded after their sweeps)
+  Real hm[2][DIM];
+  const auto me_node = metric + ((CNODE && tid < EPB * NN && e0 + tid / NN < E)
+                                     ? (size_t)(e0 + tid / NN) * (NM * NN) + (tid - (tid / NN) * NN)
+                                     : 0);
   if constexpr (CNODE) {
-    const int el = tid / NN, i = tid - el * NN;
-    const bool ok = tid < EPB * NN && e0 + el < E;
-    const auto me = metric + (ok ? (size_t)(e0 + el) * (NM * NN) + i : 0);
 #pragma unroll
-    for (int n = 0; n < DIM; ++n)
+    for (int n = 0; n < 2; ++n)
 #pragma unroll
-      for (int m = 0; m < 3; ++m) hm[n][m] = m < DIM ? Real(0.5) * me[(n * DIM + m) * NN] : Real(0);
+      for (int m = 0; m < DIM; ++m) hm[n][m] = Real(0.5) * me_node[(n * DIM + m) * NN];
   }
   if (MESH == MESH_CURVED && !NODEL) {
     const auto me = metric + (size_t)(lactive ? e0 + lel : 0) * (NM * NN);
@@ -894,27 +896,29 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     Po.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][i] : Real(0);
     Real no[3] = {Real(0), Real(0), Real(0)};
     Real Ad[NV];
-    if constexpr (CNODE) { no[0] = hm[0][0]; no[1] = hm[0][1]; no[2] = hm[0][2]; }
-    // the two direction buffers (never read on affine meshes)
+    // the two direction buffers (never read on affine meshes); the node's own
+    // vectors are read back from them rather than held in registers
     const Real(*sn0)[NN] = reinterpret_cast<const Real(*)[NN]>(&s_nrm[CNODE ? el : 0][0][0][0]);
     const Real(*sn1)[NN] = reinterpret_cast<const Real(*)[NN]>(&s_nrm[CNODE ? el : 0][1][0][0]);
+    if constexpr (CNODE) { no[0] = sn0[0][i]; no[1] = sn0[1][i]; no[2] = sn0[2][i]; }
     node_fluxes<0, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, ix, s_dt, P.scale[0],
                                             a.ops.inv_gm1, Ad);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Sn[v] = Ad[v];
-    if constexpr (CNODE) { no[0] = hm[1][0]; no[1] = hm[1][1]; no[2] = hm[1][2]; }
+    if constexpr (CNODE) { no[0] = sn1[0][i]; no[1] = sn1[1][i]; no[2] = sn1[2][i]; }
     node_fluxes<1, DIM, N, VF, MESH, Real>(sp, sn1, Po, no, i, iy, s_dt, P.scale[1],
                                             a.ops.inv_gm1, Ad);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Sn[v] += Ad[v];
     if constexpr (CNODE) {
       // direction 2 replaces direction 0 in the first buffer
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) no[m] = Real(0.5) * me_node[(2 * DIM + m) * NN];
       __syncthreads();
       if (tid < EPB * NN && e0 + tid / NN < E)
 #pragma unroll
-        for (int m = 0; m < DIM; ++m) s_nrm[el][0][m][i] = hm[2][m];
+        for (int m = 0; m < DIM; ++m) s_nrm[el][0][m][i] = no[m];
       __syncthreads();
-      no[0] = hm[2][0]; no[1] = hm[2][1]; no[2] = hm[2][2];
     }
     node_fluxes<2, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, iz, s_dt, P.scale[2],
                                             a.ops.inv_gm1, Ad);
