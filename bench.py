@@ -256,6 +256,7 @@ def precision_sweep(args, esdg, inputs, torch, dev):
             res[prec + "_u"] = g.get_state()
             g.set_state(u0)
             res[prec + "_ms"] = time_steps(g, args.sweep_steps, 10, args.sweep_cfl, torch)
+            res[prec + "_tile"] = g.tile_variant()  # (variant, elements per workgroup)
             nodes = g.n_dof
             g.close()
 
@@ -275,6 +276,8 @@ def precision_sweep(args, esdg, inputs, torch, dev):
             "rhs_rel_l2": r2, "rhs_rel_linf": ri,
             "state_rel_l2_after_steps": s2, "state_rel_linf_after_steps": si,
             "steps": args.sweep_steps, "dt": float("%.4e" % dt),
+            # tile variant (3 = one lane per node, 0-2 = one lane per line) and elements per workgroup
+            "tile_variant_epb": {"fp64": list(res["fp64_tile"]), "fp32": list(res["fp32_tile"])},
         }
         del res
     out["workload"] = ("density wave rho = 1 + 0.98 sin(pi(x+y+z)), v = (0.1,0.2,0.3), p = 20 on the warped %d^3 "
