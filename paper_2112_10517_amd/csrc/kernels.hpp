@@ -618,25 +618,28 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
 // LDS, evaluates f(u_i, u_k) (bitwise the pair's flux, see volume_flux) and
 // accumulates D~_ik F in increasing k, the order in which the line layout's
 // pair loop reaches node i.  sn holds the halved contravariant vectors of
-// direction DIR of the element ([DIM][NN]); no is the node's own.
+// direction DIR of the element ([DIM][NN]); no is the node's own.  s_dts is
+// D~ without its diagonal, row id holding D~_ik for k = j + (j >= id),
+// j = 0..N-2: the sweep's j-th coefficient is one load at a lane-constant
+// base, and the partner's node index one select and one add.
 template <int DIR, int DIM, int N, int VF, int MESH, typename Real>
 __device__ __forceinline__ void node_fluxes(const Real (*sp)[Pow<N, DIM>::value], const Real (*sn)[Pow<N, DIM>::value],
                                             const Prim<Real>& Po, const Real (&no)[3], int i, int id,
-                                            const Real* s_dt, Real scale, Real inv_gm1, Real (&A)[DIM + 2]) {
+                                            const Real* s_dts, Real scale, Real inv_gm1, Real (&A)[DIM + 2]) {
 #pragma clang fp contract(off)  // as in line_fluxes
   constexpr int NV = DIM + 2;
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int stride = Pow<N, DIR>::value;
-  const int base = i - id * stride;
-  const Real* drow = s_dt + id * N;
+  const int q_lo = i - id * stride;  // partner k = j for j < id
+  const int q_hi = q_lo + stride;    // partner k = j + 1 from j = id on
+  const Real* drow = s_dts + id * (N - 1);
 #pragma unroll
   for (int v = 0; v < NV; ++v) A[v] = Real(0);
   // a rolled loop: unrolled, the partners' loads are hoisted ahead of the
   // fluxes and the registers spill
 #pragma unroll 1
   for (int j = 0; j < N - 1; ++j) {
-    const int k = j + (j >= id ? 1 : 0);
-    const int q = base + k * stride;
+    const int q = (j >= id ? q_hi : q_lo) + j * stride;
     Prim<Real> Pk;
     Pk.rho = sp[0][q];
     Pk.v0 = sp[1][q];
@@ -654,7 +657,7 @@ __device__ __forceinline__ void node_fluxes(const Real (*sp)[Pow<N, DIM>::value]
       volume_flux<VF, DIM>(Po, Pk, DIR == 0 ? Real(1) : Real(0), DIR == 1 ? Real(1) : Real(0),
                            DIR == 2 ? Real(1) : Real(0), inv_gm1, F);
     }
-    const Real dik = drow[k];
+    const Real dik = drow[j];
 #pragma unroll
     for (int v = 0; v < NV; ++v) A[v] = mad(dik, F[v], A[v]);
   }
@@ -696,7 +699,8 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   Real(*s_acc)[NV][NN] = reinterpret_cast<Real(*)[NV][NN]>(&s_prim[0][0][0]);
   __shared__ Real s_face[EPB][NV][NFACE];  // surface fluxes of the element's faces
   __shared__ int s_nbr[EPB][2 * DIM];      // neighbour across face (2 dir + side), side 1 = +
-  __shared__ Real s_dt[(NODEL || DtInLds<N, Real>::value) ? N * N : 1];  // D~ when it stays out of scalar registers
+  __shared__ Real s_dt[DtInLds<N, Real>::value ? N * N : 1];  // D~ when it stays out of scalar registers
+  __shared__ Real s_dts[NODEL ? N * (N - 1) : 1];  // node layout: D~ rows without the diagonal
   // node layout, curved: halved contravariant vectors of two directions
   // (directions 0 and 1, then 2 in the first buffer)
   __shared__ Real s_nrm[CNODE ? EPB : 1][2][DIM][CNODE ? NN : 1];
@@ -783,8 +787,13 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
 #pragma unroll
       for (int m = 0; m < 3; ++m) nrm[k][m] = m < DIM ? Real(0.5) * me[(ldir * DIM + m) * NN + lbase + k * stride] : Real(0);
   }
-  if (NODEL || DtInLds<N, Real>::value)
+  if (DtInLds<N, Real>::value)
     for (int t = tid; t < N * N; t += THREADS) s_dt[t] = a.ops.Dt[t];
+  if (NODEL)
+    for (int t = tid; t < N * (N - 1); t += THREADS) {
+      const int r = t / (N - 1), j = t - r * (N - 1);
+      s_dts[t] = a.ops.Dt[r * N + j + (j >= r ? 1 : 0)];
+    }
   __syncthreads();  // s_nbr, s_dt
   Real tL[FPT][NV], tR[FPT][NV], tn[FPT][3];
   constexpr int NPF = DIM + 4;
@@ -901,12 +910,12 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     const Real(*sn0)[NN] = reinterpret_cast<const Real(*)[NN]>(&s_nrm[CNODE ? el : 0][0][0][0]);
     const Real(*sn1)[NN] = reinterpret_cast<const Real(*)[NN]>(&s_nrm[CNODE ? el : 0][1][0][0]);
     if constexpr (CNODE) { no[0] = sn0[0][i]; no[1] = sn0[1][i]; no[2] = sn0[2][i]; }
-    node_fluxes<0, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, ix, s_dt, P.scale[0],
+    node_fluxes<0, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, ix, s_dts, P.scale[0],
                                             a.ops.inv_gm1, Ad);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Sn[v] = Ad[v];
     if constexpr (CNODE) { no[0] = sn1[0][i]; no[1] = sn1[1][i]; no[2] = sn1[2][i]; }
-    node_fluxes<1, DIM, N, VF, MESH, Real>(sp, sn1, Po, no, i, iy, s_dt, P.scale[1],
+    node_fluxes<1, DIM, N, VF, MESH, Real>(sp, sn1, Po, no, i, iy, s_dts, P.scale[1],
                                             a.ops.inv_gm1, Ad);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Sn[v] += Ad[v];
@@ -920,7 +929,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
         for (int m = 0; m < DIM; ++m) s_nrm[el][0][m][i] = no[m];
       __syncthreads();
     }
-    node_fluxes<2, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, iz, s_dt, P.scale[2],
+    node_fluxes<2, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, iz, s_dts, P.scale[2],
                                             a.ops.inv_gm1, Ad);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Sn[v] += Ad[v];
