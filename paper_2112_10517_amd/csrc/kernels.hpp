@@ -440,11 +440,14 @@ constexpr int tile_epb(int dim, int N, int np, int rbytes, int variant) {
 }
 
 // D~ is a scalar operand of the pair loop (N^2 values in scalar registers)
-// except for N = 8 in FP64: its 128 scalar registers exceed a wave's, and
+// except for N = 8: in FP64 its 128 scalar registers exceed a wave's, and
 // the code generated at -O2/-O3 for the spilled operands gave wrong volume
-// sums (correct at -O1 and with D~ in LDS), so that tile reads D~ from LDS.
+// sums (correct at -O1 and with D~ in LDS); in FP32 its 64 registers left
+// the line tiles 15-30 scalar registers short, and one of them gave wrong
+// sums after an unrelated change.  N = 8 tiles read D~ from LDS (no scalar
+// spills).
 template <int N, typename Real>
-struct DtInLds { static constexpr bool value = N * N * (int)sizeof(Real) > 400; };
+struct DtInLds { static constexpr bool value = N >= 8; };
 
 template <int VF, int DIM>
 struct PrimCount { static constexpr int value = (VF == VF_RANOCHA) ? DIM + 5 : DIM + 2; };
@@ -668,16 +671,12 @@ __device__ __forceinline__ void node_fluxes(const Real (*sp)[Pow<N, DIM>::value]
 }
 
 // Waves per SIMD the register allocation of a tile must allow: the tile's
-// default, except for the FP32 p = 7 affine tile of the line layout, which
-// fits three waves without spilling (measured faster; the curved one would
-// spill), and the FP64 node tiles up to N = 5, whose prologue (two or three
-// face nodes per lane) spills at four waves (three measured 3% faster at
-// p = 4).
+// default, except for the FP64 node tiles up to N = 5, whose prologue (two or
+// three face nodes per lane) spills at four waves (three measured 3% faster
+// at p = 4).
 template <int DIM, int N, int MESH, typename Real, int EPB_, int LAY = LAY_LINES>
 struct StageWaves {
-  static constexpr int value = (LAY == LAY_LINES && sizeof(Real) == 4 && N == 8 && MESH == MESH_AFFINE) ? 3
-                               : (LAY == LAY_NODES && sizeof(Real) == 8 && N <= 5)                   ? 3
-                                                                                                     : Tile<DIM, N, EPB_, LAY>::WPE;
+  static constexpr int value = (LAY == LAY_NODES && sizeof(Real) == 8 && N <= 5) ? 3 : Tile<DIM, N, EPB_, LAY>::WPE;
 };
 
 template <int DIM, int N, int VF, int MESH, typename Real, int EPB_, int NODES = NODES_LGL, int LAY = LAY_LINES>
