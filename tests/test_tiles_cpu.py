@@ -1,0 +1,61 @@
+"""Workgroup shapes of the stage kernel (host logic, no GPU): every tile
+variant of every 3D degree and precision fits the hardware -- at most 1024
+lanes in whole 64-lane waves, one node per lane in the node layout, the
+LDS the kernel declares within a CU's 160 KiB and, for the variants that
+are not the fallback default, within the 80 KiB budget that lets two
+workgroups share a CU."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CAP = 80 * 1024
+
+
+@pytest.fixture(scope="module")
+def shapes(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not found")
+    exe = str(tmp_path_factory.mktemp("tiles") / "tile_shapes")
+    cmd = [HIPCC, "-std=c++17", "-O1", "-x", "hip", "--cuda-host-only", "--offload-arch=gfx950",
+           "-I", os.path.join(ROOT, "paper_2112_10517_amd", "csrc"), "-I", os.path.join(ROOT, "include"),
+           os.path.join(ROOT, "tests", "c", "tile_shapes.hip"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, out.stderr
+    rows = []
+    for line in out.stdout.splitlines():
+        f = line.split()
+        rows.append({f[i]: (f[i + 1] if f[i] == "prec" else int(f[i + 1])) for i in range(0, len(f), 2)})
+    assert len(rows) == 7 * 4 * 4
+    return rows
+
+
+def test_lanes_and_waves(shapes):
+    for s in shapes:
+        assert 64 <= s["threads"] <= 1024 and s["threads"] % 64 == 0, s
+        assert s["epb"] >= 1, s
+        assert s["npt"] * s["threads"] >= s["epb"] * s["nn"], s  # every node has a lane
+        assert 1 <= s["waves"] <= 8, s
+
+
+def test_node_layout_one_node_per_lane(shapes):
+    for s in (s for s in shapes if s["variant"] == 3):
+        assert s["npt"] == 1 and s["threads"] >= s["epb"] * s["nn"], s
+        assert s["threads"] - s["epb"] * s["nn"] < 64, s  # idle lanes only in the last wave
+        # at least 128 lanes unless a single element already has fewer nodes... with 80% of them busy
+        if s["threads"] >= 128 and s["nn"] >= 27:
+            assert 5 * s["epb"] * s["nn"] >= 4 * s["threads"] or s["epb"] == 1, s
+
+
+def test_lds_within_budget(shapes):
+    for s in shapes:
+        assert s["lds"] <= 160 * 1024, s
+        if s["variant"] in (1, 2) and s["epb"] != s["epb0"]:
+            assert s["lds"] <= CAP + 4096, s  # the variant's own LDS estimate is within the budget
+        if s["variant"] == 3 and s["epb"] > 1:
+            assert s["lds"] <= CAP + 4096, s
