@@ -270,6 +270,32 @@ def test_isentropic_vortex_parity(orc, esdg, dim, warp, vol):
         assert abs(rate) < 1e-13 * escale and abs(rate - m.entropy_rate(u, du)) < 1e-13 * escale
 
 
+@pytest.mark.parametrize("p,n,warp", [(5, (2, 3, 2), 0.1), (7, (2, 2, 2), 0.0), (7, (2, 1, 2), 0.1)])
+def test_entropy_conservation_node_layout(orc, esdg, p, n, warp):
+    """Entropy-conservative volume and surface fluxes in the node layout
+    (tile variant 3, one lane per node; every pair evaluated from both of its
+    nodes): the right-hand side matches the oracle and dS/dt = 0 to round-off
+    on the scale sum J W |w . du| -- the pair fluxes of the two ends must
+    cancel as exactly as the line layout's single evaluation."""
+    m, g = make_pair(orc, esdg, 3, p, n, warp=warp, vol="ranocha", surf="ranocha")
+    u = noisy(inputs.random_fourier(m.coords(), 8), 6)
+    g.set_state(u)
+    v_before = g.tile_variant()[0]
+    try:
+        g.set_tile_variant(3)
+        assert rhs_parity(g.rhs(), m, u) <= 1.0
+        du = m.rhs(u)
+        w = np.stack([orc.entropy_vars(3, 1.4, u[e, :, i]) for e in range(m.n_elem) for i in range(m.nodes)])
+        w = w.reshape(m.n_elem, m.nodes, 5).transpose(0, 2, 1)
+        _, J = m.metrics()
+        escale = np.sum((J * m.weights()[None, :])[:, None, :] * np.abs(w * du))
+        rate = g.entropy_rate()
+        print("p=%d warp=%.1f node layout: entropy rate %.3e (relative %.3e)" % (p, warp, rate, abs(rate) / escale))
+        assert abs(rate) < 1e-13 * escale and abs(rate - m.entropy_rate(u, du)) < 1e-13 * escale
+    finally:
+        g.set_tile_variant(v_before)
+
+
 @pytest.mark.parametrize("prec,cfl", [("fp64", False), ("fp32", False), ("fp64", True), ("fp32", True)])
 def test_checkpoint_resume_bitwise(esdg, prec, cfl):
     # the state and time read through the ABI (FP64, canonical layout) are the
