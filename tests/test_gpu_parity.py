@@ -176,10 +176,12 @@ def test_llf_entropy_dissipation_and_cfl_steps(orc, esdg):
     assert rel_err(g.get_state(), uo) < TOL
 
 
-def test_cfl_steps_across_calls(orc, esdg):
+@pytest.mark.parametrize("p", [3, 5])
+def test_cfl_steps_across_calls(orc, esdg, p):
     # the CFL step of a step's start state is carried over between calls and
     # recomputed after set_state; both paths must equal the oracle's CFL steps
-    m, g = make_pair(orc, esdg, 3, 3, (3, 4, 2), warp=0.1, vol="ranocha", surf="llf")
+    # (p = 3: line layout; p = 5: node layout, by default)
+    m, g = make_pair(orc, esdg, 3, p, (3, 4, 2), warp=0.1, vol="ranocha", surf="llf")
     u = noisy(inputs.random_fourier(m.coords(), 12), 13)
     g.set_state(u)
     t = g.step(dt=0.0, nsteps=2, cfl=0.4, t=0.0)
