@@ -31,6 +31,12 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 FP64_VALU_PEAK_TF = 78.6    # MI355X FP64 vector
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2112_10517_amd", "csrc", "kernels.hpp")
+# rocprofv3 records (HBM traffic, FP64 VALU instruction counts) of the stage
+# kernel, by (dim, p, elements per direction, volume flux) of the bench line
+# they were taken on; used only while the kernel source is unchanged
+PROFILE_OF = {(3, 3, 16, "ranocha"): "stage_kernel_3d_p3_warped16_fp64.md",
+              (3, 7, 32, "ranocha"): "stage_kernel_3d_p7_warped32_fp64.md"}
 
 
 def algorithmic_stage_bytes(dim: int, N: int, curved: bool, real_bytes: int = 8) -> float:
@@ -609,6 +615,7 @@ def main(argv=None):
     copy_gbs = 5 * 2 * cb / (c0.elapsed_time(c1) * 1e-3) / 1e9
     del src, dst
 
+    profile = PROFILE_OF.get((dim, p, n, args.flux))
     line = {
         "metric": "PID (ns per DOF per RHS) FP64 plain vs FP32 batched; served jobs/s + p99 latency",
         "value": round(pid_ns, 6),
@@ -647,17 +654,13 @@ def main(argv=None):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-            "traffic": recorded_traffic(os.path.join(ROOT, "paper_2112_10517_amd", "csrc", "kernels.hpp"),
-                                        os.path.join(ROOT, "profiles", "stage_kernel_3d_p3_warped16_fp64.md"))
-            if (dim, p, n, args.flux) == (3, 3, 16, "ranocha") else None,
+            "traffic": recorded_traffic(KERNEL_SOURCE, os.path.join(ROOT, "profiles", profile)) if profile else None,
             "algorithmic_bytes_per_node": bytes_per_node,
             "bytes_per_launch": traffic_bytes,
             "avg_launch_us": round(vol_avg_s * 1e6, 3),
             "copy_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved_gbs / copy_gbs, 4),
-            "valu": recorded_valu(os.path.join(ROOT, "paper_2112_10517_amd", "csrc", "kernels.hpp"),
-                                  os.path.join(ROOT, "profiles", "stage_kernel_3d_p3_warped16_fp64.md"), vol_avg_s)
-            if (dim, p, n, args.flux) == (3, 3, 16, "ranocha") else None,
+            "valu": recorded_valu(KERNEL_SOURCE, os.path.join(ROOT, "profiles", profile), vol_avg_s) if profile else None,
         },
         "cpu_baseline": None,
     }
