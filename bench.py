@@ -234,12 +234,35 @@ def random_fourier_device(x, seed, torch, gamma=1.4):
     return u
 
 
+def entropy_scale(esdg, g, u, du, p, gamma=1.4):
+    """sum_i J_i W_i |w(u_i) . du_i| over a 3D mesh (host FP64): the size of
+    the terms whose sum is dS/dt, the scale an entropy-rate residual is
+    measured on.  w: the entropy variables of U = -rho s/(gamma - 1),
+    s = ln p - gamma ln rho; J: the library's (esdg_get_inv_jacobian); W: the
+    tensor-product LGL weights.  u, du: [elem][var][node] host arrays."""
+    import numpy as np
+    _, w1, _, _ = esdg.operators(p)
+    N = p + 1
+    idx = np.arange(N ** 3)
+    W = w1[idx % N] * w1[(idx // N) % N] * w1[idx // (N * N)]
+    rho = u[:, 0]
+    rv2 = (u[:, 1] ** 2 + u[:, 2] ** 2 + u[:, 3] ** 2) / rho
+    pr = (gamma - 1.0) * (u[:, 4] - 0.5 * rv2)
+    s = np.log(pr) - gamma * np.log(rho)
+    wdu = ((gamma - s) / (gamma - 1.0) - 0.5 * rv2 / pr) * du[:, 0]
+    wdu += (u[:, 1] * du[:, 1] + u[:, 2] * du[:, 2] + u[:, 3] * du[:, 3] - rho * du[:, 4]) / pr
+    return float(np.sum(W[None, :] / g.inv_jacobian() * np.abs(wdu)))
+
+
 def precision_sweep(args, esdg, inputs, torch, dev):
     """Density wave on the warped 32^3 box at p = 4 and 7, Ranocha + LLF: FP32
     bulk against FP64.  PID of both (CFL-mode RK4 steps); relative L2 and Linf
     differences of the FP32 right-hand side and of the FP32 state after a
     fixed number of equal fixed-dt steps, against the FP64 ones (per
-    conserved variable; the FP64 path matches the oracle to 1e-12).  The
+    conserved variable; the FP64 path matches the oracle to 1e-12); the
+    entropy rate (FP64 reduction) of the initial state with the LLF surface
+    flux and, as the discrete residual, with the entropy-conservative one,
+    relative to sum J W |w . du|.  The
     density wave's momentum and energy right-hand sides are O(|v|) remainders
     of an O(p) pressure-flux divergence that cancels, so their FP32 relative
     error is that of the cancelled terms, not of the result."""
@@ -252,9 +275,11 @@ def precision_sweep(args, esdg, inputs, torch, dev):
         for prec in ("fp64", "fp32"):
             g = esdg.Problem(3, p, (n, n, n), warp=0.1, volume_flux="ranocha", surface_flux="llf", precision=prec)
             if u0 is None:
-                u0 = torch.from_numpy(inputs.density_wave(g.coords())).to(dev)
+                u0_host = inputs.density_wave(g.coords())
+                u0 = torch.from_numpy(u0_host).to(dev)
             g.set_state(u0)
             res[prec + "_rhs"] = g.rhs()
+            res[prec + "_dsdt_llf"] = g.entropy_rate()
             if dt is None:
                 dt = 0.5 * g.max_dt(args.sweep_cfl)
             g.step(dt=dt, nsteps=args.sweep_steps)
@@ -265,6 +290,15 @@ def precision_sweep(args, esdg, inputs, torch, dev):
             res[prec + "_tile"] = g.tile_variant()  # (variant, elements per workgroup)
             nodes = g.n_dof
             g.close()
+            # the discrete entropy-rate residual: the same state with the
+            # entropy-conservative flux on the faces as well, where dS/dt is
+            # zero up to round-off (FP64 reduction in both precisions)
+            ge = esdg.Problem(3, p, (n, n, n), warp=0.1, volume_flux="ranocha", surface_flux="ranocha",
+                              precision=prec)
+            ge.set_state(u0)
+            res[prec + "_dsdt_ec"] = ge.entropy_rate()
+            res[prec + "_dsdt_scale"] = entropy_scale(esdg, ge, u0_host, ge.rhs(), p)
+            ge.close()
 
         def diff(a, b):
             # per conserved variable (rho, rho v1..v3, rho e)
@@ -284,6 +318,19 @@ def precision_sweep(args, esdg, inputs, torch, dev):
             "steps": args.sweep_steps, "dt": float("%.4e" % dt),
             # tile variant (3 = one lane per node, 0-2 = one lane per line) and elements per workgroup
             "tile_variant_epb": {"fp64": list(res["fp64_tile"]), "fp32": list(res["fp32_tile"])},
+            # dS/dt of the initial state with the LLF surface flux and, as the
+            # discrete residual, with the entropy-conservative one, and both
+            # relative to the scale sum J W |w . du| of the latter (the
+            # continuous initial interpolant has no jumps at the faces, so the
+            # LLF rate is a residual too)
+            "entropy_rate": {prec: {"llf": float("%.4e" % res[prec + "_dsdt_llf"]),
+                                    "ec_residual": float("%.4e" % res[prec + "_dsdt_ec"]),
+                                    "scale": float("%.4e" % res[prec + "_dsdt_scale"]),
+                                    "llf_rel": float("%.3e" % (abs(res[prec + "_dsdt_llf"]) /
+                                                               res[prec + "_dsdt_scale"])),
+                                    "ec_residual_rel": float("%.3e" % (abs(res[prec + "_dsdt_ec"]) /
+                                                                       res[prec + "_dsdt_scale"]))}
+                             for prec in ("fp64", "fp32")},
         }
         del res
     out["workload"] = ("density wave rho = 1 + 0.98 sin(pi(x+y+z)), v = (0.1,0.2,0.3), p = 20 on the warped %d^3 "

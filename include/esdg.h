@@ -122,6 +122,17 @@ esdg_status esdg_set_stream(esdg_problem *prob, void *stream);
 /* Node coordinates [elem][dim][node] into a host buffer (FP64). */
 esdg_status esdg_get_coords(const esdg_problem *prob, double *x);
 
+/* 1/J per node, [elem][node] (node x-fastest), into a caller-owned host
+ * buffer of n_elem * nodes_per_elem doubles: the values the kernels scale
+ * the right-hand side with, J = det(dx/dxi) from the collocation
+ * derivatives of the node coordinates (Sec. 2.3, metric terms); in FP32 mode
+ * the FP32 values the kernels read, widened.  Affine meshes: the box's
+ * constant 1/J.  For host quadratures sum_i J_i W_i f_i (W the LGL weights
+ * of esdg_operators, tensor products per element).  Synchronous (a strided
+ * device-to-host copy on the problem's stream); ESDG_EINVAL for a NULL
+ * argument, ESDG_EDEVICE if the copy fails. */
+esdg_status esdg_get_inv_jacobian(esdg_problem *prob, double *inv_j);
+
 /* Set / read the conserved state u[elem][var][node] (FP64, host or device
  * memory as `where` says; device pointers must be on the handle's device). */
 esdg_status esdg_set_state(esdg_problem *prob, const double *u, int32_t where);

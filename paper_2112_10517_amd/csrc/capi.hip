@@ -508,6 +508,30 @@ esdg_status esdg_get_coords(const esdg_problem* P, double* x) {
   return ESDG_OK;
 }
 
+esdg_status esdg_get_inv_jacobian(esdg_problem* P, double* inv_j) {
+  ESDG_TRY(check_handle(P, false));
+  if (!inv_j) return fail(P, ESDG_EINVAL, "NULL argument");
+  const size_t count = (size_t)P->E * P->nn;
+  if (P->mesh != MESH_CURVED) {
+    for (size_t i = 0; i < count; ++i) inv_j[i] = 1.0 / P->geo.J_affine;
+    return ESDG_OK;
+  }
+  // the 1/J row of every element inside the device metric array
+  // [E][dim*dim + 1][nn]: one strided copy of E rows of nn values
+  const size_t row = (size_t)P->nn * P->rsize, pitch = (size_t)(P->dim * P->dim + 1) * row;
+  const char* src = (const char*)P->METRIC + (size_t)P->dim * P->dim * row;
+  if (P->rsize == sizeof(double)) {
+    ESDG_HIP(&P->err, hipMemcpy2DAsync(inv_j, row, src, pitch, row, (size_t)P->E, hipMemcpyDeviceToHost, P->stream));
+    ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
+  } else {
+    std::vector<float> f(count);
+    ESDG_HIP(&P->err, hipMemcpy2DAsync(f.data(), row, src, pitch, row, (size_t)P->E, hipMemcpyDeviceToHost, P->stream));
+    ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
+    for (size_t i = 0; i < count; ++i) inv_j[i] = f[i];
+  }
+  return ESDG_OK;
+}
+
 esdg_status esdg_set_state(esdg_problem* P, const double* u, int32_t where) {
   ESDG_TRY(check_handle(P, false));
   if (!u) return fail(P, ESDG_EINVAL, "NULL state");

@@ -71,6 +71,7 @@ SIGNATURES = {
     "esdg_sizes": (_st, [_vp, _pi64, _pi32, _pi32]),
     "esdg_set_stream": (_st, [_vp, _vp]),
     "esdg_get_coords": (_st, [_vp, _dp]),
+    "esdg_get_inv_jacobian": (_st, [_vp, _dp]),
     "esdg_set_state": (_st, [_vp, _vp, _i32]),
     "esdg_get_state": (_st, [_vp, _vp, _i32]),
     "esdg_rhs": (_st, [_vp, _vp, _i32]),
@@ -289,6 +290,12 @@ class Problem:
     def coords(self) -> np.ndarray:
         x = np.zeros((self.n_elem, self.dim, self.nodes))
         self._call(self._lib.esdg_get_coords, x.ctypes.data_as(C.POINTER(C.c_double)))
+        return x
+
+    def inv_jacobian(self) -> np.ndarray:
+        """1/J per node [elem][node] as the kernels use it (host FP64 array)."""
+        x = np.zeros((self.n_elem, self.nodes))
+        self._call(self._lib.esdg_get_inv_jacobian, x.ctypes.data_as(C.POINTER(C.c_double)))
         return x
 
     def set_state(self, u):

@@ -76,3 +76,39 @@ def test_bench_profiles_hold_both_records(key):
 def test_more_than_one_gpu_is_refused(capsys):
     assert bench.main(["--gpus", "2"]) == 2
     assert "one GPU" in capsys.readouterr().err
+
+
+def test_entropy_scale_against_oracle_entropy_variables(orc):
+    """bench.entropy_scale = sum_i J_i W_i |w(u_i) . du_i| with the oracle's
+    entropy variables and LGL weights (a stand-in for the problem supplies
+    1/J; the library's weights come from esdg_operators, a host call)."""
+    import numpy as np
+    from paper_2112_10517_amd import esdg
+    if not os.path.exists(esdg.LIB_PATH):
+        pytest.skip("HIP library not built")
+    p, E = 2, 3
+    N = p + 1
+    nn = N ** 3
+    rng = np.random.default_rng(7)
+    rho = rng.uniform(0.5, 2.0, (E, nn))
+    v = rng.uniform(-0.5, 0.5, (E, 3, nn))
+    pr = rng.uniform(0.5, 2.0, (E, nn))
+    u = np.empty((E, 5, nn))
+    u[:, 0] = rho
+    u[:, 1:4] = rho[:, None] * v
+    u[:, 4] = pr / 0.4 + 0.5 * rho * (v ** 2).sum(axis=1)
+    du = rng.standard_normal((E, 5, nn))
+    inv_j = rng.uniform(0.5, 4.0, (E, nn))
+
+    class Stand:
+        def inv_jacobian(self):
+            return inv_j
+
+    m = orc.Mesh(3, p, (E, 1, 1))
+    W = m.weights()
+    expect = 0.0
+    for e in range(E):
+        for i in range(nn):
+            w = orc.entropy_vars(3, 1.4, u[e, :, i])
+            expect += W[i] / inv_j[e, i] * abs(float(np.dot(w, du[e, :, i])))
+    assert bench.entropy_scale(esdg, Stand(), u, du, p) == pytest.approx(expect, rel=1e-12)

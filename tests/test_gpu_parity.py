@@ -321,3 +321,26 @@ def test_checkpoint_resume_bitwise(esdg, prec, cfl):
     c.step(dt=dt, nsteps=5, cfl=0.5)
     assert c.get_time() == t10
     assert np.array_equal(c.get_state(), u10)
+
+
+@pytest.mark.parametrize("dim,p,n,warp,prec", [(3, 3, (2, 3, 2), 0.1, "fp64"), (3, 7, (2, 1, 2), 0.1, "fp64"),
+                                               (3, 4, (3, 2, 2), 0.1, "fp32"), (2, 5, (3, 4), 0.1, "fp64"),
+                                               (3, 3, (2, 3, 4), 0.0, "fp64")])
+def test_inv_jacobian(orc, esdg, dim, p, n, warp, prec):
+    """esdg_get_inv_jacobian returns the 1/J the kernels use: against the
+    oracle's independent geometry (own LGL construction and metric
+    evaluation, R1 and R10); FP32 mode returns the FP32-rounded values; an
+    affine box the constant 1 / prod(h/2)."""
+    m = orc.Mesh(dim, p, n, warp=warp)
+    g = esdg.Problem(dim, p, n, warp=warp, precision=prec)
+    try:
+        inv_j = g.inv_jacobian()
+        _, J = m.metrics()
+        assert inv_j.shape == J.shape
+        tol = 1e-12 if prec == "fp64" else 2.0 ** -23
+        np.testing.assert_allclose(inv_j * J, 1.0, rtol=0, atol=tol)
+        if warp == 0.0:
+            h = [2.0 / k for k in n]
+            assert np.all(inv_j == 1.0 / np.prod([0.5 * x for x in h]))
+    finally:
+        g.close()
