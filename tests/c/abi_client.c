@@ -123,6 +123,27 @@ static void gpu_checks(void) {
   CHECK(esdg_get_state(g, u, ESDG_HOST) == ESDG_ESTATE, "state read before esdg_set_state");
   OK(esdg_get_coords(g, x));
 
+  /* 1/J: positive, and sum_i W_i J_i over the warped mesh is the box volume 8
+   * to round-off: the warp adds one scalar phi to every coordinate, so the
+   * collocation Jacobian is (h/2)^3 (1 + sum_k D_k phi), and by the SBP
+   * property the weighted sum of D_k phi over an element is a difference of
+   * face values, which cancels over the periodic mesh */
+  {
+    double ox[4], ow[4], oD[16], oDt[16], vol = 0.0;
+    double *inv_j = (double *)malloc(sizeof(double) * (size_t)(E * nn));
+    int i;
+    CHECK(esdg_get_inv_jacobian(g, (double *)0) == ESDG_EINVAL, "NULL 1/J buffer accepted");
+    OK(esdg_get_inv_jacobian(g, inv_j));
+    OK(esdg_operators(3, ox, ow, oD, oDt));
+    for (k = 0; k < E; ++k)
+      for (i = 0; i < nn; ++i) {
+        CHECK(inv_j[k * nn + i] > 0.0, "1/J <= 0 at element %lld node %d", (long long)k, i);
+        vol += ow[i % 4] * ow[(i / 4) % 4] * ow[i / 16] / inv_j[k * nn + i];
+      }
+    CHECK(fabs(vol - 8.0) < 1e-11, "sum W J = %.15f, box volume 8", vol);
+    free(inv_j);
+  }
+
   /* free stream on the warped mesh */
   for (k = 0; k < E; ++k)
     for (v = 0; v < nv; ++v) {

@@ -330,7 +330,12 @@ def test_inv_jacobian(orc, esdg, dim, p, n, warp, prec):
     """esdg_get_inv_jacobian returns the 1/J the kernels use: against the
     oracle's independent geometry (own LGL construction and metric
     evaluation, R1 and R10); FP32 mode returns the FP32-rounded values; an
-    affine box the constant 1 / prod(h/2)."""
+    affine box the constant 1 / prod(h/2).  Independently of the oracle,
+    sum_i W_i J_i is the box volume 2^dim to round-off: the warp adds one
+    scalar phi to every coordinate, so the collocation Jacobian is
+    prod(h/2) (1 + sum_k D_k phi), and by the SBP property the weighted sum of
+    D_k phi over an element is a difference of face values, which cancels
+    over the periodic mesh."""
     m = orc.Mesh(dim, p, n, warp=warp)
     g = esdg.Problem(dim, p, n, warp=warp, precision=prec)
     try:
@@ -339,6 +344,8 @@ def test_inv_jacobian(orc, esdg, dim, p, n, warp, prec):
         assert inv_j.shape == J.shape
         tol = 1e-12 if prec == "fp64" else 2.0 ** -23
         np.testing.assert_allclose(inv_j * J, 1.0, rtol=0, atol=tol)
+        vol = np.sum(m.weights()[None, :] / inv_j)
+        assert abs(vol - 2.0 ** dim) < (1e-12 if prec == "fp64" else 1e-6) * 2.0 ** dim, vol
         if warp == 0.0:
             h = [2.0 / k for k in n]
             assert np.all(inv_j == 1.0 / np.prod([0.5 * x for x in h]))
