@@ -3,7 +3,9 @@
 * affine boxes: Ja^n = prod_{j != n}(h_j/2) e_n and J = prod_j h_j/2 exactly;
 * warped boxes: the discrete metric identities sum_i D_i (Ja)^i = 0 hold to
   round-off, the two sides of every face see the same normal, J > 0, and at
-  high degree the metrics converge to the analytic cofactors of the map."""
+  high degree the metrics converge to the analytic cofactors of the map;
+* warped boxes: sum W J is the box volume to round-off (rank-one Jacobian of
+  the warp, SBP)."""
 import numpy as np
 import pytest
 
@@ -86,3 +88,21 @@ def test_warped_metrics_converge_to_map(orc):
             worst_J = max(worst_J, abs(J[e, q] - det) / det)
             worst_Ja = max(worst_Ja, np.abs(Ja[e, :, :, q] - cof).max() / np.abs(cof).max())
     assert worst_J < 1e-4 and worst_Ja < 1e-4, (worst_J, worst_Ja)
+
+
+@pytest.mark.parametrize("dim,p,n,warp", [(2, 3, (3, 4), 0.1), (2, 6, (2, 3), 0.15), (3, 3, (2, 3, 2), 0.1),
+                                          (3, 5, (3, 2, 2), 0.1), (3, 7, (2, 1, 2), 0.05)])
+def test_warped_volume_is_exact(orc, dim, p, n, warp):
+    """sum_i W_i J_i over a warped periodic box is its volume to round-off at
+    any degree: the map adds one scalar phi to every coordinate, so the
+    collocation Jacobian is prod(h/2) (1 + sum_k D_k phi) (a rank-one update of
+    the identity), and by the SBP property 1^T M D = 1^T B the weighted sum of
+    D_k phi over an element is a difference of its face values, which cancels
+    over the periodic mesh.  A wrong D, a dropped term of the determinant or
+    a wrong scale breaks it."""
+    m = orc.Mesh(dim, p, n, warp=warp, lo=(-1.0, -2.0, 0.0)[:dim] + (0.0,) * (3 - dim),
+                 hi=(1.0, 2.0, 3.0)[:dim] + (1.0,) * (3 - dim))
+    _, J = m.metrics()
+    vol = float(np.prod([(2.0, 4.0, 3.0)[j] for j in range(dim)]))
+    assert J.min() > 0
+    assert abs(np.sum(m.weights()[None, :] * J) - vol) < 1e-13 * vol
