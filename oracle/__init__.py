@@ -83,8 +83,6 @@ def _load():
         lib.orc_totals.argtypes = [C.c_void_p, dp, dp]
         lib.orc_entropy_rate.argtypes = [C.c_void_p, dp, dp]
         lib.orc_entropy_rate.restype = C.c_double
-        lib.orc_total_entropy.argtypes = [C.c_void_p, dp]
-        lib.orc_total_entropy.restype = C.c_double
         lib.orc_max_dt.argtypes = [C.c_void_p, dp, C.c_double]
         lib.orc_max_dt.restype = C.c_double
         lib.orc_rk4.argtypes = [C.c_void_p, dp, C.c_double, C.c_int, C.c_double, dp]
@@ -308,9 +306,6 @@ class Mesh:
         u = self._state(u)
         du = self.rhs(u) if du is None else self._state(du)
         return self._lib.orc_entropy_rate(self._h, _ptr(u), _ptr(du))
-
-    def total_entropy(self, u) -> float:
-        return self._lib.orc_total_entropy(self._h, _ptr(self._state(u)))
 
     def max_dt(self, u, cfl: float) -> float:
         return self._lib.orc_max_dt(self._h, _ptr(self._state(u)), cfl)

@@ -873,20 +873,6 @@ double orc_entropy_rate(const orc_mesh *m, const double *u, const double *du) {
   return (double)s;
 }
 
-/* total entropy sum J_i W_i U(u_i) */
-double orc_total_entropy(const orc_mesh *m, const double *u) {
-  long double s = 0.0L;
-  double zero[3] = {0, 0, 0};
-  for (int64_t e = 0; e < m->ne; ++e)
-    for (int i = 0; i < m->nn; ++i) {
-      double ui[5], U, F;
-      gather(m, u, e, i, ui);
-      orc_entropy(m->d.dim, m->d.gamma, ui, zero, &U, &F);
-      s += (long double)m->J[e * m->nn + i] * weight(m, i) * U;
-    }
-  return (double)s;
-}
-
 /* R17: dt = cfl * 2 / ((p+1) max_i sum_n (|v.Ja^n_i| + c_i |Ja^n_i|) / J_i) */
 double orc_max_dt(const orc_mesh *m, const double *u, double cfl) {
   double lmax = 0.0;
