@@ -123,18 +123,26 @@ esdg_status esdg_set_stream(esdg_problem *prob, void *stream);
 esdg_status esdg_get_coords(const esdg_problem *prob, double *x);
 
 /* 1/J per node, [elem][node] (node x-fastest), into a caller-owned host
- * buffer of n_elem * nodes_per_elem doubles: the values the kernels scale
- * the right-hand side with, J = det(dx/dxi) from the collocation
- * derivatives of the node coordinates (Sec. 2.3, metric terms); in FP32 mode
- * the FP32 values the kernels read, widened.  Affine meshes: the box's
- * constant 1/J.  For host quadratures sum_i J_i W_i f_i (W the LGL weights
+ * buffer of n_elem * nodes_per_elem doubles, J = det(dx/dxi) from the
+ * collocation derivatives of the node coordinates (Sec. 2.3, metric terms).
+ * Curved meshes: the values the kernels scale the right-hand side with (in
+ * FP32 mode the FP32 values they read, widened).  Affine meshes: the box's
+ * exact constant 1/J = prod_n 2/h_n in FP64 (the kernels apply it as the
+ * per-direction factors 2/h_n of the contravariant vectors and never read
+ * 1/J itself).  For host quadratures sum_i J_i W_i f_i (W the LGL weights
  * of esdg_operators, tensor products per element).  Synchronous (a strided
  * device-to-host copy on the problem's stream); ESDG_EINVAL for a NULL
- * argument, ESDG_EDEVICE if the copy fails. */
+ * argument, ESDG_EDEVICE if the copy fails, ESDG_ENOMEM if host memory for
+ * the FP32 staging runs out. */
 esdg_status esdg_get_inv_jacobian(esdg_problem *prob, double *inv_j);
 
-/* Set / read the conserved state u[elem][var][node] (FP64, host or device
- * memory as `where` says; device pointers must be on the handle's device). */
+/* Set / read the conserved state u[elem][var][node]: the nodal values of
+ * the conserved variables (rho, rho v, rho e) of the compressible Euler
+ * equations (Sec. 3) that the semi-discretisation du/dt = RHS(u) of Sec. 2
+ * advances.  FP64, host or device memory as `where` says (device pointers
+ * on the handle's device); in FP32 mode set rounds to FP32 on the device and
+ * get widens.  Host calls synchronise the stream.  ESDG_EINVAL for a NULL
+ * pointer; esdg_get_state before any esdg_set_state gives ESDG_ESTATE. */
 esdg_status esdg_set_state(esdg_problem *prob, const double *u, int32_t where);
 esdg_status esdg_get_state(esdg_problem *prob, double *u, int32_t where);
 
@@ -142,15 +150,21 @@ esdg_status esdg_get_state(esdg_problem *prob, double *u, int32_t where);
  * du has the state layout, FP64, host or device memory. */
 esdg_status esdg_rhs(esdg_problem *prob, double *du, int32_t where);
 
-/* step!: advance the state by nsteps steps of the problem's integrator
- * (esdg_set_integrator): classical RK4 (Butcher a = 1/2, 1/2, 1; b = 1/6, 1/3,
- * 1/3, 1/6) in low-storage form (state, accumulator and two alternating stage
- * buffers), or the five-stage 2N-storage scheme; each stage one fused
- * launch (surface flux + volume term + lifting + stage update).  dt > 0: fixed step; dt <= 0:
- * dt = cfl*2/((p+1) max_i sum_n (|v.Ja^n|+c|Ja^n|)/J_i) recomputed at the start
- * of every step on the device.  The problem's time (device, FP64) advances by
- * each step's dt.  t_inout (may be NULL): on entry the time to start from, on
- * return the time reached (this synchronises the stream). */
+/* step!: advance the state by nsteps steps of an explicit Runge-Kutta
+ * method, the time integration of the semi-discretisation (Sec. 4.1: the
+ * paper's runs use explicit low-storage Runge-Kutta schemes): the problem's
+ * integrator (esdg_set_integrator), classical RK4 (Butcher a = 1/2, 1/2, 1;
+ * b = 1/6, 1/3, 1/3, 1/6) in low-storage form (state, accumulator and two
+ * alternating stage buffers), or the five-stage 2N-storage scheme; each
+ * stage one fused launch (surface flux + volume term + lifting + stage
+ * update).  dt > 0: fixed step; dt <= 0: the CFL step of esdg_max_dt,
+ * recomputed at the start of every step on the device.  The problem's time
+ * (device, FP64) advances by each step's dt.  t_inout (may be NULL): on
+ * entry the time to start from, on return the time reached (this
+ * synchronises the stream).  ESDG_ENONPHYSICAL, with nothing enqueued, if an
+ * earlier kernel met a non-physical state (the flag is cleared by reporting
+ * it); with t_inout also if this call's own kernels met one.  ESDG_EINVAL for
+ * nsteps < 0 or dt <= 0 with cfl <= 0; ESDG_ESTATE before esdg_set_state. */
 esdg_status esdg_step(esdg_problem *prob, double dt, int32_t nsteps, double cfl,
                       double *t_inout);
 
@@ -171,21 +185,33 @@ esdg_status esdg_get_integrator(const esdg_problem *prob, int32_t *integrator);
 esdg_status esdg_set_time(esdg_problem *prob, double t);
 esdg_status esdg_get_time(esdg_problem *prob, double *t);
 
+/* The reductions below synchronise the stream, write their result and then
+ * return ESDG_ENONPHYSICAL if any kernel so far met a non-physical state
+ * (rho <= 0, p <= 0 or non-finite; the flag is cleared by reporting it).
+ * ESDG_EINVAL for a NULL output, ESDG_ESTATE before esdg_set_state. */
+
 /* entropy_rate: dS/dt = sum_i J_i W_i w(u_i) . RHS_i with the entropy
  * U = -rho s/(gamma-1), s = ln p - gamma ln rho (Sec. 2 entropy definitions);
  * FP64 fixed-order reduction on the device.  Zero to round-off for the
  * Ranocha flux in volume and surface on periodic meshes. */
 esdg_status esdg_entropy_rate(esdg_problem *prob, double *dSdt);
 
-/* totals[v] = sum_i J_i W_i u_{i,v} (FP64, fixed order); totals has dim+2 entries. */
+/* totals[v] = sum_i J_i W_i u_{i,v}, the discrete integrals of the conserved
+ * variables that the semi-discretisation keeps constant on periodic meshes
+ * (Sec. 2, conservation); FP64, fixed order; dim+2 entries. */
 esdg_status esdg_totals(esdg_problem *prob, double *totals);
 
-/* CFL step size of the current state (same formula as esdg_step). */
+/* CFL step size of the current state, the same formula esdg_step uses:
+ * dt = cfl*2/((p+1) max_i sum_n (|v_i.Ja^n_i| + c_i |Ja^n_i|)/J_i), c the
+ * speed of sound.  The paper's runs control the step size by a CFL
+ * condition (Sec. 4.1) without stating the formula; this is the library's
+ * reading of it.  FP64 maximum on the device; ESDG_EINVAL for cfl <= 0. */
 esdg_status esdg_max_dt(esdg_problem *prob, double cfl, double *dt);
 
 /* Wait for the handle's stream and report deferred device errors
  * (ESDG_ENONPHYSICAL if any kernel saw a non-physical state; the flag is
- * cleared by reporting it). */
+ * cleared by reporting it).  The flag lives in host-mapped memory, so
+ * esdg_step can report it without waiting. */
 esdg_status esdg_sync(esdg_problem *prob);
 
 /* Per-kernel timing with hipEvents on the handle's stream: while enabled,
@@ -256,8 +282,10 @@ esdg_status esdg_batch_create(esdg_problem *const *probs, int32_t count, const d
                               int32_t flags, esdg_batch **out);
 void esdg_batch_destroy(esdg_batch *batch);
 
-/* nsteps RK4 steps of every member as in esdg_step (dt > 0 fixed, else CFL
- * with each member's own dt). */
+/* nsteps steps of every member as in esdg_step (dt > 0 fixed, else CFL
+ * with each member's own dt).  ESDG_ENONPHYSICAL, with nothing enqueued,
+ * while a member's non-physical flag is raised (esdg_batch_sync names the
+ * member and clears its flag). */
 esdg_status esdg_batch_step(esdg_batch *batch, double dt, int32_t nsteps, double cfl);
 
 /* Right-hand side of every member's state; du[i] (FP64, state layout, host or

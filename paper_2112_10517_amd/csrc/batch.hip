@@ -33,13 +33,11 @@ struct GraphEntry {
   hipGraphExec_t exec = nullptr;
 };
 
-// pointers of member i's time slots and flag, gathered by one kernel
-__global__ void __launch_bounds__(256) gather_status_kernel(double* const* times, const int* const* flags, int par,
-                                                            int count, double* t_out, int* f_out) {
+// member i's time (slot par of its time slots), gathered by one kernel
+__global__ void __launch_bounds__(256) gather_times_kernel(double* const* times, int par, int count, double* t_out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   t_out[i] = times[i][par];
-  f_out[i] = *flags[i];
 }
 
 }  // namespace
@@ -61,9 +59,7 @@ struct esdg_batch {
   int version = -1;   // tile-variant table version the groups were built for
   std::vector<GraphEntry> graphs;
   double** time_ptrs = nullptr;  // device: SCAL of every member
-  int** flag_ptrs = nullptr;     // device: FLAG of every member
   double* t_out = nullptr;       // device [count]
-  int* f_out = nullptr;          // device [count]
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> step_events;
   std::string err;
@@ -251,25 +247,30 @@ esdg_status check_batch(esdg_batch* b) {
   return ESDG_OK;
 }
 
-esdg_status gather(esdg_batch* b, std::vector<double>* t, std::vector<int>* f) {
+esdg_status gather(esdg_batch* b, std::vector<double>* t) {
   int count = (int)b->probs.size();
   int par = b->par;
-  void* args[] = {&b->time_ptrs, &b->flag_ptrs, &par, &count, &b->t_out, &b->f_out};
-  ESDG_TRY(launch_kernel(launcher_on(b, b->stream), -1, (const void*)&gather_status_kernel,
+  void* args[] = {&b->time_ptrs, &par, &count, &b->t_out};
+  ESDG_TRY(launch_kernel(launcher_on(b, b->stream), -1, (const void*)&gather_times_kernel,
                          dim3((unsigned)((count + 255) / 256)), dim3(256), args));
   t->resize(count);
-  f->resize(count);
   ESDG_HIP(&b->err, hipMemcpyAsync(t->data(), b->t_out, sizeof(double) * count, hipMemcpyDeviceToHost, b->stream));
-  ESDG_HIP(&b->err, hipMemcpyAsync(f->data(), b->f_out, sizeof(int) * count, hipMemcpyDeviceToHost, b->stream));
   ESDG_HIP(&b->err, hipStreamSynchronize(b->stream));
   return ESDG_OK;
+}
+
+// first member whose non-physical flag is raised (no wait), or -1
+int flagged_member(const esdg_batch* b) {
+  for (size_t i = 0; i < b->probs.size(); ++i)
+    if (flag_raised(b->probs[i])) return (int)i;
+  return -1;
 }
 
 void destroy_batch(esdg_batch* b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_graphs(b);
   free_groups(b);
-  void* bufs[] = {b->time_ptrs, b->flag_ptrs, b->t_out, b->f_out};
+  void* bufs[] = {b->time_ptrs, b->t_out};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   for (auto& e : b->step_events) {
@@ -371,18 +372,11 @@ static esdg_status batch_create_impl(esdg_problem* const* probs, int32_t count, 
     }
   }
   std::vector<double*> tp(count);
-  std::vector<int*> fp(count);
-  for (int i = 0; i < count; ++i) {
-    tp[i] = probs[i]->SCAL;
-    fp[i] = probs[i]->FLAG;
-  }
+  for (int i = 0; i < count; ++i) tp[i] = probs[i]->SCAL;
   if (hipMalloc((void**)&b->time_ptrs, sizeof(double*) * count) != hipSuccess ||
-      hipMalloc((void**)&b->flag_ptrs, sizeof(int*) * count) != hipSuccess ||
-      hipMalloc((void**)&b->t_out, sizeof(double) * count) != hipSuccess ||
-      hipMalloc((void**)&b->f_out, sizeof(int) * count) != hipSuccess)
+      hipMalloc((void**)&b->t_out, sizeof(double) * count) != hipSuccess)
     return bail(bfail(b, ESDG_ENOMEM, "device allocation of the batch tables failed"));
   if (hipMemcpyAsync(b->time_ptrs, tp.data(), sizeof(double*) * count, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-      hipMemcpyAsync(b->flag_ptrs, fp.data(), sizeof(int*) * count, hipMemcpyHostToDevice, b->stream) != hipSuccess ||
       hipStreamSynchronize(b->stream) != hipSuccess)
     return bail(bfail(b, ESDG_EDEVICE, "upload of the batch tables failed"));
   esdg_status st = refresh_groups(b);
@@ -404,6 +398,11 @@ static esdg_status batch_step_impl(esdg_batch* b, double dt, int32_t nsteps, dou
   const bool use_cfl = !(dt > 0.0);
   if (use_cfl && !(cfl > 0.0)) return bfail(b, ESDG_EINVAL, "dt <= 0 needs cfl > 0");
   if (nsteps == 0) return ESDG_OK;
+  // members an earlier kernel found non-physical are not stepped;
+  // esdg_batch_sync names them and clears their flags
+  const int flagged = flagged_member(b);
+  if (flagged >= 0)
+    return report(&b->err, ESDG_ENONPHYSICAL, "member %d met a non-physical state (see esdg_batch_sync)", flagged);
   ESDG_TRY(refresh_groups(b));
   ESDG_TRY(sync_in(b));
   const Launcher L = launcher_on(b, b->stream);
@@ -478,8 +477,7 @@ static esdg_status batch_times_impl(esdg_batch* b, double* t) {
   ESDG_TRY(sync_in(b));
   ESDG_TRY(align_parity(b));
   std::vector<double> tv;
-  std::vector<int> fv;
-  ESDG_TRY(gather(b, &tv, &fv));
+  ESDG_TRY(gather(b, &tv));
   std::copy(tv.begin(), tv.end(), t);
   return ESDG_OK;
 }
@@ -490,17 +488,12 @@ static esdg_status batch_sync_impl(esdg_batch* b, int32_t* bad) {
   if (bad) *bad = -1;
   ESDG_TRY(sync_in(b));
   ESDG_TRY(align_parity(b));
-  std::vector<double> tv;
-  std::vector<int> fv;
-  ESDG_TRY(gather(b, &tv, &fv));
-  for (size_t i = 0; i < fv.size(); ++i) {
-    if (fv[i]) {
-      if (bad) *bad = (int32_t)i;
-      ESDG_HIP(&b->err, hipMemsetAsync(b->probs[i]->FLAG, 0, sizeof(int), b->stream));
-      ESDG_HIP(&b->err, hipStreamSynchronize(b->stream));
-      return report(&b->err, ESDG_ENONPHYSICAL, "member %zu met a non-physical state (rho <= 0, p <= 0 or non-finite)",
-                    i);
-    }
+  ESDG_HIP(&b->err, hipStreamSynchronize(b->stream));
+  const int i = flagged_member(b);
+  if (i >= 0) {
+    if (bad) *bad = (int32_t)i;
+    flag_clear(b->probs[i]);
+    return report(&b->err, ESDG_ENONPHYSICAL, "member %d met a non-physical state (rho <= 0, p <= 0 or non-finite)", i);
   }
   return ESDG_OK;
 }

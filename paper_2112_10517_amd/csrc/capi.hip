@@ -221,6 +221,14 @@ esdg_status read_scalars(esdg_problem* P, int first, int count, double* out) {
   return ESDG_OK;
 }
 
+// ESDG_ENONPHYSICAL (and the flag cleared) if a kernel has raised P's
+// non-physical flag; no wait for the stream
+esdg_status report_flag(esdg_problem* P) {
+  if (!flag_raised(P)) return ESDG_OK;
+  flag_clear(P);
+  return fail(P, ESDG_ENONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or non-finite) met by a kernel");
+}
+
 esdg_status set_time(esdg_problem* P, double t) {
   double* dst = P->SCAL + P->par;
   void* args[] = {&dst, &t};
@@ -228,10 +236,11 @@ esdg_status set_time(esdg_problem* P, double t) {
 }
 
 void free_buffers(esdg_problem* P) {
-  void* bufs[] = {P->U,       P->Y,    P->Y2,   P->R,   P->DU,   P->STAGE64, P->METRIC,
-                  P->NFACE,   P->PARTIAL, P->SCAL, P->LAM, P->FLAG, P->DESC,    P->FACEB};
+  void* bufs[] = {P->U,     P->Y,       P->Y2,   P->R,   P->DU,   P->STAGE64, P->METRIC,
+                  P->NFACE, P->PARTIAL, P->SCAL, P->LAM, P->DESC, P->FACEB};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  if (P->FLAG_H) (void)hipHostFree(P->FLAG_H);
   for (auto& t : P->launches) {
     (void)hipEventDestroy(t.start);
     (void)hipEventDestroy(t.stop);
@@ -315,7 +324,7 @@ esdg_status esdg_footprint(const esdg_mesh_desc* d, int64_t* bytes) {
   int blocks;
   int64_t per;
   reduction_blocks(E * nn, &blocks, &per);
-  b += 8 * 8 * (int64_t)blocks + 16 * 8 + 2 * kLamSlots * 8 + 4 + (int64_t)sizeof(ProbDesc<double>);
+  b += 8 * 8 * (int64_t)blocks + 16 * 8 + 2 * kLamSlots * 8 + (int64_t)sizeof(ProbDesc<double>);
   *bytes = b;
   return ESDG_OK;
 }
@@ -394,13 +403,17 @@ static esdg_status init_mesh_impl(const esdg_mesh_desc* d, esdg_problem** out) {
                 {&P->Y2, ns},
                 {(void**)&P->PARTIAL, sizeof(double) * 8 * (size_t)P->red_blocks},
                 {(void**)&P->SCAL, sizeof(double) * 16},
-                {(void**)&P->LAM, sizeof(unsigned long long) * 2 * kLamSlots},
-                {(void**)&P->FLAG, sizeof(int)}};
+                {(void**)&P->LAM, sizeof(unsigned long long) * 2 * kLamSlots}};
   for (auto& a : allocs) {
     if (hipMalloc(a.ptr, a.bytes) != hipSuccess) {
       return fail(nullptr, ESDG_ENOMEM, "device allocation of %zu bytes failed", a.bytes);
     }
   }
+  if (hipHostMalloc((void**)&P->FLAG_H, sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&P->FLAG, P->FLAG_H, 0) != hipSuccess) {
+    return fail(nullptr, ESDG_ENOMEM, "pinned host allocation of the non-physical flag failed");
+  }
+  flag_clear(P);
   if (P->nodes == NODES_GAUSS &&
       hipMalloc(&P->FACEB, (size_t)P->E * 2 * P->dim * (P->dim + 4) * P->nf * P->rsize) != hipSuccess) {
     return fail(nullptr, ESDG_ENOMEM, "device allocation of the face states failed");
@@ -457,8 +470,7 @@ static esdg_status init_mesh_impl(const esdg_mesh_desc* d, esdg_problem** out) {
     }
   }
   // cleared on the handle's stream (which need not be ordered with the null stream)
-  if (hipMemsetAsync(P->FLAG, 0, sizeof(int), P->stream) != hipSuccess ||
-      hipMemsetAsync(P->SCAL, 0, sizeof(double) * 16, P->stream) != hipSuccess ||
+  if (hipMemsetAsync(P->SCAL, 0, sizeof(double) * 16, P->stream) != hipSuccess ||
       hipStreamSynchronize(P->stream) != hipSuccess) {
     return fail(nullptr, ESDG_EDEVICE, "device initialisation failed");
   }
@@ -508,7 +520,7 @@ esdg_status esdg_get_coords(const esdg_problem* P, double* x) {
   return ESDG_OK;
 }
 
-esdg_status esdg_get_inv_jacobian(esdg_problem* P, double* inv_j) {
+static esdg_status get_inv_jacobian_impl(esdg_problem* P, double* inv_j) {
   ESDG_TRY(check_handle(P, false));
   if (!inv_j) return fail(P, ESDG_EINVAL, "NULL argument");
   const size_t count = (size_t)P->E * P->nn;
@@ -530,6 +542,11 @@ esdg_status esdg_get_inv_jacobian(esdg_problem* P, double* inv_j) {
     for (size_t i = 0; i < count; ++i) inv_j[i] = f[i];
   }
   return ESDG_OK;
+}
+
+esdg_status esdg_get_inv_jacobian(esdg_problem* P, double* inv_j) {
+  // the FP32 path stages the values in a host vector: no exception crosses the ABI
+  return guarded(P ? &P->err : nullptr, [&] { return get_inv_jacobian_impl(P, inv_j); });
 }
 
 esdg_status esdg_set_state(esdg_problem* P, const double* u, int32_t where) {
@@ -590,6 +607,8 @@ esdg_status esdg_step(esdg_problem* P, double dt, int32_t nsteps, double cfl, do
   if (nsteps < 0) return fail(P, ESDG_EINVAL, "nsteps must be >= 0");
   const bool use_cfl = !(dt > 0.0);
   if (use_cfl && !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "dt <= 0 needs cfl > 0");
+  // a state an earlier kernel found non-physical is not stepped
+  ESDG_TRY(report_flag(P));
   if (t_inout) ESDG_TRY(set_time(P, *t_inout));
   if (nsteps > 0) {
     // classical RK4 in low-storage form (U state, R accumulator) or the 2N
@@ -618,7 +637,10 @@ esdg_status esdg_step(esdg_problem* P, double dt, int32_t nsteps, double cfl, do
     }
     P->lam_valid = use_cfl;
   }
-  if (t_inout) ESDG_TRY(read_scalars(P, P->par, 1, t_inout));
+  if (t_inout) {
+    ESDG_TRY(read_scalars(P, P->par, 1, t_inout));  // synchronises: this call's kernels have run
+    ESDG_TRY(report_flag(P));
+  }
   return ESDG_OK;
 }
 
@@ -651,35 +673,30 @@ esdg_status esdg_entropy_rate(esdg_problem* P, double* dSdt) {
   if (!dSdt) return fail(P, ESDG_EINVAL, "NULL output");
   ESDG_TRY(rhs_into(P, P->DU));
   ESDG_TRY(run_reduce(P, launcher_of(P), RED_ENTROPY, 0.0, nullptr));
-  return read_scalars(P, 2, 1, dSdt);
+  ESDG_TRY(read_scalars(P, 2, 1, dSdt));
+  return report_flag(P);
 }
 
 esdg_status esdg_totals(esdg_problem* P, double* totals) {
   ESDG_TRY(check_handle(P, true));
   if (!totals) return fail(P, ESDG_EINVAL, "NULL output");
   ESDG_TRY(run_reduce(P, launcher_of(P), RED_TOTALS, 0.0, nullptr));
-  return read_scalars(P, 2, P->nv, totals);
+  ESDG_TRY(read_scalars(P, 2, P->nv, totals));
+  return report_flag(P);
 }
 
 esdg_status esdg_max_dt(esdg_problem* P, double cfl, double* dt) {
   ESDG_TRY(check_handle(P, true));
   if (!dt || !(cfl > 0.0)) return fail(P, ESDG_EINVAL, "need cfl > 0 and an output pointer");
   ESDG_TRY(run_reduce(P, launcher_of(P), RED_MAXLAMBDA, cfl, nullptr));
-  return read_scalars(P, 2, 1, dt);
+  ESDG_TRY(read_scalars(P, 2, 1, dt));
+  return report_flag(P);
 }
 
 esdg_status esdg_sync(esdg_problem* P) {
   ESDG_TRY(check_handle(P, false));
   ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
-  int flag = 0;
-  ESDG_HIP(&P->err, hipMemcpyAsync(&flag, P->FLAG, sizeof(int), hipMemcpyDeviceToHost, P->stream));
-  ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
-  if (flag) {
-    ESDG_HIP(&P->err, hipMemsetAsync(P->FLAG, 0, sizeof(int), P->stream));
-    ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));
-    return fail(P, ESDG_ENONPHYSICAL, "non-physical state (rho <= 0, p <= 0 or non-finite) met by a kernel");
-  }
-  return ESDG_OK;
+  return report_flag(P);
 }
 
 esdg_status esdg_get_tile_variant(const esdg_problem* P, int32_t* variant, int32_t* elems_per_block) {

@@ -71,7 +71,7 @@ struct ProbDesc {
   const Real* nface;         // curved: [dim][E][dim][nf] normal of the + face of each element
   unsigned long long* lam;   // CFL: 2 x kLamSlots slots by step parity (bit patterns of non-negative doubles)
   double* time;              // time of the state, 2 slots by step parity
-  int* flag;                 // non-physical state flag
+  int* flag;                 // non-physical state flag (host-mapped memory; kernels store 1)
   Real* faceb;               // Gauss: entropy-projected face states [E][2 dim][dim+4][nf] (rho, v, p, log rho, log beta)
   double t_end;              // a step never passes t_end: dt = min(dt, t_end - t)
   int E, n0, n1, n2;         // elements, per direction
@@ -852,7 +852,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     const Real E_ = uo[r][DIM + 1];
     const Real v0 = m0 * inv_rho, v1 = m1 * inv_rho, v2 = m2 * inv_rho;
     const Real p = gm1 * (E_ - Real(0.5) * (m0 * v0 + m1 * v1 + m2 * v2));
-    if (!(rho > Real(0)) || !(p > Real(0)) || !isfinite(E_) || !isfinite(m0 + m1 + m2)) atomicOr(P.flag, 1);
+    if (!(rho > Real(0)) || !(p > Real(0)) || !isfinite(E_) || !isfinite(m0 + m1 + m2)) *(volatile int*)P.flag = 1;
     s_prim[el][0][i] = rho;
     s_prim[el][1][i] = v0;
     if (DIM > 1) s_prim[el][DIM > 1 ? 2 : 0][i] = v1;
@@ -1162,7 +1162,7 @@ __global__ void __launch_bounds__((Tile<DIM, N>::THREADS)) gauss_project_kernel(
     const double lp = (s + g * lb) / (1.0 - g);
     const double lr = lb + lp;
     const double rho = exp(lr), p = exp(lp);
-    if (!(beta > 0.0) || !isfinite(rho + p)) atomicOr(P.flag, 1);
+    if (!(beta > 0.0) || !isfinite(rho + p)) *(volatile int*)P.flag = 1;
     const size_t o = (((size_t)(e0 + el) * (2 * DIM) + fc) * NPF) * NF + f;
     fb[o] = (Real)rho;
 #pragma unroll

@@ -51,7 +51,8 @@ struct esdg_problem {
   double* SCAL = nullptr;     // FP64 scalars: [0..1] time by step parity, [2..7] results
   unsigned long long* LAM = nullptr;  // CFL slots: 2 x kLamSlots by step parity (bit patterns of doubles)
   void* DESC = nullptr;               // ProbDesc<Real> of this problem (device)
-  int* FLAG = nullptr;                // non-physical flag
+  int* FLAG = nullptr;                // non-physical flag: device address of FLAG_H
+  int* FLAG_H = nullptr;              // the flag in host-mapped pinned memory (kernels store 1)
   void* FACEB = nullptr;              // Gauss: entropy-projected face states
   int red_blocks = 1;
   int64_t red_per_block = 256;
@@ -125,6 +126,13 @@ struct StepCtl {
 enum { BUF_U = 0, BUF_Y = 1, BUF_Y2 = 2, BUF_R = 3, BUF_DU = 4 };
 
 inline unsigned long long* lam_slot(esdg_problem* P, int k) { return P->LAM + k * kLamSlots; }
+
+// The non-physical flag of a problem lives in host-mapped pinned memory: a
+// kernel that meets rho <= 0, p <= 0 or a non-finite state stores 1 into it,
+// and the host reads it without waiting for the stream (a raised flag is
+// seen once the kernel that stored it has run).  Only the host clears it.
+inline bool flag_raised(const esdg_problem* P) { return __atomic_load_n(P->FLAG_H, __ATOMIC_ACQUIRE) != 0; }
+inline void flag_clear(esdg_problem* P) { __atomic_store_n(P->FLAG_H, 0, __ATOMIC_RELEASE); }
 
 // Tile variant of the stage kernel currently chosen for P's parameters
 // (process-wide table, written by the autotuner) and its version counter.

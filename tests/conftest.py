@@ -18,3 +18,17 @@ def orc():
     import oracle
     oracle.build()
     return oracle
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    # the measured parity figures of every GPU check (R20 per conserved
+    # variable, difference over sigma, fraction of the bar used)
+    try:
+        import parity
+    except ImportError:
+        return
+    lines = parity.summary_lines()
+    if lines:
+        terminalreporter.section("parity against the oracle")
+        for ln in lines:
+            terminalreporter.write_line(ln)

@@ -1,0 +1,118 @@
+"""Parity bars of the GPU tests against the CPU oracle (one definition for
+every test module, the smoke check included).
+
+FP64 right-hand sides, per conserved variable v:
+
+    max_i |gpu_iv - oracle_iv| <= max(REL * max_i |RHS_iv|, SIGMA64 * max_i sigma_iv)
+
+sigma_i is the oracle's sum of the magnitudes of every term of RHS_i
+(Mesh.rhs_scale, pinned in test_oracle_scale.py).  REL = 1e-12 is the
+relative target (reading R20: the max-norm error of a variable over the
+max norm of its right-hand side).  The sigma term covers rows whose terms
+cancel: an FP64 evaluation of a sum of terms in any order, the oracle's
+included, carries an error of a few eps * sigma, so where sigma/|RHS| is
+large no FP64 evaluation is within REL of the exact value.  SIGMA64 =
+1e-14 (45 eps) bounds the difference of two such evaluations with the
+flux arithmetic's own rounding (log means, reciprocals) in each term; the
+measured GPU-oracle difference is at most 4.4e-15 sigma.  Every FP64 check
+records the R20 figure per variable and the sigma ratio; the session summary
+prints them, so a bar met only through the sigma term is visible.
+
+States after time steps, per variable:
+
+    max_i |gpu_iv - oracle_iv| <= REL * max_i |u_iv| + SIGMA64 * T * max_i sigma_iv(u_0)
+
+with T the integrated time: each step adds dt times the RHS rounding
+(the stage weights sum to one).
+
+FP32 bulk against the FP64 oracle: max_i |gpu32_iv - oracle64_iv| <=
+SIGMA32 * max_i sigma_iv, SIGMA32 = 1e-6 (about 17 units of FP32 round-off
+of the sums; measured 0.5e-7 .. 1.2e-7 sigma).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+REL = 1e-12
+SIGMA64 = 1e-14
+SIGMA32 = 1e-6
+
+# (label, kind, R20 per variable, max |d| / max sigma, ratio to the bar)
+RECORDS = []
+
+
+def _per_var(a, b, fn):
+    return [fn(np.asarray(a)[:, v], np.asarray(b)[:, v]) for v in range(np.asarray(b).shape[1])]
+
+
+def r20(gpu, ref):
+    """max|gpu - ref| / max|ref| per conserved variable."""
+    def f(a, b):
+        s = np.abs(b).max()
+        d = np.abs(a - b).max()
+        return float(d / s) if s > 0 else float(d)
+    return _per_var(gpu, ref, f)
+
+
+def rhs64(gpu, ref, sigma, label=""):
+    """Worst ratio of the FP64 right-hand-side difference to its bar (pass: <= 1)."""
+    gpu = np.asarray(gpu)
+    worst, srat = 0.0, 0.0
+    for v in range(ref.shape[1]):
+        d = np.abs(gpu[:, v] - ref[:, v]).max()
+        bound = max(REL * np.abs(ref[:, v]).max(), SIGMA64 * sigma[:, v].max())
+        worst = max(worst, d / bound)
+        srat = max(srat, d / sigma[:, v].max())
+    RECORDS.append((label, "rhs64", r20(gpu, ref), srat, worst))
+    return worst
+
+
+def state64(gpu, ref, sigma0=None, t_span=0.0, label=""):
+    """Worst ratio of an FP64 state difference after steps to its bar (pass: <= 1)."""
+    gpu = np.asarray(gpu)
+    worst, srat = 0.0, 0.0
+    for v in range(ref.shape[1]):
+        d = np.abs(gpu[:, v] - ref[:, v]).max()
+        bound = REL * np.abs(ref[:, v]).max()
+        if sigma0 is not None and t_span > 0:
+            s = sigma0[:, v].max()
+            bound += SIGMA64 * t_span * s
+            srat = max(srat, d / (t_span * s))
+        worst = max(worst, d / bound)
+    RECORDS.append((label, "state64", r20(gpu, ref), srat, worst))
+    return worst
+
+
+def state32(gpu, ref, sigma0, t_span, nsteps, label=""):
+    """Worst ratio of an FP32-bulk state difference after nsteps RK4 steps
+    to its bar (pass: <= 1): every stage rounds the state to FP32 (eps32
+    |u| per stage, four per step) and every step adds dt times the FP32
+    right-hand-side error (SIGMA32 sigma), i.e.
+    4 nsteps eps32 max|u_v| + SIGMA32 T max sigma_v(u_0)."""
+    gpu = np.asarray(gpu)
+    eps32 = 2.0 ** -24
+    worst, srat = 0.0, 0.0
+    for v in range(ref.shape[1]):
+        d = np.abs(gpu[:, v] - ref[:, v]).max()
+        s = sigma0[:, v].max()
+        bound = 4 * nsteps * eps32 * np.abs(ref[:, v]).max() + SIGMA32 * t_span * s
+        worst = max(worst, d / bound)
+        srat = max(srat, d / (t_span * s))
+    RECORDS.append((label, "state32", r20(gpu, ref), srat, worst))
+    return worst
+
+
+def rhs32(gpu, ref, sigma, label=""):
+    """max over variables of max|gpu32 - oracle64| / max sigma_v (pass: <= SIGMA32)."""
+    gpu = np.asarray(gpu)
+    ws = max(np.abs(gpu[:, v] - ref[:, v]).max() / sigma[:, v].max() for v in range(ref.shape[1]))
+    RECORDS.append((label, "rhs32", r20(gpu, ref), ws, ws / SIGMA32))
+    return ws
+
+
+def summary_lines():
+    out = []
+    for label, kind, r, srat, worst in RECORDS:
+        out.append("%-7s %-58s R20 %s  |d|/sigma %.1e  bar use %.2f"
+                   % (kind, label[:58], " ".join("%.1e" % x for x in r), srat, worst))
+    return out

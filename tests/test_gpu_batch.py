@@ -11,10 +11,9 @@ import pytest
 
 from paper_2112_10517_amd import inputs
 
-pytestmark = pytest.mark.gpu
+import parity
 
-TOL32 = 1e-6
-TOL64_REL, TOL64_SIGMA = 1e-12, 5e-14
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
@@ -191,9 +190,9 @@ def test_batched_fp32_subset_vs_oracle(orc, esdg):
     for s, u, d in zip(specs, us, outs):
         m = orc.Mesh(3, s[1], s[2], warp=s[3], vol_flux=s[4], surf_flux=s[5])
         ref, sigma = m.rhs(u), m.rhs_scale(u)
-        err = max(np.abs(d[:, v] - ref[:, v]).max() / sigma[:, v].max() for v in range(5))
+        err = parity.rhs32(d, ref, sigma, label="batched fp32 p=%d %s warp %.1f" % (s[1], s[2], s[3]))
         worst = max(worst, err)
-        assert err <= TOL32, (s, err)
+        assert err <= parity.SIGMA32, (s, err)
     print("batched fp32 subset: worst err/sigma %.2e over %d problems" % (worst, len(specs)))
 
 
@@ -209,21 +208,20 @@ def test_batched_fp64_member_vs_oracle(orc, esdg):
     for s, u, d in zip(specs, us, outs):
         m = orc.Mesh(s[0], s[1], s[2], warp=s[3], vol_flux=s[4], surf_flux=s[5])
         ref, sigma = m.rhs(u), m.rhs_scale(u)
-        for v in range(ref.shape[1]):
-            bound = max(TOL64_REL * np.abs(ref[:, v]).max(), TOL64_SIGMA * sigma[:, v].max())
-            assert np.abs(d[:, v] - ref[:, v]).max() <= bound
+        assert parity.rhs64(d, ref, sigma, label="batched fp64 %dD p=%d %s" % (s[0], s[1], s[2])) <= 1.0
 
 
 # ---- serving
 
-def job(kind, n, p, seed=0):
+def job(kind, n, p, prec="fp32"):
     """(mesh keywords, initial state) of a served job: density wave on
-    [-1,1]^3 or Taylor-Green vortex on [0,2pi]^3, affine, FP32 bulk."""
+    [-1,1]^3 or Taylor-Green vortex on [0,2pi]^3, affine, FP32 bulk unless
+    prec says otherwise."""
     if kind == "dw":
-        mesh = dict(dim=3, p=p, n=(n, n, n), precision="fp32")
+        mesh = dict(dim=3, p=p, n=(n, n, n), precision=prec)
         lo, hi = (-1.0,) * 3, (1.0,) * 3
     else:
-        mesh = dict(dim=3, p=p, n=(n, n, n), lo=(0.0,) * 3, hi=(2 * np.pi,) * 3, precision="fp32")
+        mesh = dict(dim=3, p=p, n=(n, n, n), lo=(0.0,) * 3, hi=(2 * np.pi,) * 3, precision=prec)
         lo, hi = (0.0,) * 3, (2 * np.pi,) * 3
     from oracle import Mesh
     x = Mesh(3, p, (n, n, n), lo=lo, hi=hi).coords()
@@ -232,7 +230,7 @@ def job(kind, n, p, seed=0):
 
 
 def serve(esdg, jobs, t_end, steps_per_tick=4, budget=0, max_active=0):
-    """Submit jobs (list of (tick to submit at, kind, n, p)); run to completion.
+    """Submit jobs (list of (tick to submit at, kind, n, p[, precision])); run to completion.
     Returns {index: final state} and the largest number of admitted jobs."""
     S = esdg.Server(cfl=0.5, steps_per_tick=steps_per_tick, hbm_budget=budget, max_active=max_active)
     ids, out, peak, tick = {}, {}, 0, 0
@@ -268,6 +266,42 @@ def test_server_result_alone_equals_in_mix(esdg):
     # and alone with another tick length: the same steps, the same result
     alone2, _ = serve(esdg, [target], t_end, steps_per_tick=7)
     assert np.array_equal(alone[0], alone2[0])
+
+
+def served_on_oracle(m, u, t_end, cfl):
+    """A served job on the oracle: classical RK4 steps of the CFL step size
+    of R17, the last one shortened to end at t_end (the server's rule, R22)."""
+    t, k = 0.0, 0
+    while t < t_end:
+        dt = min(m.max_dt(u, cfl), t_end - t)
+        u, _ = m.rk4(u, dt, 1)
+        t += dt
+        k += 1
+    return u, t, k
+
+
+def test_served_results_vs_oracle(orc, esdg):
+    """Each served result against the oracle's RK4 run of the same job to
+    the same end time: FP32 jobs in a mix at the FP32 state bar, one FP64
+    job (in the same mix) at the FP64 state bar."""
+    t_end, cfl = 0.02, 0.5
+    mix = [(0, "dw", 3, 3), (0, "tgv", 3, 4), (1, "dw", 2, 5), (1, "tgv", 2, 3, "fp64")]
+    out, peak = serve(esdg, mix, t_end)
+    assert peak >= 3
+    for i, spec in enumerate(mix):
+        kind, n, p = spec[1:4]
+        prec = spec[4] if len(spec) > 4 else "fp32"
+        _, u = job(kind, n, p)
+        lo, hi = ((-1.0,) * 3, (1.0,) * 3) if kind == "dw" else ((0.0,) * 3, (2 * np.pi,) * 3)
+        m = orc.Mesh(3, p, (n, n, n), lo=lo, hi=hi, vol_flux="ranocha", surf_flux="llf")
+        uo, t, k = served_on_oracle(m, u, t_end, cfl)
+        assert t == t_end
+        sigma0 = m.rhs_scale(u)
+        label = "served %s %s %d^3 p=%d, %d steps to t=%.2f" % (prec, kind, n, p, k, t_end)
+        if prec == "fp64":
+            assert parity.state64(out[i], uo, sigma0, t_end, label=label) <= 1.0
+        else:
+            assert parity.state32(out[i], uo, sigma0, t_end, k, label=label) <= 1.0
 
 
 def test_server_density_wave_accuracy(esdg):

@@ -1,7 +1,7 @@
 """The five-stage 2N-storage integrator (Carpenter and Kennedy; the scheme
 of the paper's FLUXO runs, Sec. 4.1) on the GPU, against the oracle's
-Williamson-form implementation: fixed-dt and CFL steps in FP64 to the 1e-12
-state bar, FP32 against the FP64 oracle, conservation, batches mixing both
+Williamson-form implementation: five fixed-dt and five CFL steps in FP64 to
+the state bar of tests/parity.py, FP32 against the FP64 oracle, conservation, batches mixing both
 integrators (each member bit-identical to stepping alone), and a bitwise
 checkpoint/resume in CFL mode."""
 import numpy as np
@@ -9,9 +9,9 @@ import pytest
 
 from paper_2112_10517_amd import inputs
 
-pytestmark = pytest.mark.gpu
+import parity
 
-TOL = 1e-12
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
@@ -39,18 +39,18 @@ def test_ck45_steps_vs_oracle(orc, esdg, dim, p, n, warp):
     assert g.integrator() == "ck45"
     u = noisy(inputs.random_fourier(m.coords(), 6), 7)
     g.set_state(u)
-    # (two + two steps keep the accumulated rounding of the p = 7 case, whose
-    # right-hand-side rounding scale sigma is the largest, inside the 1e-12 bar)
+    sigma0 = m.rhs_scale(u)
     dt = 0.5 * m.max_dt(u, 1.0)
-    g.step(dt=dt, nsteps=2)
-    uo, _ = m.ck45(u, dt, 2)
-    assert rel_err(g.get_state(), uo) < TOL
+    g.step(dt=dt, nsteps=5)
+    uo, _ = m.ck45(u, dt, 5)
+    label = "ck45 %dD p=%d %s warp %.1f" % (dim, p, n, warp)
+    assert parity.state64(g.get_state(), uo, sigma0, 5 * dt, label=label + " 5 steps") <= 1.0
     # CFL mode, carried across calls
-    t = g.step(dt=0.0, nsteps=1, cfl=0.5, t=0.0)
-    t = g.step(dt=0.0, nsteps=1, cfl=0.5, t=t)
-    uo, to = m.ck45(uo, 0.0, 2, cfl=0.5)
+    t = g.step(dt=0.0, nsteps=2, cfl=0.5, t=0.0)
+    t = g.step(dt=0.0, nsteps=3, cfl=0.5, t=t)
+    uo, to = m.ck45(uo, 0.0, 5, cfl=0.5)
     assert abs(t - to) < 1e-13 * to
-    assert rel_err(g.get_state(), uo) < TOL
+    assert parity.state64(g.get_state(), uo, sigma0, 5 * dt + to, label=label + " +5 CFL steps") <= 1.0
 
 
 def test_ck45_differs_from_rk4_and_conserves(orc, esdg):

@@ -8,9 +8,9 @@ import pytest
 
 from paper_2112_10517_amd import inputs
 
-pytestmark = pytest.mark.gpu
+import parity
 
-TOL64_REL, TOL64_SIGMA, TOL32 = 1e-12, 5e-14, 1e-6
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
@@ -45,11 +45,8 @@ def pair(orc, esdg, dim, p, n, vol, surf, prec="fp64", lo=None, hi=None):
     return m, g
 
 
-def fp64_parity(d, ref, sigma):
-    for v in range(ref.shape[1]):
-        bound = max(TOL64_REL * np.abs(ref[:, v]).max(), TOL64_SIGMA * sigma[:, v].max())
-        err = np.abs(d[:, v] - ref[:, v]).max()
-        assert err <= bound, (v, err, bound)
+def fp64_parity(d, ref, sigma, label):
+    assert parity.rhs64(d, ref, sigma, label=label) <= 1.0
 
 
 @pytest.mark.parametrize("dim,p,n,vol,surf", CASES)
@@ -61,7 +58,7 @@ def test_gauss_rhs_parity(orc, esdg, dim, p, n, vol, surf):
     assert np.abs(g.coords() - x).max() < 1e-15
     u = inputs.random_fourier(x, 7, lo=lo, hi=hi)
     g.set_state(u)
-    fp64_parity(g.rhs(), m.rhs(u), m.rhs_scale(u))
+    fp64_parity(g.rhs(), m.rhs(u), m.rhs_scale(u), "gauss %dD p=%d %s %s/%s" % (dim, p, n, vol, surf))
 
 
 @pytest.mark.parametrize("dim,p,n,vol,surf", [CASES[1], CASES[5], CASES[7]])
@@ -71,9 +68,8 @@ def test_gauss_fp32_rhs(orc, esdg, dim, p, n, vol, surf):
     g.set_state(u)
     ref, sigma = m.rhs(u), m.rhs_scale(u)
     d = g.rhs()
-    ws = max(np.abs(d[:, v] - ref[:, v]).max() / sigma[:, v].max() for v in range(dim + 2))
-    print("gauss fp32 %dD p=%d: err/sigma %.2e" % (dim, p, ws))
-    assert ws <= TOL32
+    ws = parity.rhs32(d, ref, sigma, label="gauss fp32 %dD p=%d" % (dim, p))
+    assert ws <= parity.SIGMA32
 
 
 def test_gauss_steps_parity(orc, esdg):
@@ -84,14 +80,14 @@ def test_gauss_steps_parity(orc, esdg):
     g.step(dt=dt, nsteps=10)
     uo, _ = m.rk4(u, dt, 10)
     ug = g.get_state()
-    for v in range(5):
-        assert np.abs(ug[:, v] - uo[:, v]).max() <= 1e-12 * np.abs(uo[:, v]).max()
+    sigma0 = m.rhs_scale(u)
+    assert parity.state64(ug, uo, sigma0, 10 * dt, label="gauss 3D p=3 10 steps") <= 1.0
     # CFL steps advance with the Gauss weights' CFL value of the oracle
     g.set_state(u)
     t = g.step(dt=0.0, nsteps=3, cfl=0.4, t=0.0)
     uo, to = m.rk4(u, 0.0, 3, cfl=0.4)
     assert abs(t - to) <= 1e-13 * to
-    assert np.abs(g.get_state() - uo).max() <= 1e-12 * np.abs(uo).max()
+    assert parity.state64(g.get_state(), uo, sigma0, to, label="gauss 3D p=3 3 CFL steps") <= 1.0
 
 
 @pytest.mark.parametrize("dim,p,n", [(2, 3, (3, 3)), (3, 4, (2, 2, 2))])
