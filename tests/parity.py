@@ -12,11 +12,17 @@ max norm of its right-hand side).  The sigma term covers rows whose terms
 cancel: an FP64 evaluation of a sum of terms in any order, the oracle's
 included, carries an error of a few eps * sigma, so where sigma/|RHS| is
 large no FP64 evaluation is within REL of the exact value.  SIGMA64 =
-1e-14 (45 eps) bounds the difference of two such evaluations with the
-flux arithmetic's own rounding (log means, reciprocals) in each term; the
-measured GPU-oracle difference is at most 4.4e-15 sigma.  Every FP64 check
-records the R20 figure per variable and the sigma ratio; the session summary
-prints them, so a bar met only through the sigma term is visible.
+3e-14 (about 270 eps) bounds the difference of two independent such
+evaluations.  Two rounding sources set it: the flux arithmetic (log means
+near their branch cut, reciprocals), a few eps per term on each side, and
+the geometry.  The oracle and the library build the curl-form metric terms
+independently, and the curl form applies a derivative operator twice, so
+each side's metrics carry rounding of order eps * max|D~|^2 (2e-14 at p = 3,
+3e-13 at p = 7, relative; measured on the CPU in test_geometry_cpu.py).
+The largest measured GPU-oracle difference is 1.8e-14 sigma, on a warped
+p = 7 mesh; 3e-14 gives that a margin of 1.7.  Every FP64 check records
+the R20 figure per variable and the sigma ratio; the session summary prints
+them, so a bar met only through the sigma term is visible.
 
 States after time steps, per variable:
 
@@ -34,7 +40,7 @@ from __future__ import annotations
 import numpy as np
 
 REL = 1e-12
-SIGMA64 = 1e-14
+SIGMA64 = 3e-14
 SIGMA32 = 1e-6
 
 # (label, kind, R20 per variable, max |d| / max sigma, ratio to the bar)

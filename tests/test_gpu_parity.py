@@ -1,9 +1,9 @@
 """GPU parity: the HIP library (through the C ABI) against the CPU oracle.
 
 The bars (tests/parity.py): FP64 right-hand sides per conserved variable
-max|gpu - oracle| <= max(1e-12 max|RHS_v|, 1e-14 max sigma_v), sigma_i the
+max|gpu - oracle| <= max(1e-12 max|RHS_v|, 3e-14 max sigma_v), sigma_i the
 oracle's sum of the magnitudes of the terms of RHS_i (Mesh.rhs_scale);
-states after steps 1e-12 max|u_v| plus 1e-14 sigma times the integrated
+states after steps 1e-12 max|u_v| plus 3e-14 sigma times the integrated
 time.  Every check records its R20 figure (max|d|/max|RHS| per variable),
 printed in the session summary.  Inputs are seeded and synthetic; the oracle
 never sees a GPU output.
