@@ -201,6 +201,23 @@ esdg_status esdg_entropy_rate(esdg_problem *prob, double *dSdt);
  * (Sec. 2, conservation); FP64, fixed order; dim+2 entries. */
 esdg_status esdg_totals(esdg_problem *prob, double *totals);
 
+/* Allocation-free variant of esdg_totals, for callers that cannot allocate
+ * device memory or wait for the device: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  The same sums, bit for
+ * bit (same kernels and block partition), written as dim+2 doubles to
+ * `totals_dev`, a caller-owned DEVICE pointer, in stream order on the
+ * handle's stream; the call returns without waiting for them.  Allocates
+ * nothing: the block partial sums go to a library-owned static device array
+ * of 16,384 doubles (128 KiB per GPU, held until the process ends), which
+ * every call on that GPU shares, so calls that overlap on one GPU (other
+ * handles, other streams or threads) race and must be serialised by the
+ * caller.  A problem needs red_blocks x (dim+2) <= 16,384 partials, which
+ * every valid problem meets (at most 2,048 blocks); larger needs return
+ * ESDG_EINVAL.  ESDG_ESTATE before set_state; ESDG_ENONPHYSICAL if a
+ * kernel has flagged a non-physical state (the flag is read from
+ * host-mapped memory, without a wait). */
+esdg_status esdg_totals_noalloc(esdg_problem *prob, double *totals_dev);
+
 /* CFL step size of the current state, the same formula esdg_step uses:
  * dt = cfl*2/((p+1) max_i sum_n (|v_i.Ja^n_i| + c_i |Ja^n_i|)/J_i), c the
  * speed of sound.  The paper's runs control the step size by a CFL

@@ -127,13 +127,16 @@ VolKernel pick_projection_kernel(const esdg_problem* P) {
   return gauss_kernel_for(P->prec, P->dim, P->N, P->vf, true);
 }
 
+// partial: blocks x K doubles of block sums; out: the K results (both on the
+// device).  The handle's buffers unless the caller brings others.
 template <typename Real>
-static esdg_status reduce_t(esdg_problem* P, const Launcher& L, int op, double cfl, unsigned long long* slot) {
+static esdg_status reduce_t(esdg_problem* P, const Launcher& L, int op, double cfl, unsigned long long* slot,
+                            double* partial, double* out) {
   RedArgs<Real> a{};
   a.u = (const Real*)P->U;
   a.du = (const Real*)P->DU;
   a.metric = (const Real*)P->METRIC;
-  a.partial = P->PARTIAL;
+  a.partial = partial;
   a.E = P->E;
   a.N = P->N;
   a.dim = P->dim;
@@ -148,14 +151,19 @@ static esdg_status reduce_t(esdg_problem* P, const Launcher& L, int op, double c
   ESDG_TRY(launch_kernel(L, ESDG_KERNEL_REDUCE, reduce_partial_for(P->prec, P->dim, P->mesh, op),
                          dim3(P->red_blocks), dim3(kRedThreads), args));
   int K = op == RED_TOTALS ? P->nv : 1;
-  double* out = P->SCAL + 2;
   int blocks = P->red_blocks, N = P->N;
-  void* args2[] = {&P->PARTIAL, &blocks, &K, &out, &cfl, &N, &slot};
+  void* args2[] = {&partial, &blocks, &K, &out, &cfl, &N, &slot};
   return launch_kernel(L, ESDG_KERNEL_REDUCE, reduce_final_for(op), dim3(1), dim3(kRedThreads), args2);
 }
 
+esdg_status run_reduce_into(esdg_problem* P, const Launcher& L, int op, double cfl, unsigned long long* slot,
+                            double* partial, double* out) {
+  return P->prec == PREC_FP32 ? reduce_t<float>(P, L, op, cfl, slot, partial, out)
+                              : reduce_t<double>(P, L, op, cfl, slot, partial, out);
+}
+
 esdg_status run_reduce(esdg_problem* P, const Launcher& L, int op, double cfl, unsigned long long* slot) {
-  return P->prec == PREC_FP32 ? reduce_t<float>(P, L, op, cfl, slot) : reduce_t<double>(P, L, op, cfl, slot);
+  return run_reduce_into(P, L, op, cfl, slot, P->PARTIAL, P->SCAL + 2);
 }
 
 esdg_status convert_state(esdg_problem* P, const Launcher& L, const void* src, void* dst, int to_fp64) {
@@ -246,6 +254,37 @@ void free_buffers(esdg_problem* P) {
     (void)hipEventDestroy(t.stop);
   }
   P->launches.clear();
+}
+
+}  // namespace
+
+// ---- allocation-free totals: the reduction's block partial sums live in a
+// file-scope device array instead of the handle's buffer.  In host code
+// `scratch` names a host-side stand-in, never the device memory: the
+// device address comes from hipGetSymbolAddress, once per device, with that
+// device current, and only that address is passed to kernels.
+constexpr int kScratchDoubles = 2048 * 8;  // <= 2048 reduction blocks x (dim + 2) sums: 128 KiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on first use)
+esdg_status scratch_address(esdg_problem* P, double** out) {
+  if (P->device < 0 || P->device >= kMaxDevices) return fail(P, ESDG_EINVAL, "device index %d out of range", P->device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[P->device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(P, ESDG_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", P->device, hipGetErrorString(e));
+    g_scratch_ptr[P->device] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[P->device];
+  return ESDG_OK;
 }
 
 }  // namespace
@@ -682,6 +721,24 @@ esdg_status esdg_totals(esdg_problem* P, double* totals) {
   if (!totals) return fail(P, ESDG_EINVAL, "NULL output");
   ESDG_TRY(run_reduce(P, launcher_of(P), RED_TOTALS, 0.0, nullptr));
   ESDG_TRY(read_scalars(P, 2, P->nv, totals));
+  return report_flag(P);
+}
+
+esdg_status esdg_totals_noalloc(esdg_problem* P, double* totals_dev) {
+  ESDG_TRY(check_handle(P, true));
+  if (!totals_dev) return fail(P, ESDG_EINVAL, "NULL output");
+  const int64_t need = (int64_t)P->red_blocks * P->nv;
+  if (need > kScratchDoubles)
+    return fail(P, ESDG_EINVAL, "reduction needs %lld partial sums, above the static scratch of %d doubles",
+                (long long)need, kScratchDoubles);
+  double* partial = nullptr;
+  ESDG_TRY(scratch_address(P, &partial));
+  // untimed launcher: the timing records allocate host objects
+  Launcher L;
+  L.stream = P->stream;
+  L.err = &P->err;
+  // every block writes its K partials before the final pass reads them: no clearing needed
+  ESDG_TRY(run_reduce_into(P, L, RED_TOTALS, 0.0, nullptr, partial, totals_dev));
   return report_flag(P);
 }
 

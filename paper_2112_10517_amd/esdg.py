@@ -82,6 +82,7 @@ SIGNATURES = {
     "esdg_get_time": (_st, [_vp, _dp]),
     "esdg_entropy_rate": (_st, [_vp, _dp]),
     "esdg_totals": (_st, [_vp, _dp]),
+    "esdg_totals_noalloc": (_st, [_vp, _vp]),
     "esdg_max_dt": (_st, [_vp, _d, _dp]),
     "esdg_sync": (_st, [_vp]),
     "esdg_timing_enable": (_st, [_vp, _i32]),
@@ -364,6 +365,16 @@ class Problem:
         t = np.zeros(self.n_var)
         self._call(self._lib.esdg_totals, t.ctypes.data_as(C.POINTER(C.c_double)))
         return t
+
+    def totals_noalloc(self, out):
+        """esdg_totals_noalloc: the totals into `out`, a float64 CUDA tensor of
+        n_var entries, in stream order (no wait; no allocation by the library)."""
+        import torch
+        if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+                and out.is_contiguous() and out.numel() >= self.n_var):
+            raise TypeError("totals_noalloc needs a contiguous float64 CUDA tensor of n_var entries")
+        self._call(self._lib.esdg_totals_noalloc, C.c_void_p(out.data_ptr()))
+        return out
 
     def max_dt(self, cfl: float) -> float:
         r = C.c_double()
