@@ -248,12 +248,15 @@ esdg_status esdg_timing_reset(esdg_problem *prob);
  * line of an element (one wave per direction; the fewest elements filling
  * whole waves; twice the default); variant 3 gives one lane to each node,
  * which sweeps its partners along every direction (each pair evaluated from
- * both ends, fewer registers per lane).  Every variant computes bit-identical
- * results; only the speed differs.  The variant in use is chosen per
- * (dim, p, volume flux, mesh kind, precision, node kind) in a process-wide
- * table; until changed, variant 3 for 3D LGL problems of degree p >= 4
- * (except p = 6 in FP32) and variant 0 otherwise.  2D and Gauss problems
- * have variant 0 only.
+ * both ends, fewer registers per lane); variant 4 (3D, p = 7 only) gives one
+ * lane to each node and has the lanes of a line evaluate each pair once,
+ * handing the flux to the partner lane.  Variants 0-3 compute bit-identical
+ * results; variant 4 adds each node's terms in another order (the same
+ * values up to rounding).  The variant in use is chosen per (dim, p, volume
+ * flux, mesh kind, precision, node kind) in a process-wide table; until
+ * changed, variant 4 for 3D LGL problems of degree 7, variant 3 for degrees
+ * 4-6 (except p = 6 in FP32) and variant 0 otherwise.  2D and Gauss
+ * problems have variant 0 only.
  *   esdg_autotune: times every variant on the problem's current state (reps
  *     right-hand-side launches each, written to internal scratch; the state
  *     is unchanged), stores the fastest in the table and returns it in *best
@@ -262,7 +265,7 @@ esdg_status esdg_timing_reset(esdg_problem *prob);
  *     Synchronises the stream.
  *   esdg_set_tile_variant: store a variant for the problem's parameters.
  *   esdg_get_tile_variant: the variant in use and its elements per workgroup. */
-#define ESDG_TILE_VARIANTS 4
+#define ESDG_TILE_VARIANTS 5
 esdg_status esdg_autotune(esdg_problem *prob, int32_t reps, int32_t *best, double *us_per_variant);
 esdg_status esdg_set_tile_variant(esdg_problem *prob, int32_t variant);
 esdg_status esdg_get_tile_variant(const esdg_problem *prob, int32_t *variant, int32_t *elems_per_block);

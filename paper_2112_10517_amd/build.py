@@ -21,7 +21,8 @@ ARCH = os.environ.get("ESDG_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["capi.hip", "batch.hip", "host_ops.cpp", "server.cpp", "dispatch_misc.hip", "dispatch_vol2d.hip",
            "dispatch_vol3d.hip", "dispatch_vol2d_f32.hip", "dispatch_vol3d_f32.hip", "dispatch_vol3d_tuned.hip",
            "dispatch_vol3d_f32_tuned.hip", "dispatch_vol3d_nodes.hip", "dispatch_vol3d_f32_nodes.hip",
-           "dispatch_gauss.hip", "dispatch_gauss_f32.hip"]
+           "dispatch_gauss.hip", "dispatch_gauss_f32.hip", "dispatch_vol3d_pairs.hip",
+           "dispatch_vol3d_f32_pairs.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include")]

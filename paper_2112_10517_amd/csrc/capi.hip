@@ -82,13 +82,16 @@ std::tuple<int, int, int, int, int, int> tune_key(const esdg_problem* P) {
 }
 }  // namespace
 
-// Variant used until the table holds one for the parameters: the node
-// layout (3) for 3D LGL problems of degree >= 4, where one lane per node
-// keeps enough waves per SIMD to hide the flux latencies and outruns the
-// line layout (measured at p = 4..7 in FP64, p = 4, 5, 7 in FP32); the line
-// layout (0) elsewhere.
+// Variant used until the table holds one for the parameters: for 3D LGL
+// problems, the pair layout (4) at degree 7, where one lane per node keeps
+// enough waves per SIMD and each pair is evaluated once (measured at 32^3:
+// 19-25% faster than the node layout in both precisions); the node layout
+// (3) at degrees 4-6, where one lane per node outruns the line layout
+// (measured at p = 4..6 in FP64, p = 4, 5 in FP32); the line layout (0)
+// elsewhere.
 static int default_tile_variant(const esdg_problem* P) {
   if (P->dim != 3 || P->nodes != NODES_LGL || P->N < 5) return 0;
+  if (P->N == 8) return 4;
   if (P->prec == PREC_FP32 && P->N == 7) return 0;
   return 3;
 }

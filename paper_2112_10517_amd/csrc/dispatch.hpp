@@ -12,7 +12,7 @@ struct VolKernel {
 };
 
 // number of tile variants of the 3D stage kernel (2D has one)
-constexpr int kTileVariants = 4;
+constexpr int kTileVariants = 5;
 
 // stage kernel for the given parameters and tile variant (fn == NULL if none)
 VolKernel stage_kernel_for(int prec, int dim, int N, int vf, int mesh, int variant);
@@ -24,6 +24,8 @@ VolKernel stage_kernel_3d_f64_tuned(int N, int vf, int mesh, int variant);
 VolKernel stage_kernel_3d_f32_tuned(int N, int vf, int mesh, int variant);
 VolKernel stage_kernel_3d_f64_nodes(int N, int vf, int mesh);
 VolKernel stage_kernel_3d_f32_nodes(int N, int vf, int mesh);
+VolKernel stage_kernel_3d_f64_pairs(int N, int vf, int mesh);
+VolKernel stage_kernel_3d_f32_pairs(int N, int vf, int mesh);
 // Legendre-Gauss collocation (affine meshes): the stage kernel, or with
 // project = true the entropy-projection kernel that precedes it
 VolKernel gauss_kernel_for(int prec, int dim, int N, int vf, bool project);

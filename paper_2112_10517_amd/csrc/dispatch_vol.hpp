@@ -11,7 +11,8 @@ namespace esdg {
 template <int DIM, typename Real, int N, int VF, int MESH, int V>
 VolKernel vol_kernel() {
   constexpr int EPB = tile_epb(DIM, N, PrimCount<VF, DIM>::value, (int)sizeof(Real), V);
-  constexpr int LAY = V == 3 ? LAY_NODES : LAY_LINES;  // variant 3: node layout
+  // variant 3: node layout; variant 4: pair layout
+  constexpr int LAY = V == 4 ? LAY_PAIRS : (V == 3 ? LAY_NODES : LAY_LINES);
   using T = Tile<DIM, N, EPB, LAY>;
   VolKernel k;
   k.fn = (const void*)&stage_kernel<DIM, N, VF, MESH, Real, EPB, NODES_LGL, LAY>;
@@ -22,6 +23,9 @@ VolKernel vol_kernel() {
 
 template <int DIM, typename Real, int V, int N>
 VolKernel vol_pick_n(int vf, int mesh) {
+  if constexpr (V == 4 && (DIM != 3 || N != 8)) {
+    return VolKernel{};  // the pair layout exists for 3D N = 8 only
+  } else {
   if (mesh == MESH_AFFINE) {
     if (vf == VF_RANOCHA) return vol_kernel<DIM, Real, N, VF_RANOCHA, MESH_AFFINE, V>();
     if (vf == VF_SHIMA) return vol_kernel<DIM, Real, N, VF_SHIMA, MESH_AFFINE, V>();
@@ -32,6 +36,7 @@ VolKernel vol_pick_n(int vf, int mesh) {
     if (vf == VF_CENTRAL) return vol_kernel<DIM, Real, N, VF_CENTRAL, MESH_CURVED, V>();
   }
   return VolKernel{};
+  }
 }
 
 template <int DIM, typename Real, int V>

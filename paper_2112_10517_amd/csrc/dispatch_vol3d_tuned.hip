@@ -1,4 +1,4 @@
-// 3D stage-kernel instantiations, FP64, tile variants 1 and 2 (3 in its own unit).
+// 3D stage-kernel instantiations, FP64, tile variants 1 and 2 (3 and 4 in their own units).
 #include "dispatch_vol.hpp"
 
 namespace esdg {
@@ -7,6 +7,7 @@ VolKernel stage_kernel_3d_f64_tuned(int N, int vf, int mesh, int variant) {
   if (variant == 1) return vol_pick<3, double, 1>(N, vf, mesh);
   if (variant == 2) return vol_pick<3, double, 2>(N, vf, mesh);
   if (variant == 3) return stage_kernel_3d_f64_nodes(N, vf, mesh);
+  if (variant == 4) return stage_kernel_3d_f64_pairs(N, vf, mesh);
   return VolKernel{};
 }
 

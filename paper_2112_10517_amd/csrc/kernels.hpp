@@ -368,8 +368,12 @@ struct TileShape {
 // evaluated from both ends (twice the flux evaluations), in exchange for a
 // register footprint of one node instead of one line, hence more waves per
 // SIMD at high degree.  Both layouts add the same terms in the same order, so
-// they give the same bits.
-enum Layout { LAY_LINES = 0, LAY_NODES = 1 };
+// they give the same bits.  LAY_PAIRS (3D, N = 8): one lane per node as in
+// LAY_NODES, but the lanes of a line evaluate each pair once in a rotation
+// schedule and hand the flux to the partner lane with a cross-lane permute
+// (pair_fluxes); half the flux evaluations of LAY_NODES, the same values up to
+// the order of the sums.
+enum Layout { LAY_LINES = 0, LAY_NODES = 1, LAY_PAIRS = 2 };
 
 template <int DIM, int N, int EPB_ = TileShape<DIM, N>::EPB0, int LAY_ = LAY_LINES>
 struct Tile {
@@ -388,7 +392,7 @@ struct Tile {
   // waves per SIMD the register allocation must allow: every workgroup of a
   // typical launch resident at once (3 x 64-lane waves per SIMD for N <= 4);
   // node layout: two workgroups of up to 8 waves per CU
-  static constexpr int WPE = LAY == LAY_NODES ? 4 : (N <= 4 ? 3 : (N <= 6 ? 2 : 1));
+  static constexpr int WPE = LAY != LAY_LINES ? 4 : (N <= 4 ? 3 : (N <= 6 ? 2 : 1));
   static_assert(LAY == LAY_LINES || NPT == 1, "node layout: one node per lane");
 };
 
@@ -414,6 +418,7 @@ constexpr int tile_epb(int dim, int N, int np, int rbytes, int variant) {
     return epb0;
   }
   if (variant == 2) return 2 * epb0 * per <= kTileLdsCap ? 2 * epb0 : epb0;
+  if (variant == 4) return 1;  // pair layout: one element of N^3 = 512 nodes
   if (variant == 3) {
     // node layout (LDS: primitives, two direction buffers of halved
     // contravariant vectors, face fluxes): the smallest tile of at least 128
@@ -670,13 +675,94 @@ __device__ __forceinline__ void node_fluxes(const Real (*sp)[Pow<N, DIM>::value]
   }
 }
 
+// Cross-lane copy of one value within a wave: the lane receives `x` of wave
+// lane `src` (ds_bpermute, which reads the VGPRs of the other lanes through
+// the LDS crossbar without using LDS memory; every lane of the wave active).
+__device__ __forceinline__ float lane_pull(int src, float x) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(x)));
+}
+__device__ __forceinline__ double lane_pull(int src, double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// The pairs of one line in direction DIR, each evaluated once (pair layout).
+// The N lanes of a line lie in one wave, lane stride LS apart; the lane at
+// line position a owns node i (node stride N^DIR along the line).  Round d =
+// 1 .. ceil(N/2)-1 pairs every lane with the position b = a+d (mod N): the
+// lane evaluates f(u_a, u_b) once, adds D~_ab F to its own row, and takes
+// from the lane at c = a-d (mod N), which has just evaluated the pair (c, a),
+// its F for D~_ac F.  For even N the last round d = N/2 pairs a with a+N/2
+// from both ends (no exchange; the same cost as leaving half the lanes
+// idle).  Each pair is thus evaluated once apart from the N/2 pairs of the
+// last round: N/2 evaluations per lane and direction instead of N-1.  The
+// flux is bitwise symmetric (volume_flux) and the averaged normal a sum of
+// the two halves, so both lanes of a pair see the same F.  s_rot holds
+// D~_{a,a+d} at [d-1][a] and s_rot + (N/2) N holds D~_{a,a-d} at [d-1][a].
+// The sum runs in the order of the rounds (own, then received), not in
+// increasing k as in the other layouts: the same values up to rounding.
+template <int DIR, int DIM, int N, int LS, int VF, int MESH, typename Real>
+__device__ __forceinline__ void pair_fluxes(const Real (*sp)[Pow<N, DIM>::value], const Real (*sn)[Pow<N, DIM>::value],
+                                            const Prim<Real>& Po, const Real (&no)[3], int i, int a, int lane,
+                                            const Real* s_rot, Real scale, Real inv_gm1, Real (&A)[DIM + 2]) {
+#pragma clang fp contract(off)  // as in line_fluxes
+  constexpr int NV = DIM + 2;
+  constexpr int NP = PrimCount<VF, DIM>::value;
+  constexpr int stride = Pow<N, DIR>::value;
+  constexpr int H = N / 2;                 // rounds with exchange: 1 .. (N-1)/2; even N adds round H
+  static_assert((N & (N - 1)) == 0, "pair layout: N a power of two (positions wrap with a mask)");
+  const int node0 = i - a * stride;        // node at line position 0
+  const int lane0 = lane - a * LS;         // its lane
+  const Real* rot_own = s_rot + a;         // D~_{a,a+d} at (d-1) N
+  const Real* rot_in = s_rot + H * N + a;  // D~_{a,a-d} at (d-1) N
+#pragma unroll
+  for (int v = 0; v < NV; ++v) A[v] = Real(0);
+#pragma unroll 1
+  for (int d = 1; d <= H; ++d) {
+    const int b = (a + d) & (N - 1);
+    const int q = node0 + b * stride;
+    Prim<Real> Pk;
+    Pk.rho = sp[0][q];
+    Pk.v0 = sp[1][q];
+    Pk.v1 = DIM > 1 ? sp[DIM > 1 ? 2 : 0][q] : Real(0);
+    Pk.v2 = DIM > 2 ? sp[DIM > 2 ? 3 : 0][q] : Real(0);
+    Pk.p = sp[DIM + 1][q];
+    Pk.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][q] : Real(0);
+    Pk.b = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][q] : Real(0);
+    Pk.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][q] : Real(0);
+    Real F[NV];
+    if (MESH == MESH_CURVED) {
+      volume_flux<VF, DIM>(Po, Pk, no[0] + sn[0][q], DIM > 1 ? no[1] + sn[DIM > 1 ? 1 : 0][q] : Real(0),
+                           DIM > 2 ? no[2] + sn[DIM > 2 ? 2 : 0][q] : Real(0), inv_gm1, F);
+    } else {
+      volume_flux<VF, DIM>(Po, Pk, DIR == 0 ? Real(1) : Real(0), DIR == 1 ? Real(1) : Real(0),
+                           DIR == 2 ? Real(1) : Real(0), inv_gm1, F);
+    }
+    const Real dab = rot_own[(d - 1) * N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) A[v] = mad(dab, F[v], A[v]);
+    if (2 * d < N) {  // uniform across the wave
+      const int src = lane0 + ((a - d) & (N - 1)) * LS;
+      const Real dac = rot_in[(d - 1) * N];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) A[v] = mad(dac, lane_pull(src, F[v]), A[v]);
+    }
+  }
+  if (MESH == MESH_AFFINE) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) A[v] *= scale;
+  }
+}
+
 // Waves per SIMD the register allocation of a tile must allow: the tile's
 // default, except for the FP64 node tiles up to N = 5, whose prologue (two or
 // three face nodes per lane) spills at four waves (three measured 3% faster
 // at p = 4).
 template <int DIM, int N, int MESH, typename Real, int EPB_, int LAY = LAY_LINES>
 struct StageWaves {
-  static constexpr int value = (LAY == LAY_NODES && sizeof(Real) == 8 && N <= 5) ? 3 : Tile<DIM, N, EPB_, LAY>::WPE;
+  static constexpr int value = (LAY != LAY_LINES && sizeof(Real) == 8 && N <= 5) ? 3 : Tile<DIM, N, EPB_, LAY>::WPE;
 };
 
 template <int DIM, int N, int VF, int MESH, typename Real, int EPB_, int NODES = NODES_LGL, int LAY = LAY_LINES>
@@ -684,8 +770,10 @@ __global__ void __launch_bounds__((Tile<DIM, N, EPB_, LAY>::THREADS))
 __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::value))) stage_kernel(StageArgs<Real> a) {
   static_assert(NODES == NODES_LGL || MESH == MESH_AFFINE, "Gauss collocation is built for affine meshes");
   static_assert(LAY == LAY_LINES || (NODES == NODES_LGL && DIM == 3), "node layout: 3D LGL");
+  static_assert(LAY != LAY_PAIRS || (N == 8 && EPB_ == 1), "pair layout: N = 8, one element (8 waves) per block");
   using T = Tile<DIM, N, EPB_, LAY>;
-  constexpr bool NODEL = LAY == LAY_NODES;
+  constexpr bool NODEL = LAY != LAY_LINES;  // one lane per node (node and pair layouts)
+  constexpr bool PAIRS = LAY == LAY_PAIRS;
   constexpr bool CNODE = NODEL && MESH == MESH_CURVED;
   constexpr int NN = T::NN, NF = T::NF, L = T::L, EPB = T::EPB, NV = T::NV, NFACE = T::NFACE;
   constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, LANES_DIR = T::LANES_DIR;
@@ -699,7 +787,8 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   __shared__ Real s_face[EPB][NV][NFACE];  // surface fluxes of the element's faces
   __shared__ int s_nbr[EPB][2 * DIM];      // neighbour across face (2 dir + side), side 1 = +
   __shared__ Real s_dt[DtInLds<N, Real>::value ? N * N : 1];  // D~ when it stays out of scalar registers
-  __shared__ Real s_dts[NODEL ? N * (N - 1) : 1];  // node layout: D~ rows without the diagonal
+  __shared__ Real s_dts[NODEL ? (PAIRS ? N * N : N * (N - 1)) : 1];  // node layout: D~ rows without the diagonal;
+                                                   // pair layout: D~_{a,a+d}, then D~_{a,a-d} (pair_fluxes)
   // node layout, curved: halved contravariant vectors of two directions
   // (directions 0 and 1, then 2 in the first buffer)
   __shared__ Real s_nrm[CNODE ? EPB : 1][2][DIM][CNODE ? NN : 1];
@@ -788,10 +877,17 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   }
   if (DtInLds<N, Real>::value)
     for (int t = tid; t < N * N; t += THREADS) s_dt[t] = a.ops.Dt[t];
-  if (NODEL)
+  if (NODEL && !PAIRS)
     for (int t = tid; t < N * (N - 1); t += THREADS) {
       const int r = t / (N - 1), j = t - r * (N - 1);
       s_dts[t] = a.ops.Dt[r * N + j + (j >= r ? 1 : 0)];
+    }
+  if (PAIRS)
+    for (int t = tid; t < 2 * (N / 2) * N; t += THREADS) {
+      const int hh = t / ((N / 2) * N), rr = t - hh * (N / 2) * N;
+      const int d = rr / N + 1, ap = rr - (d - 1) * N;
+      const int k = hh ? (ap - d + N) % N : (ap + d) % N;
+      s_dts[t] = a.ops.Dt[ap * N + k];
     }
   __syncthreads();  // s_nbr, s_dt
   Real tL[FPT][NV], tR[FPT][NV], tn[FPT][3];
@@ -909,13 +1005,20 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     const Real(*sn0)[NN] = reinterpret_cast<const Real(*)[NN]>(&s_nrm[CNODE ? el : 0][0][0][0]);
     const Real(*sn1)[NN] = reinterpret_cast<const Real(*)[NN]>(&s_nrm[CNODE ? el : 0][1][0][0]);
     if constexpr (CNODE) { no[0] = sn0[0][i]; no[1] = sn0[1][i]; no[2] = sn0[2][i]; }
-    node_fluxes<0, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, ix, s_dts, P.scale[0],
-                                            a.ops.inv_gm1, Ad);
+    const int lane = tid & 63;
+    // pair layout: a wave is one z-plane of the element, so the lines of
+    // directions 0 and 1 lie in one wave (lane strides 1 and N)
+    if constexpr (PAIRS)
+      pair_fluxes<0, DIM, N, 1, VF, MESH, Real>(sp, sn0, Po, no, i, ix, lane, s_dts, P.scale[0], a.ops.inv_gm1, Ad);
+    else
+      node_fluxes<0, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, ix, s_dts, P.scale[0], a.ops.inv_gm1, Ad);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Sn[v] = Ad[v];
     if constexpr (CNODE) { no[0] = sn1[0][i]; no[1] = sn1[1][i]; no[2] = sn1[2][i]; }
-    node_fluxes<1, DIM, N, VF, MESH, Real>(sp, sn1, Po, no, i, iy, s_dts, P.scale[1],
-                                            a.ops.inv_gm1, Ad);
+    if constexpr (PAIRS)
+      pair_fluxes<1, DIM, N, N, VF, MESH, Real>(sp, sn1, Po, no, i, iy, lane, s_dts, P.scale[1], a.ops.inv_gm1, Ad);
+    else
+      node_fluxes<1, DIM, N, VF, MESH, Real>(sp, sn1, Po, no, i, iy, s_dts, P.scale[1], a.ops.inv_gm1, Ad);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Sn[v] += Ad[v];
     if constexpr (CNODE) {
@@ -928,10 +1031,36 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
         for (int m = 0; m < DIM; ++m) s_nrm[el][0][m][i] = no[m];
       __syncthreads();
     }
-    node_fluxes<2, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, iz, s_dts, P.scale[2],
-                                            a.ops.inv_gm1, Ad);
+    if constexpr (PAIRS) {
+      // direction 2: the lanes are re-mapped so that a wave holds one
+      // y-plane (lane x + N z of wave y takes node (x, y, z)), which puts
+      // each z-line in one wave at lane stride N; the sums go back to the
+      // nodes' own lanes through the primitives' LDS
+      const int i2 = (lane % N) + N * (tid / 64) + N * N * (lane / N);
+      Prim<Real> P2;
+      P2.rho = sp[0][i2];
+      P2.v0 = sp[1][i2];
+      P2.v1 = sp[2][i2];
+      P2.v2 = sp[3][i2];
+      P2.p = sp[4][i2];
+      P2.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][i2] : Real(0);
+      P2.b = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][i2] : Real(0);
+      P2.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][i2] : Real(0);
+      Real n2[3] = {Real(0), Real(0), Real(0)};
+      if constexpr (CNODE) { n2[0] = sn0[0][i2]; n2[1] = sn0[1][i2]; n2[2] = sn0[2][i2]; }
+      pair_fluxes<2, DIM, N, N, VF, MESH, Real>(sp, sn0, P2, n2, i2, lane / N, lane, s_dts, P.scale[2],
+                                                a.ops.inv_gm1, Ad);
+      __syncthreads();  // every lane has read the primitives
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Sn[v] += Ad[v];
+      for (int v = 0; v < NV; ++v) s_acc[0][v][i2] = Ad[v];
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Sn[v] += s_acc[0][v][i];
+    } else {
+      node_fluxes<2, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, iz, s_dts, P.scale[2], a.ops.inv_gm1, Ad);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Sn[v] += Ad[v];
+    }
   }
 
   // ---- volume term, line layout: each lane sweeps the pairs of its line

@@ -25,7 +25,7 @@ KERNEL_STAGE, KERNEL_REDUCE, KERNEL_PROJECT = 1, 2, 3
 NODES = {"lgl": 0, "gauss": 1}
 INTEGRATORS = {"rk4": 0, "ck45": 1}
 PMAX = 7
-TILE_VARIANTS = 4
+TILE_VARIANTS = 5
 BATCH_GRAPHS, BATCH_CONCURRENT = 1, 2
 JOB_QUEUED, JOB_ACTIVE, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 

@@ -289,28 +289,61 @@ def test_isentropic_vortex_parity(orc, esdg, dim, warp, vol):
         assert abs(rate) < 1e-13 * escale and abs(rate - m.entropy_rate(u, du)) < 1e-13 * escale
 
 
-@pytest.mark.parametrize("p,n,warp", [(5, (2, 3, 2), 0.1), (7, (2, 2, 2), 0.0), (7, (2, 1, 2), 0.1)])
-def test_entropy_conservation_node_layout(orc, esdg, p, n, warp):
+@pytest.mark.parametrize("p,n,warp,variant", [(5, (2, 3, 2), 0.1, 3), (7, (2, 2, 2), 0.0, 3), (7, (2, 1, 2), 0.1, 3),
+                                               (7, (2, 2, 2), 0.0, 4), (7, (2, 1, 2), 0.1, 4)])
+def test_entropy_conservation_node_layout(orc, esdg, p, n, warp, variant):
     """Entropy-conservative volume and surface fluxes in the node layout
     (tile variant 3, one lane per node; every pair evaluated from both of its
-    nodes): the right-hand side matches the oracle and dS/dt = 0 to round-off
-    on the scale sum J W |w . du| -- the pair fluxes of the two ends must
-    cancel as exactly as the line layout's single evaluation."""
+    nodes) and the pair layout (variant 4; each pair evaluated by one lane and
+    handed to its partner): the right-hand side matches the oracle and
+    dS/dt = 0 to round-off on the scale sum J W |w . du| -- the pair fluxes
+    of the two ends must cancel as exactly as the line layout's."""
     m, g = make_pair(orc, esdg, 3, p, n, warp=warp, vol="ranocha", surf="ranocha")
     u = noisy(inputs.random_fourier(m.coords(), 8), 6)
     g.set_state(u)
     v_before = g.tile_variant()[0]
     try:
-        g.set_tile_variant(3)
-        assert rhs_parity(g.rhs(), m, u, label="node layout EC p=%d warp %.1f" % (p, warp)) <= 1.0
+        g.set_tile_variant(variant)
+        assert rhs_parity(g.rhs(), m, u, label="variant %d EC p=%d warp %.1f" % (variant, p, warp)) <= 1.0
         du = m.rhs(u)
         w = np.stack([orc.entropy_vars(3, 1.4, u[e, :, i]) for e in range(m.n_elem) for i in range(m.nodes)])
         w = w.reshape(m.n_elem, m.nodes, 5).transpose(0, 2, 1)
         _, J = m.metrics()
         escale = np.sum((J * m.weights()[None, :])[:, None, :] * np.abs(w * du))
         rate = g.entropy_rate()
-        print("p=%d warp=%.1f node layout: entropy rate %.3e (relative %.3e)" % (p, warp, rate, abs(rate) / escale))
+        print("p=%d warp=%.1f variant %d: entropy rate %.3e (relative %.3e)"
+              % (p, warp, variant, rate, abs(rate) / escale))
         assert abs(rate) < 1e-13 * escale and abs(rate - m.entropy_rate(u, du)) < 1e-13 * escale
+    finally:
+        g.set_tile_variant(v_before)
+
+
+PAIR_CASES = [
+    (7, (2, 1, 2), 0.1, "ranocha", "llf"),
+    (7, (2, 2, 1), 0.0, "ranocha", "ranocha"),
+    (7, (1, 2, 2), 0.1, "central", "central"),
+    (7, (2, 2, 2), 0.0, "shima", "llf"),
+    (7, (3, 1, 1), 0.1, "shima", "ranocha"),
+]
+
+
+@pytest.mark.parametrize("p,n,warp,vol,surf", PAIR_CASES)
+def test_pair_layout_parity(orc, esdg, p, n, warp, vol, surf):
+    """Pair layout (tile variant 4): right-hand side and three CFL steps
+    against the oracle (FP64 bars), on seams of periodic boxes one to three
+    elements wide in each direction."""
+    m, g = make_pair(orc, esdg, 3, p, n, warp=warp, vol=vol, surf=surf)
+    u = noisy(inputs.random_fourier(m.coords(), 12), 13)
+    g.set_state(u)
+    v_before = g.tile_variant()[0]
+    try:
+        g.set_tile_variant(4)
+        assert g.tile_variant() == (4, 1)
+        assert rhs_parity(g.rhs(), m, u, label="pair layout p=%d %s %s/%s" % (p, n, vol, surf)) <= 1.0
+        t = g.step(nsteps=3, cfl=0.3, t=0.0)
+        uo, to = m.rk4(u, 0.0, 3, cfl=0.3)
+        assert abs(t - to) <= 1e-14 * to
+        assert state_parity(g.get_state(), uo, m, u, to, label="pair layout p=%d %s 3 CFL steps" % (p, n)) <= 1.0
     finally:
         g.set_tile_variant(v_before)
 

@@ -31,7 +31,9 @@ def shapes(tmp_path_factory):
     for line in out.stdout.splitlines():
         f = line.split()
         rows.append({f[i]: (f[i + 1] if f[i] == "prec" else int(f[i + 1])) for i in range(0, len(f), 2)})
-    assert len(rows) == 7 * 4 * 4
+    # variants 0-3 for N = 2..8, and the pair layout (4) for N = 8; four
+    # (precision, flux, mesh) combinations each
+    assert len(rows) == (7 * 4 + 1) * 4
     return rows
 
 
@@ -50,6 +52,17 @@ def test_node_layout_one_node_per_lane(shapes):
         # at least 128 lanes unless a single element already has fewer nodes... with 80% of them busy
         if s["threads"] >= 128 and s["nn"] >= 27:
             assert 5 * s["epb"] * s["nn"] >= 4 * s["threads"] or s["epb"] == 1, s
+
+
+def test_pair_layout_shape(shapes):
+    """The pair layout: one element of 512 nodes, one lane per node, so each
+    64-lane wave is one z-plane (the x- and y-lines stay inside a wave), and
+    two workgroups (four waves per SIMD) fit a CU's LDS."""
+    pairs = [s for s in shapes if s["variant"] == 4]
+    assert len(pairs) == 4
+    for s in pairs:
+        assert s["nn"] == 512 and s["epb"] == 1 and s["threads"] == 512 and s["npt"] == 1, s
+        assert 2 * s["lds"] <= 160 * 1024 and s["waves"] == 4, s
 
 
 def test_lds_within_budget(shapes):
