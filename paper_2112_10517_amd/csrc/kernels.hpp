@@ -630,8 +630,8 @@ __device__ __forceinline__ void line_fluxes(const Real (*sp)[Pow<N, DIM>::value]
 // D~ without its diagonal, row id holding D~_ik for k = j + (j >= id),
 // j = 0..N-2: the sweep's j-th coefficient is one load at a lane-constant
 // base, and the partner's node index one select and one add.
-template <int DIR, int DIM, int N, int VF, int MESH, typename Real>
-__device__ __forceinline__ void node_fluxes(const Real (*sp)[Pow<N, DIM>::value], const Real (*sn)[Pow<N, DIM>::value],
+template <int DIR, int DIM, int N, int VF, int MESH, typename Real, int RL>
+__device__ __forceinline__ void node_fluxes(const Real (*sp)[RL], const Real (*sn)[RL],
                                             const Prim<Real>& Po, const Real (&no)[3], int i, int id,
                                             const Real* s_dts, Real scale, Real inv_gm1, Real (&A)[DIM + 2]) {
 #pragma clang fp contract(off)  // as in line_fluxes
@@ -675,6 +675,11 @@ __device__ __forceinline__ void node_fluxes(const Real (*sp)[Pow<N, DIM>::value]
   }
 }
 
+// LDS slot of node q when every 64-node block of a row is followed by PAD
+// unused entries (PAD = 0: the node index itself)
+template <int PAD>
+__device__ __forceinline__ int lds_node(int q) { return PAD ? q + (q >> 6) * PAD : q; }
+
 // Cross-lane copy of one value within a wave: the lane receives `x` of wave
 // lane `src` (ds_bpermute, which reads the VGPRs of the other lanes through
 // the LDS crossbar without using LDS memory; every lane of the wave active).
@@ -703,10 +708,11 @@ __device__ __forceinline__ double lane_pull(int src, double x) {
 // D~_{a,a+d} at [d-1][a] and s_rot + (N/2) N holds D~_{a,a-d} at [d-1][a].
 // The sum runs in the order of the rounds (own, then received), not in
 // increasing k as in the other layouts: the same values up to rounding.
-template <int DIR, int DIM, int N, int LS, int VF, int MESH, typename Real>
-__device__ __forceinline__ void pair_fluxes(const Real (*sp)[Pow<N, DIM>::value], const Real (*sn)[Pow<N, DIM>::value],
-                                            const Prim<Real>& Po, const Real (&no)[3], int i, int a, int lane,
-                                            const Real* s_rot, Real scale, Real inv_gm1, Real (&A)[DIM + 2]) {
+// Rows of sp and sn have RL entries, node q at lds_node<PAD>(q).
+template <int DIR, int DIM, int N, int LS, int VF, int MESH, typename Real, int RL, int PAD>
+__device__ __forceinline__ void pair_fluxes(const Real (*sp)[RL], const Real (*sn)[RL], const Prim<Real>& Po,
+                                            const Real (&no)[3], int i, int a, int lane, const Real* s_rot, Real scale,
+                                            Real inv_gm1, Real (&A)[DIM + 2]) {
 #pragma clang fp contract(off)  // as in line_fluxes
   constexpr int NV = DIM + 2;
   constexpr int NP = PrimCount<VF, DIM>::value;
@@ -722,7 +728,7 @@ __device__ __forceinline__ void pair_fluxes(const Real (*sp)[Pow<N, DIM>::value]
 #pragma unroll 1
   for (int d = 1; d <= H; ++d) {
     const int b = (a + d) & (N - 1);
-    const int q = node0 + b * stride;
+    const int q = lds_node<PAD>(node0 + b * stride);
     Prim<Real> Pk;
     Pk.rho = sp[0][q];
     Pk.v0 = sp[1][q];
@@ -779,11 +785,16 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, LANES_DIR = T::LANES_DIR;
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int NM = DIM * DIM + 1;
-  __shared__ Real s_prim[EPB][NP][NN];     // primitive variables (and logs)
+  // node-indexed LDS rows; the pair layout pads each 64-node z-plane by
+  // LPAD entries, so that its z-lines (one node per plane, read by 8 lanes
+  // at once) fall on different banks
+  constexpr int LPAD = PAIRS ? 8 : 0;
+  constexpr int NNL = NN + (NN / 64) * LPAD;
+  __shared__ Real s_prim[EPB][NP][NNL];     // primitive variables (and logs)
   // volume term, summed over directions in order (line layout): reuses the
   // primitives' LDS, which every lane has read into registers by then
   static_assert(NV <= NP, "volume sums fit in the primitives' LDS");
-  Real(*s_acc)[NV][NN] = reinterpret_cast<Real(*)[NV][NN]>(&s_prim[0][0][0]);
+  Real(*s_acc)[NV][NNL] = reinterpret_cast<Real(*)[NV][NNL]>(&s_prim[0][0][0]);
   __shared__ Real s_face[EPB][NV][NFACE];  // surface fluxes of the element's faces
   __shared__ int s_nbr[EPB][2 * DIM];      // neighbour across face (2 dir + side), side 1 = +
   __shared__ Real s_dt[DtInLds<N, Real>::value ? N * N : 1];  // D~ when it stays out of scalar registers
@@ -791,7 +802,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
                                                    // pair layout: D~_{a,a+d}, then D~_{a,a-d} (pair_fluxes)
   // node layout, curved: halved contravariant vectors of two directions
   // (directions 0 and 1, then 2 in the first buffer)
-  __shared__ Real s_nrm[CNODE ? EPB : 1][2][DIM][CNODE ? NN : 1];
+  __shared__ Real s_nrm[CNODE ? EPB : 1][2][DIM][CNODE ? NNL : 1];
 
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -949,22 +960,23 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     const Real v0 = m0 * inv_rho, v1 = m1 * inv_rho, v2 = m2 * inv_rho;
     const Real p = gm1 * (E_ - Real(0.5) * (m0 * v0 + m1 * v1 + m2 * v2));
     if (!(rho > Real(0)) || !(p > Real(0)) || !isfinite(E_) || !isfinite(m0 + m1 + m2)) *(volatile int*)P.flag = 1;
-    s_prim[el][0][i] = rho;
-    s_prim[el][1][i] = v0;
-    if (DIM > 1) s_prim[el][DIM > 1 ? 2 : 0][i] = v1;
-    if (DIM > 2) s_prim[el][DIM > 2 ? 3 : 0][i] = v2;
-    s_prim[el][DIM + 1][i] = p;
+    const int li = lds_node<LPAD>(i);
+    s_prim[el][0][li] = rho;
+    s_prim[el][1][li] = v0;
+    if (DIM > 1) s_prim[el][DIM > 1 ? 2 : 0][li] = v1;
+    if (DIM > 2) s_prim[el][DIM > 2 ? 3 : 0][li] = v2;
+    s_prim[el][DIM + 1][li] = p;
     if (NP > DIM + 2) {
       const Real beta = rho * dev_rcp(p);
-      s_prim[el][(NP > DIM + 2) ? DIM + 2 : 0][i] = dev_log(rho);
-      s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][i] = beta;
-      s_prim[el][(NP > DIM + 2) ? DIM + 4 : 0][i] = dev_log(beta);
+      s_prim[el][(NP > DIM + 2) ? DIM + 2 : 0][li] = dev_log(rho);
+      s_prim[el][(NP > DIM + 2) ? DIM + 3 : 0][li] = beta;
+      s_prim[el][(NP > DIM + 2) ? DIM + 4 : 0][li] = dev_log(beta);
     }
     if constexpr (CNODE) {
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int m = 0; m < DIM; ++m) s_nrm[el][b][m][i] = hm[b][m];
+        for (int m = 0; m < DIM; ++m) s_nrm[el][b][m][li] = hm[b][m];
     }
   }
 
@@ -987,36 +999,39 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   if constexpr (NODEL) {
     const bool ok = tid < EPB * NN && e0 + tid / NN < E;
     const int el = ok ? tid / NN : 0, i = ok ? tid - el * NN : 0;  // idle lanes repeat node 0
-    const Real(*sp)[NN] = s_prim[el];
+    const Real(*sp)[NNL] = s_prim[el];
     const int ix = i % N, iy = (i / N) % N, iz = i / (N * N);
+    const int li = lds_node<LPAD>(i);
     Prim<Real> Po;
-    Po.rho = sp[0][i];
-    Po.v0 = sp[1][i];
-    Po.v1 = sp[2][i];
-    Po.v2 = sp[3][i];
-    Po.p = sp[4][i];
-    Po.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][i] : Real(0);
-    Po.b = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][i] : Real(0);
-    Po.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][i] : Real(0);
+    Po.rho = sp[0][li];
+    Po.v0 = sp[1][li];
+    Po.v1 = sp[2][li];
+    Po.v2 = sp[3][li];
+    Po.p = sp[4][li];
+    Po.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][li] : Real(0);
+    Po.b = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][li] : Real(0);
+    Po.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][li] : Real(0);
     Real no[3] = {Real(0), Real(0), Real(0)};
     Real Ad[NV];
     // the two direction buffers (never read on affine meshes); the node's own
     // vectors are read back from them rather than held in registers
-    const Real(*sn0)[NN] = reinterpret_cast<const Real(*)[NN]>(&s_nrm[CNODE ? el : 0][0][0][0]);
-    const Real(*sn1)[NN] = reinterpret_cast<const Real(*)[NN]>(&s_nrm[CNODE ? el : 0][1][0][0]);
-    if constexpr (CNODE) { no[0] = sn0[0][i]; no[1] = sn0[1][i]; no[2] = sn0[2][i]; }
+    const Real(*sn0)[NNL] = reinterpret_cast<const Real(*)[NNL]>(&s_nrm[CNODE ? el : 0][0][0][0]);
+    const Real(*sn1)[NNL] = reinterpret_cast<const Real(*)[NNL]>(&s_nrm[CNODE ? el : 0][1][0][0]);
+    if constexpr (CNODE) { no[0] = sn0[0][li]; no[1] = sn0[1][li]; no[2] = sn0[2][li]; }
     const int lane = tid & 63;
     // pair layout: a wave is one z-plane of the element, so the lines of
     // directions 0 and 1 lie in one wave (lane strides 1 and N)
     if constexpr (PAIRS)
-      pair_fluxes<0, DIM, N, 1, VF, MESH, Real>(sp, sn0, Po, no, i, ix, lane, s_dts, P.scale[0], a.ops.inv_gm1, Ad);
+      pair_fluxes<0, DIM, N, 1, VF, MESH, Real, NNL, LPAD>(sp, sn0, Po, no, i, ix, lane, s_dts, P.scale[0],
+                                                           a.ops.inv_gm1, Ad);
     else
       node_fluxes<0, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, ix, s_dts, P.scale[0], a.ops.inv_gm1, Ad);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Sn[v] = Ad[v];
-    if constexpr (CNODE) { no[0] = sn1[0][i]; no[1] = sn1[1][i]; no[2] = sn1[2][i]; }
+    if constexpr (CNODE) { no[0] = sn1[0][li]; no[1] = sn1[1][li]; no[2] = sn1[2][li]; }
     if constexpr (PAIRS)
-      pair_fluxes<1, DIM, N, N, VF, MESH, Real>(sp, sn1, Po, no, i, iy, lane, s_dts, P.scale[1], a.ops.inv_gm1, Ad);
+      pair_fluxes<1, DIM, N, N, VF, MESH, Real, NNL, LPAD>(sp, sn1, Po, no, i, iy, lane, s_dts, P.scale[1],
+                                                           a.ops.inv_gm1, Ad);
     else
       node_fluxes<1, DIM, N, VF, MESH, Real>(sp, sn1, Po, no, i, iy, s_dts, P.scale[1], a.ops.inv_gm1, Ad);
 #pragma unroll
@@ -1028,7 +1043,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
       __syncthreads();
       if (tid < EPB * NN && e0 + tid / NN < E)
 #pragma unroll
-        for (int m = 0; m < DIM; ++m) s_nrm[el][0][m][i] = no[m];
+        for (int m = 0; m < DIM; ++m) s_nrm[el][0][m][li] = no[m];
       __syncthreads();
     }
     if constexpr (PAIRS) {
@@ -1037,25 +1052,26 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
       // each z-line in one wave at lane stride N; the sums go back to the
       // nodes' own lanes through the primitives' LDS
       const int i2 = (lane % N) + N * (tid / 64) + N * N * (lane / N);
+      const int l2 = lds_node<LPAD>(i2);
       Prim<Real> P2;
-      P2.rho = sp[0][i2];
-      P2.v0 = sp[1][i2];
-      P2.v1 = sp[2][i2];
-      P2.v2 = sp[3][i2];
-      P2.p = sp[4][i2];
-      P2.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][i2] : Real(0);
-      P2.b = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][i2] : Real(0);
-      P2.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][i2] : Real(0);
+      P2.rho = sp[0][l2];
+      P2.v0 = sp[1][l2];
+      P2.v1 = sp[2][l2];
+      P2.v2 = sp[3][l2];
+      P2.p = sp[4][l2];
+      P2.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][l2] : Real(0);
+      P2.b = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][l2] : Real(0);
+      P2.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][l2] : Real(0);
       Real n2[3] = {Real(0), Real(0), Real(0)};
-      if constexpr (CNODE) { n2[0] = sn0[0][i2]; n2[1] = sn0[1][i2]; n2[2] = sn0[2][i2]; }
-      pair_fluxes<2, DIM, N, N, VF, MESH, Real>(sp, sn0, P2, n2, i2, lane / N, lane, s_dts, P.scale[2],
-                                                a.ops.inv_gm1, Ad);
+      if constexpr (CNODE) { n2[0] = sn0[0][l2]; n2[1] = sn0[1][l2]; n2[2] = sn0[2][l2]; }
+      pair_fluxes<2, DIM, N, N, VF, MESH, Real, NNL, LPAD>(sp, sn0, P2, n2, i2, lane / N, lane, s_dts, P.scale[2],
+                                                           a.ops.inv_gm1, Ad);
       __syncthreads();  // every lane has read the primitives
 #pragma unroll
-      for (int v = 0; v < NV; ++v) s_acc[0][v][i2] = Ad[v];
+      for (int v = 0; v < NV; ++v) s_acc[0][v][l2] = Ad[v];
       __syncthreads();
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Sn[v] += s_acc[0][v][i];
+      for (int v = 0; v < NV; ++v) Sn[v] += s_acc[0][v][li];
     } else {
       node_fluxes<2, DIM, N, VF, MESH, Real>(sp, sn0, Po, no, i, iz, s_dts, P.scale[2], a.ops.inv_gm1, Ad);
 #pragma unroll
