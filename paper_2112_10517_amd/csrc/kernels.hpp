@@ -93,6 +93,7 @@ struct StageArgs {
   // sum over directions of wave speeds of the step's start state, the maximum
   // over the problem's kLamSlots slots of parity par; then clipped to t_end
   double dt_fixed, cfl;
+  double gamma64;       // gamma in FP64 (the CFL wave speeds are FP64 in both precisions)
   int par;              // step parity: time and CFL slots of the step's start state
   int lam_update;       // LAST stage: atomic max of the new state's value into parity 1 - par
   StageOps<Real> ops;
@@ -473,34 +474,39 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
 }
 
 // CFL wave-speed sum of one node, sum_n (|v.Ja^n| + c |Ja^n|) / J (affine:
-// sum_n (|v_n| + c) 2/h_n), from its conservative state.  me points at the
-// node's first metric entry (stride nn between entries; curved meshes).  The
-// last RK stage and the CFL reduction both use this one expression, so the
-// step size of a state is the same whichever of them computed it.
+// sum_n (|v_n| + c) 2/h_n), from its conservative state, evaluated in FP64
+// for both state precisions (the time step is an FP64 reduction).  me points
+// at the node's first metric entry (stride nn between entries; curved
+// meshes).  The last RK stage and the CFL reduction both use this one
+// expression, so the step size of a state is the same whichever of them
+// computed it.
 template <int DIM, int MESH, typename Real, typename MP>
-__device__ __forceinline__ Real cfl_rate(const Real (&u)[DIM + 2], MP me, int64_t nn, Real rinvj,
-                                         const Real* scale, Real gamma) {
-  const Real gm1 = gamma - Real(1);
-  const Real rho = u[0], ir = dev_rcp(rho);
-  const Real w0 = u[1] * ir;
-  const Real w1 = DIM > 1 ? u[DIM > 1 ? 2 : 1] * ir : Real(0);
-  const Real w2 = DIM > 2 ? u[DIM > 2 ? 3 : 1] * ir : Real(0);
-  const Real pr = gm1 * (u[DIM + 1] - Real(0.5) * rho * (w0 * w0 + w1 * w1 + w2 * w2));
-  const Real c = sqrt(gamma * pr * ir);
-  Real lam = Real(0);
+__device__ __forceinline__ double cfl_rate(const Real (&ur)[DIM + 2], MP me, int64_t nn, Real rinvj_r,
+                                           const Real* scale, double gamma) {
+  double u[DIM + 2];
+#pragma unroll
+  for (int v = 0; v < DIM + 2; ++v) u[v] = (double)ur[v];
+  const double gm1 = gamma - 1.0;
+  const double rho = u[0], ir = dev_rcp(rho);
+  const double w0 = u[1] * ir;
+  const double w1 = DIM > 1 ? u[DIM > 1 ? 2 : 1] * ir : 0.0;
+  const double w2 = DIM > 2 ? u[DIM > 2 ? 3 : 1] * ir : 0.0;
+  const double pr = gm1 * (u[DIM + 1] - 0.5 * rho * (w0 * w0 + w1 * w1 + w2 * w2));
+  const double c = sqrt(gamma * pr * ir);
+  double lam = 0.0;
   if (MESH == MESH_CURVED) {
 #pragma unroll
     for (int n = 0; n < DIM; ++n) {
-      const Real j0 = me[(n * DIM) * nn];
-      const Real j1 = DIM > 1 ? me[(n * DIM + (DIM > 1 ? 1 : 0)) * nn] : Real(0);
-      const Real j2 = DIM > 2 ? me[(n * DIM + (DIM > 2 ? 2 : 0)) * nn] : Real(0);
+      const double j0 = (double)me[(n * DIM) * nn];
+      const double j1 = DIM > 1 ? (double)me[(n * DIM + (DIM > 1 ? 1 : 0)) * nn] : 0.0;
+      const double j2 = DIM > 2 ? (double)me[(n * DIM + (DIM > 2 ? 2 : 0)) * nn] : 0.0;
       lam += fabs(w0 * j0 + w1 * j1 + w2 * j2) + c * sqrt(j0 * j0 + j1 * j1 + j2 * j2);
     }
-    lam *= rinvj;
+    lam *= (double)rinvj_r;
   } else {
-    lam = (fabs(w0) + c) * scale[0];
-    if (DIM > 1) lam += (fabs(w1) + c) * scale[DIM > 1 ? 1 : 0];
-    if (DIM > 2) lam += (fabs(w2) + c) * scale[DIM > 2 ? 2 : 0];
+    lam = (fabs(w0) + c) * (double)scale[0];
+    if (DIM > 1) lam += (fabs(w1) + c) * (double)scale[DIM > 1 ? 1 : 0];
+    if (DIM > 2) lam += (fabs(w2) + c) * (double)scale[DIM > 2 ? 2 : 0];
   }
   return lam;
 }
@@ -1208,8 +1214,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     if (lam_out) {
       // CFL wave-speed sum of the new state at this node
       const auto me = MESH == MESH_CURVED ? metric + (size_t)ee * (NM * NN) + i : metric;
-      const Real lam = cfl_rate<DIM, MESH, Real>(unew, me, (int64_t)NN, rinvj[r], P.scale, a.ops.gamma);
-      const double ld = (double)lam;
+      const double ld = cfl_rate<DIM, MESH, Real>(unew, me, (int64_t)NN, rinvj[r], P.scale, a.gamma64);
       if (!(ld <= lam_max)) lam_max = ld;  // a NaN wins and poisons dt (flagged anyway)
     }
   }
@@ -1392,7 +1397,7 @@ __global__ void __launch_bounds__(kRedThreads) reduce_partial_kernel(RedArgs<Rea
         for (int v = 0; v < NV; ++v) ur[v] = a.u[(e * NV + v) * nn + i];
         const Real* me = MESH == MESH_CURVED ? a.metric + e * NM * nn + i : a.metric;
         const Real rinvj = MESH == MESH_CURVED ? a.metric[(e * NM + DIM * DIM) * nn + i] : Real(1);
-        const double lam = (double)cfl_rate<DIM, MESH, Real>(ur, me, (int64_t)nn, rinvj, a.scale, (Real)a.gamma);
+        const double lam = cfl_rate<DIM, MESH, Real>(ur, me, (int64_t)nn, rinvj, a.scale, a.gamma);
         if (!(lam <= accv[0])) accv[0] = lam;  // NaN propagates
       }
     }

@@ -214,6 +214,7 @@ esdg_status run_stage_on(const esdg_problem* rep, const Launcher& L, const VolKe
   a.coef_a = (Real)coef_a;
   a.dt_fixed = ctl.dt_fixed;
   a.cfl = ctl.cfl;
+  a.gamma64 = rep->gamma;
   a.par = ctl.par;
   a.lam_update = ctl.lam_update;
   a.ops = stage_ops<Real>(rep);
