@@ -120,6 +120,72 @@ def time_steps(g, steps, warmup, cfl, torch):
     return 1e3 * (time.perf_counter() - t0) / steps
 
 
+# Comparisons of GPU results with the CPU oracle.  The GPU sections record
+# what they computed (right-hand sides or states, per precision, on the
+# elements listed) with the recipe of the input; the cpu_baseline leg runs
+# the oracle on its own mesh and inputs and fills in the errors.
+ORACLE_CHECKS = []
+
+
+def sample_elements(n, count, seed):
+    """Seeded element sample of an n^3 box: seams and corners of the periodic
+    box plus `count` random elements."""
+    import numpy as np
+    E = n ** 3
+    rng = np.random.default_rng(seed)
+    corners = [0, n - 1, n * (n - 1), E - 1, E // 2]
+    return np.unique(np.concatenate([corners, rng.choice(E, min(count, E), replace=False)])).astype(np.int64)
+
+
+def record_check(where, key, mesh, state, gpu, elems=None, steps=None, dt=None, sample=""):
+    """Queue an oracle comparison.  where: the dict the result goes into,
+    under `key`; mesh: oracle.Mesh arguments; state: (generator name, args)
+    of the input; gpu: {precision: host array [elem][var][node]} on `elems`
+    (None: every element); steps/dt: compare states after `steps` RK4 steps
+    of fixed dt instead of right-hand sides."""
+    ORACLE_CHECKS.append(dict(where=where, key=key, mesh=mesh, state=state, gpu=gpu, elems=elems, steps=steps,
+                              dt=dt, sample=sample))
+
+
+def error_figures(gpu, ref, sigma=None):
+    """Per conserved variable: relative L2 (over the compared nodes) and Linf
+    errors of gpu against ref, and max|gpu - ref| / max sigma."""
+    import numpy as np
+    nv = ref.shape[1]
+    l2 = [float("%.3e" % (np.linalg.norm(gpu[:, v] - ref[:, v]) / np.linalg.norm(ref[:, v]))) for v in range(nv)]
+    li = [float("%.3e" % (np.abs(gpu[:, v] - ref[:, v]).max() / np.abs(ref[:, v]).max())) for v in range(nv)]
+    out = {"rel_l2": l2, "rel_linf": li}
+    if sigma is not None:
+        out["max_err_over_sigma"] = float("%.3e" % max(np.abs(gpu[:, v] - ref[:, v]).max() / sigma[:, v].max()
+                                                        for v in range(nv)))
+    return out
+
+
+def run_oracle_checks(oracle, inputs):
+    """The oracle side of every recorded comparison (cpu_baseline leg)."""
+    import numpy as np
+    for c in ORACLE_CHECKS:
+        t0 = time.perf_counter()
+        m = oracle.Mesh(**c["mesh"])
+        gen, gargs = c["state"]
+        u = getattr(inputs, gen)(m.coords(), **gargs)
+        res = {"vs": "FP64 oracle", "sample": c["sample"]}
+        if c["steps"]:
+            ref, _ = m.rk4(u, c["dt"], c["steps"])
+            for prec, arr in c["gpu"].items():
+                res[prec] = error_figures(arr, ref)
+        else:
+            if c["elems"] is None:
+                ref, sig = m.rhs(u), m.rhs_scale(u)
+            else:
+                ref, sig = m.rhs_elements(u, c["elems"])
+            for prec, arr in c["gpu"].items():
+                res[prec] = error_figures(arr, ref, sig)
+        res["oracle_s"] = round(time.perf_counter() - t0, 2)
+        del m
+        c["where"][c["key"]] = res
+
+
 def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
     """Same workload in FP32 bulk precision and with the Shima volume flux."""
     import numpy as np
@@ -127,11 +193,17 @@ def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
     out = {}
     steps = max(10, args.steps // 2)
     # FP32 bulk (state, metrics, fluxes in FP32; FP64 reductions) against FP64
+    # and, in the cpu_baseline leg, both against the oracle: the right-hand
+    # side of the initial state and the state after 10 equal steps (the FP64
+    # problem's step size for both)
     res = {}
+    dt = None
     for prec in ("fp64", "fp32"):
         g = esdg.Problem(dim, p, (n, n, n), warp=0.1, volume_flux=args.flux, surface_flux="llf", precision=prec)
         g.set_state(u0_dev)
-        dt = 0.5 * g.max_dt(args.cfl)
+        res[prec + "_rhs"] = g.rhs()
+        if dt is None:
+            dt = 0.5 * g.max_dt(args.cfl)
         g.step(dt=dt, nsteps=10)
         res[prec] = g.get_state()
         g.set_state(u0_dev)
@@ -146,6 +218,12 @@ def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
         "speedup_vs_fp64": round(res["fp64_ms"] / res["fp32_ms"], 3),
         "state_max_rel_err_vs_fp64_after_10_steps": float("%.3e" % err),
     }
+    mesh = dict(dim=dim, p=p, n=(n, n, n), warp=0.1, vol_flux=args.flux, surf_flux="llf")
+    record_check(out["fp32_bulk"], "rhs_vs_oracle", mesh, ("random_fourier", {"seed": 2}),
+                 {"fp64": res["fp64_rhs"], "fp32": res["fp32_rhs"]}, sample="every node, initial state")
+    record_check(out["fp32_bulk"], "state_vs_oracle_after_10_steps", mesh, ("random_fourier", {"seed": 2}),
+                 {"fp64": res["fp64"], "fp32": res["fp32"]}, steps=10, dt=dt,
+                 sample="every node, 10 RK4 steps of dt %.4e" % dt)
     # Shima (KEP, no log means) volume flux, FP64
     g = esdg.Problem(dim, p, (n, n, n), warp=0.1, volume_flux="shima", surface_flux="llf")
     g.set_state(u0_dev)
@@ -259,7 +337,8 @@ def precision_sweep(args, esdg, inputs, torch, dev):
     bulk against FP64.  PID of both (CFL-mode RK4 steps); relative L2 and Linf
     differences of the FP32 right-hand side and of the FP32 state after a
     fixed number of equal fixed-dt steps, against the FP64 ones (per
-    conserved variable; the FP64 path matches the oracle to 1e-12); the
+    conserved variable), and both precisions against the oracle on sampled
+    elements (cpu_baseline leg); the
     entropy rate (FP64 reduction) of the initial state with the LLF surface
     flux and, as the discrete residual, with the entropy-conservative one,
     relative to sum J W |w . du|.  The
@@ -272,6 +351,7 @@ def precision_sweep(args, esdg, inputs, torch, dev):
     for p in [int(q) for q in args.sweep_p.split(",") if q]:
         res, u0 = {}, None
         dt = None
+        el = sample_elements(n, 40, p)
         for prec in ("fp64", "fp32"):
             g = esdg.Problem(3, p, (n, n, n), warp=0.1, volume_flux="ranocha", surface_flux="llf", precision=prec)
             if u0 is None:
@@ -279,6 +359,7 @@ def precision_sweep(args, esdg, inputs, torch, dev):
                 u0 = torch.from_numpy(u0_host).to(dev)
             g.set_state(u0)
             res[prec + "_rhs"] = g.rhs()
+            res[prec + "_rhs_el"] = res[prec + "_rhs"][el]
             res[prec + "_dsdt_llf"] = g.entropy_rate()
             if dt is None:
                 dt = 0.5 * g.max_dt(args.sweep_cfl)
@@ -332,6 +413,10 @@ def precision_sweep(args, esdg, inputs, torch, dev):
                                                                        res[prec + "_dsdt_scale"]))}
                              for prec in ("fp64", "fp32")},
         }
+        record_check(out["p%d" % p], "rhs_vs_oracle",
+                     dict(dim=3, p=p, n=(n, n, n), warp=0.1, vol_flux="ranocha", surf_flux="llf"),
+                     ("density_wave", {}), {"fp64": res["fp64_rhs_el"], "fp32": res["fp32_rhs_el"]}, elems=el,
+                     sample="%d elements (seed %d: seams, corners and random), initial state" % (len(el), p))
         del res
     out["workload"] = ("density wave rho = 1 + 0.98 sin(pi(x+y+z)), v = (0.1,0.2,0.3), p = 20 on the warped %d^3 "
                        "box, Ranocha + LLF, RK4 at CFL %.2f" % (n, args.sweep_cfl))
@@ -342,7 +427,9 @@ def batched(args, esdg, torch, dev, fp64_pid):
     """256 uneven periodic 3D problems (n ~ U{4..24}, p ~ U{2..7}, Cartesian or
     warped with equal probability, seeded random Fourier states, seed =
     problem index), FP32 bulk, Ranocha + LLF, one launch per (p, mesh kind)
-    group per RK stage, each step replayed as a HIP graph, tiles autotuned."""
+    group per RK stage, each step replayed as a HIP graph, tiles autotuned.
+    The groups' launches of a stage run one after another or on forked
+    streams; both are timed and the faster is reported."""
     import numpy as np
     rng = np.random.default_rng(args.batch_seed)
     specs = [(int(rng.integers(4, 25)), int(rng.integers(2, 8)), 0.1 if rng.random() < 0.5 else 0.0)
@@ -358,27 +445,52 @@ def batched(args, esdg, torch, dev, fp64_pid):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     nodes = sum(q.n_dof for q in probs)
-    B = esdg.Batch(probs, graphs=True, concurrent=args.batch_concurrent)
+    # FP32 right-hand sides of a seeded subset of members, computed by the
+    # batch at the initial states, for the oracle comparison (cpu_baseline
+    # leg; at most 6 sampled elements per member)
+    pick = sorted(set(int(i) for i in np.random.default_rng(args.batch_seed + 1).choice(len(probs), 12, replace=False)))
+    outs = [np.empty(q.shape) if i in pick else None for i, q in enumerate(probs)]
+    B = esdg.Batch(probs, graphs=True)
+    B.rhs(outs)
+    checks = {}
+    for i in pick:
+        n, p, warp = specs[i]
+        el = sample_elements(n, 4, 100 + i)[:6]
+        record_check(checks, "member%d_p%d_n%d_%s" % (i, p, n, "warped" if warp else "affine"),
+                     dict(dim=3, p=p, n=(n, n, n), warp=warp, vol_flux="ranocha", surf_flux="llf"),
+                     ("random_fourier", {"seed": i}), {"fp32": outs[i][el]}, elems=el,
+                     sample="%d elements of member %d, initial state" % (len(el), i))
+    del outs
     t0 = time.perf_counter()
     B.autotune(args.batch_tune_reps)
     tune_s = time.perf_counter() - t0
     groups, tiles = B.info()
+    B.close()
     chosen = {}
     for q, (n, p, warp) in zip(probs, specs):
         chosen["p%d_%s" % (p, "warped" if warp else "affine")] = q.tile_variant()
-    B.step(nsteps=args.batch_warmup, cfl=args.batch_cfl)
-    B.sync()
-    torch.cuda.synchronize()
-    B.timing(True)
-    B.timing_read()
-    t0 = time.perf_counter()
-    B.step(nsteps=args.batch_steps, cfl=args.batch_cfl)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms, ev_n = B.timing_read()
-    B.timing(False)
-    B.sync()
-    ms = 1e3 * wall / args.batch_steps
+    # the groups of a stage launched one after another, and on forked
+    # streams (parallel branches of the step's graph): both timed, the faster
+    # reported as the batched figure
+    timing = {}
+    for conc in (False, True):
+        B = esdg.Batch(probs, graphs=True, concurrent=conc)
+        B.step(nsteps=args.batch_warmup, cfl=args.batch_cfl)
+        B.sync()
+        torch.cuda.synchronize()
+        B.timing(True)
+        B.timing_read()
+        t0 = time.perf_counter()
+        B.step(nsteps=args.batch_steps, cfl=args.batch_cfl)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev_ms, ev_n = B.timing_read()
+        B.timing(False)
+        B.sync()
+        B.close()
+        timing[conc] = (1e3 * wall / args.batch_steps, ev_ms / max(ev_n, 1))
+    conc = timing[True][0] < timing[False][0]
+    ms, ev_step_ms = timing[conc]
     pid = ms * 1e6 / (4 * nodes)
     # the same problems stepped one after another (no batch): launch-bound small problems
     seq_ms = None
@@ -399,10 +511,12 @@ def batched(args, esdg, torch, dev, fp64_pid):
         "nodes": nodes,
         "groups": groups,
         "tiles": tiles,
-        "concurrent_groups": bool(args.batch_concurrent),
+        "concurrent_groups": bool(conc),
+        "ms_per_step_sequential_groups": round(timing[False][0], 4),
+        "ms_per_step_concurrent_groups": round(timing[True][0], 4),
         "pid_ns": round(pid, 6),
         "ms_per_step": round(ms, 4),
-        "event_ms_per_step": round(ev_ms / max(ev_n, 1), 4),
+        "event_ms_per_step": round(ev_step_ms, 4),
         "steps": args.batch_steps,
         "vs_fp64_plain_pid": round(fp64_pid / pid, 3),
         "unbatched_ms_per_step": None if seq_ms is None else round(seq_ms, 4),
@@ -410,6 +524,7 @@ def batched(args, esdg, torch, dev, fp64_pid):
         "tile_variant_epb": {k: chosen[k] for k in sorted(chosen)},
         "setup_s": round(setup_s, 1),
         "autotune_s": round(tune_s, 2),
+        "fp32_members_vs_oracle": checks,
     }
 
 
@@ -436,7 +551,8 @@ def serve_run(args, esdg, jobs, arrivals):
     """Run the server over jobs [(kind, n, p, u0)] arriving at the given
     times (s, relative to the start); returns per-job latencies and totals."""
     import numpy as np
-    S = esdg.Server(cfl=args.cfl, steps_per_tick=args.serve_tick, graphs=True)
+    S = esdg.Server(cfl=args.cfl, steps_per_tick=args.serve_tick, graphs=True, max_active=args.serve_max_active,
+                    hbm_budget=int(args.serve_hbm_gib * (1 << 30)))
     t_end = args.serve_t_end
     ids, lat, steps_of, pending = {}, {}, {}, list(range(len(jobs)))
     dw_err = None
@@ -483,6 +599,8 @@ def serve_run(args, esdg, jobs, arrivals):
         "mean_queue_depth": round(float(np.mean(depth)), 2),
         "served_pid_ns": round(elapsed * 1e9 / node_rhs, 6),
         "density_wave_error": dw_err,
+        "max_active_cap": args.serve_max_active,
+        "hbm_budget_gib": args.serve_hbm_gib,
     }
 
 
@@ -509,6 +627,22 @@ def served(args, esdg):
         jobs.append((kind, n, p, u0))
     arr = np.cumsum(gaps) - gaps[0]
     sat = serve_run(args, esdg, jobs[:args.serve_jobs], arr[:args.serve_jobs])
+    # the density-wave job whose FP32 error is reported, served alone in FP64
+    # (same mesh, end time and CFL): the error of the discretisation itself
+    de = sat["density_wave_error"]
+    if de is not None:
+        S = esdg.Server(cfl=args.cfl, steps_per_tick=args.serve_tick, graphs=True)
+        n, p = de["n"], de["p"]
+        jid = S.submit(inputs.density_wave(box_coords(esdg, p, n, -1.0, 1.0)), args.serve_t_end, dim=3, p=p,
+                       n=(n, n, n), lo=(-1.0,) * 3, hi=(1.0,) * 3, precision="fp64")
+        while True:
+            done, _, _ = S.tick()
+            if jid in done:
+                break
+        u64 = S.fetch(jid, want_state=True)
+        S.close()
+        exact = inputs.density_wave(box_coords(esdg, p, n, -1.0, 1.0), t=args.serve_t_end)
+        de["rho_linf_error_fp64_alone"] = float("%.3e" % np.abs(u64[:, 0] - exact[:, 0]).max())
     out = {"workload": "Poisson arrivals %.0f/s (seed %d): density wave or Taylor-Green vortex, n ~ U{8..32}, "
                        "p ~ U{3,4,5}, affine, t_end %.2f, CFL %.2f, FP32 bulk, Ranocha + LLF"
                        % (args.serve_rate, args.serve_seed, args.serve_t_end, args.cfl),
@@ -531,7 +665,7 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=16, help="elements per direction")
     ap.add_argument("--p", type=int, default=3)
     ap.add_argument("--cfl", type=float, default=0.5)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-single-seconds", type=float, default=5.0,
@@ -554,7 +688,7 @@ def main(argv=None):
     ap.add_argument("--batch-warmup", type=int, default=2)
     ap.add_argument("--batch-seq-steps", type=int, default=2)
     ap.add_argument("--batch-tune-reps", type=int, default=5)
-    ap.add_argument("--batch-concurrent", action="store_true",
+    ap.add_argument("--batch-concurrent", action="store_true",  # kept for old command lines: both are timed
                     help="run the groups of a batch step on concurrent streams")
     ap.add_argument("--batch-cfl", type=float, default=0.3,
                     help="CFL number of the batched workload (classical RK4 with this CFL definition is "
@@ -566,6 +700,10 @@ def main(argv=None):
     ap.add_argument("--serve-seed", type=int, default=5)
     ap.add_argument("--serve-t-end", type=float, default=0.5)
     ap.add_argument("--serve-tick", type=int, default=4, help="RK steps per server tick")
+    ap.add_argument("--serve-max-active", type=int, default=8,
+                    help="slots: jobs stepped together (admitted in arrival order as slots and memory free up)")
+    ap.add_argument("--serve-hbm-gib", type=float, default=4.0,
+                    help="HBM budget of the admitted jobs' footprints (GiB)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this many MiB (HBM "
                          "counter calibration under a profiler)")
@@ -733,30 +871,42 @@ def main(argv=None):
         del src, dst
 
     if not args.no_cpu_baseline:
+        # the cpu_baseline leg: the CPU oracle timed on the host's cores (the
+        # paper's protocol, mean and standard deviation of five runs of
+        # equal length from the same initial state), then the oracle side of
+        # every recorded comparison with the GPU results
         import oracle
         m = oracle.Mesh(dim, p, (n, n, n), warp=0.1, vol_flux=args.flux, surf_flux="llf")
-        uc = inputs.random_fourier(m.coords(), 2)
-        steps = 0
+        uc0 = inputs.random_fourier(m.coords(), 2)
+        # steps per run from a first step, so that five runs take about cpu_seconds
         t0 = time.perf_counter()
-        while True:
-            uc, _ = m.rk4(uc, 0.0, 1, cfl=args.cfl)
-            steps += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
-                break
-        el = time.perf_counter() - t0
+        m.rk4(uc0, 0.0, 1, cfl=args.cfl)
+        per_step = time.perf_counter() - t0
+        k = max(1, int(args.cpu_seconds / 5 / per_step))
+        pids = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            m.rk4(uc0, 0.0, k, cfl=args.cfl)
+            pids.append((time.perf_counter() - t0) * 1e9 / (k * 4 * nodes))
         line["cpu_baseline"] = {
-            "value": round(el * 1e9 / (steps * 4 * nodes), 3),
+            "value": round(float(np.mean(pids)), 3),
             "unit": "ns/DOF/RHS",
             "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "%d RK4 steps (CFL %.2f, %d RHS) of the same %d^3 p=%d workload, %.1f s"
-                      % (steps, args.cfl, 4 * steps, n, p, el),
+            "std": round(float(np.std(pids, ddof=1)), 3),
+            "runs": 5,
+            "sample": "5 runs of %d RK4 steps (CFL %.2f, %d RHS each) of the same %d^3 p=%d workload from its "
+                      "initial state, %.1f s in all; value = mean, std over the runs"
+                      % (k, args.cfl, 4 * k, n, p, sum(pids) * k * 4 * nodes * 1e-9),
         }
+        del m
+        run_oracle_checks(oracle, inputs)
         if args.cpu_single_seconds > 0:
             # one host thread: like for like with the paper's serial PIDs
             nt = oracle.num_threads()
             oracle.set_num_threads(1)
             try:
+                m = oracle.Mesh(dim, p, (n, n, n), warp=0.1, vol_flux=args.flux, surf_flux="llf")
                 uc = inputs.random_fourier(m.coords(), 2)
                 steps = 0
                 t0 = time.perf_counter()
