@@ -3,7 +3,7 @@ every test module, the smoke check included).
 
 FP64 right-hand sides, per conserved variable v:
 
-    max_i |gpu_iv - oracle_iv| <= max(REL * max_i |RHS_iv|, SIGMA64 * max_i sigma_iv)
+    max_i |gpu_iv - oracle_iv| <= max(REL * max_i |RHS_iv|, F * max_i sigma_iv)
 
 sigma_i is the oracle's sum of the magnitudes of every term of RHS_i
 (Mesh.rhs_scale, pinned in test_oracle_scale.py).  REL = 1e-12 is the
@@ -20,16 +20,25 @@ independently, and the curl form applies a derivative operator twice, so
 each side's metrics carry rounding of order eps * max|D~|^2 (2e-14 at p = 3,
 3e-13 at p = 7, relative; measured on the CPU in test_geometry_cpu.py).
 The largest measured GPU-oracle difference is 1.8e-14 sigma, on a warped
-p = 7 mesh; 3e-14 gives that a margin of 1.7.  Every FP64 check records
-the R20 figure per variable and the sigma ratio; the session summary prints
-them, so a bar met only through the sigma term is visible.
+p = 7 mesh; 3e-14 gives that a margin of 1.7.  A third source depends on
+the state: the library takes the log means' logarithm differences from
+per-node logarithms (Sec. 7.2 precomputation).  In the logarithmic branch
+the difference is at least ln(1.01/0.99) = 0.02 and each logarithm carries
+up to one unit in the last place, eps |ln a| with eps = 2^-52, so such a
+term's relative error can reach eps (1 + 100 L), L = max |ln rho|, |ln beta|
+over the state (beta = rho/p; pinned on the CPU in test_parity_bar.py).
+The sigma factor is therefore SIGMA64 + 100 eps L when the test passes its
+input state: 3.7e-14 for the random states (L ~ 0.3), 1.8e-13 for the
+density wave, whose beta = rho/20 reaches 1e-3 (L ~ 6.9).  Every FP64 check
+records the R20 figure per variable and the sigma ratio; the session summary
+prints them, so a bar met only through the sigma term is visible.
 
 States after time steps, per variable:
 
-    max_i |gpu_iv - oracle_iv| <= REL * max_i |u_iv| + SIGMA64 * T * max_i sigma_iv(u_0)
+    max_i |gpu_iv - oracle_iv| <= REL * max_i |u_iv| + F * T * max_i sigma_iv(u_0)
 
-with T the integrated time: each step adds dt times the RHS rounding
-(the stage weights sum to one).
+with F the sigma factor above and T the integrated time: each step adds dt
+times the RHS rounding (the stage weights sum to one).
 
 FP32 bulk against the FP64 oracle: max_i |gpu32_iv - oracle64_iv| <=
 SIGMA32 * max_i sigma_iv, SIGMA32 = 1e-6 (about 17 units of FP32 round-off
@@ -42,6 +51,24 @@ import numpy as np
 REL = 1e-12
 SIGMA64 = 3e-14
 SIGMA32 = 1e-6
+EPS64 = 2.0 ** -52
+
+
+def log_range(u, gamma=1.4):
+    """L = max over the nodes of |ln rho| and |ln beta|, beta = rho/p, of a
+    state [elem][var][node] (the magnitude of the per-node logarithms)."""
+    u = np.asarray(u)
+    nv = u.shape[1]
+    dim = nv - 2
+    rho = u[:, 0]
+    kin = sum(u[:, 1 + m] ** 2 for m in range(dim)) / rho
+    p = (gamma - 1.0) * (u[:, dim + 1] - 0.5 * kin)
+    return float(max(np.abs(np.log(rho)).max(), np.abs(np.log(rho / p)).max()))
+
+
+def sigma_factor(u=None):
+    """FP64 sigma factor of the bar: SIGMA64, plus 100 eps L for the state u."""
+    return SIGMA64 + (100.0 * EPS64 * log_range(u) if u is not None else 0.0)
 
 # (label, kind, R20 per variable, max |d| / max sigma, ratio to the bar)
 RECORDS = []
@@ -60,29 +87,32 @@ def r20(gpu, ref):
     return _per_var(gpu, ref, f)
 
 
-def rhs64(gpu, ref, sigma, label=""):
-    """Worst ratio of the FP64 right-hand-side difference to its bar (pass: <= 1)."""
+def rhs64(gpu, ref, sigma, label="", u=None):
+    """Worst ratio of the FP64 right-hand-side difference to its bar (pass:
+    <= 1); u: the input state, for the state-dependent part of the sigma factor."""
     gpu = np.asarray(gpu)
     worst, srat = 0.0, 0.0
+    sf = sigma_factor(u)
     for v in range(ref.shape[1]):
         d = np.abs(gpu[:, v] - ref[:, v]).max()
-        bound = max(REL * np.abs(ref[:, v]).max(), SIGMA64 * sigma[:, v].max())
+        bound = max(REL * np.abs(ref[:, v]).max(), sf * sigma[:, v].max())
         worst = max(worst, d / bound)
         srat = max(srat, d / sigma[:, v].max())
     RECORDS.append((label, "rhs64", r20(gpu, ref), srat, worst))
     return worst
 
 
-def state64(gpu, ref, sigma0=None, t_span=0.0, label=""):
+def state64(gpu, ref, sigma0=None, t_span=0.0, label="", u0=None):
     """Worst ratio of an FP64 state difference after steps to its bar (pass: <= 1)."""
     gpu = np.asarray(gpu)
     worst, srat = 0.0, 0.0
+    sf = sigma_factor(u0)
     for v in range(ref.shape[1]):
         d = np.abs(gpu[:, v] - ref[:, v]).max()
         bound = REL * np.abs(ref[:, v]).max()
         if sigma0 is not None and t_span > 0:
             s = sigma0[:, v].max()
-            bound += SIGMA64 * t_span * s
+            bound += sf * t_span * s
             srat = max(srat, d / (t_span * s))
         worst = max(worst, d / bound)
     RECORDS.append((label, "state64", r20(gpu, ref), srat, worst))

@@ -176,8 +176,8 @@ def test_tile_variants_are_bit_identical(orc, esdg, spec):
             o, sig = m.rhs(u), m.rhs_scale(u)
             label = "pair layout p=7 %s %s warp %.1f" % (prec, vf, warp)
             if prec == "fp64":
-                assert parity.rhs64(d4, o, sig, label=label) <= 1.0
-                assert parity.rhs64(ref, o, sig, label=label + " (node layout)") <= 1.0
+                assert parity.rhs64(d4, o, sig, label=label, u=u) <= 1.0
+                assert parity.rhs64(ref, o, sig, label=label + " (node layout)", u=u) <= 1.0
             else:
                 assert parity.rhs32(d4, o, sig, label=label) <= parity.SIGMA32
         best, us = q.autotune(reps=3)
@@ -228,7 +228,7 @@ def test_batched_fp64_member_vs_oracle(orc, esdg):
     for s, u, d in zip(specs, us, outs):
         m = orc.Mesh(s[0], s[1], s[2], warp=s[3], vol_flux=s[4], surf_flux=s[5])
         ref, sigma = m.rhs(u), m.rhs_scale(u)
-        assert parity.rhs64(d, ref, sigma, label="batched fp64 %dD p=%d %s" % (s[0], s[1], s[2])) <= 1.0
+        assert parity.rhs64(d, ref, sigma, label="batched fp64 %dD p=%d %s" % (s[0], s[1], s[2]), u=u) <= 1.0
 
 
 # ---- serving
@@ -319,7 +319,7 @@ def test_served_results_vs_oracle(orc, esdg):
         sigma0 = m.rhs_scale(u)
         label = "served %s %s %d^3 p=%d, %d steps to t=%.2f" % (prec, kind, n, p, k, t_end)
         if prec == "fp64":
-            assert parity.state64(out[i], uo, sigma0, t_end, label=label) <= 1.0
+            assert parity.state64(out[i], uo, sigma0, t_end, label=label, u0=u) <= 1.0
         else:
             assert parity.state32(out[i], uo, sigma0, t_end, k, label=label) <= 1.0
 

@@ -45,8 +45,8 @@ def pair(orc, esdg, dim, p, n, vol, surf, prec="fp64", lo=None, hi=None):
     return m, g
 
 
-def fp64_parity(d, ref, sigma, label):
-    assert parity.rhs64(d, ref, sigma, label=label) <= 1.0
+def fp64_parity(d, ref, sigma, label, u=None):
+    assert parity.rhs64(d, ref, sigma, label=label, u=u) <= 1.0
 
 
 @pytest.mark.parametrize("dim,p,n,vol,surf", CASES)
@@ -58,7 +58,7 @@ def test_gauss_rhs_parity(orc, esdg, dim, p, n, vol, surf):
     assert np.abs(g.coords() - x).max() < 1e-15
     u = inputs.random_fourier(x, 7, lo=lo, hi=hi)
     g.set_state(u)
-    fp64_parity(g.rhs(), m.rhs(u), m.rhs_scale(u), "gauss %dD p=%d %s %s/%s" % (dim, p, n, vol, surf))
+    fp64_parity(g.rhs(), m.rhs(u), m.rhs_scale(u), "gauss %dD p=%d %s %s/%s" % (dim, p, n, vol, surf), u=u)
 
 
 @pytest.mark.parametrize("dim,p,n,vol,surf", [CASES[1], CASES[5], CASES[7]])
@@ -81,13 +81,13 @@ def test_gauss_steps_parity(orc, esdg):
     uo, _ = m.rk4(u, dt, 10)
     ug = g.get_state()
     sigma0 = m.rhs_scale(u)
-    assert parity.state64(ug, uo, sigma0, 10 * dt, label="gauss 3D p=3 10 steps") <= 1.0
+    assert parity.state64(ug, uo, sigma0, 10 * dt, label="gauss 3D p=3 10 steps", u0=u) <= 1.0
     # CFL steps advance with the Gauss weights' CFL value of the oracle
     g.set_state(u)
     t = g.step(dt=0.0, nsteps=3, cfl=0.4, t=0.0)
     uo, to = m.rk4(u, 0.0, 3, cfl=0.4)
     assert abs(t - to) <= 1e-13 * to
-    assert parity.state64(g.get_state(), uo, sigma0, to, label="gauss 3D p=3 3 CFL steps") <= 1.0
+    assert parity.state64(g.get_state(), uo, sigma0, to, label="gauss 3D p=3 3 CFL steps", u0=u) <= 1.0
 
 
 @pytest.mark.parametrize("dim,p,n", [(2, 3, (3, 3)), (3, 4, (2, 2, 2))])

@@ -30,12 +30,12 @@ def esdg():
 def rhs_parity(gpu, m, u, ref=None, label=""):
     """worst ratio of |gpu - oracle| to the FP64 bar over the variables (must be <= 1)."""
     ref = m.rhs(u) if ref is None else ref
-    return parity.rhs64(gpu, ref, m.rhs_scale(u), label=label)
+    return parity.rhs64(gpu, ref, m.rhs_scale(u), label=label, u=u)
 
 
 def state_parity(gpu, uo, m, u0, t_span, label=""):
     """worst ratio of |gpu - oracle| to the FP64 state bar after steps (must be <= 1)."""
-    return parity.state64(gpu, uo, m.rhs_scale(u0), t_span, label=label)
+    return parity.state64(gpu, uo, m.rhs_scale(u0), t_span, label=label, u0=u0)
 
 
 def make_pair(orc, E, dim, p, n, warp=0.0, vol="ranocha", surf="llf", lo=None, hi=None):

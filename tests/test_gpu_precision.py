@@ -121,7 +121,8 @@ def test_precision_sweep_32cubed(orc, esdg, p):
     el = sampled_elements(n, 40, p)
     ref, sigma = m.rhs_elements(u, el)
     del m
-    assert parity.rhs64(d64[el], ref, sigma, label="32^3 p=%d density wave, %d sampled elements" % (p, len(el))) <= 1.0
+    assert parity.rhs64(d64[el], ref, sigma, label="32^3 p=%d density wave, %d sampled elements" % (p, len(el)),
+                        u=u) <= 1.0
     g32 = esdg.Problem(3, p, (n, n, n), warp=0.1, volume_flux="ranocha", surface_flux="llf", precision="fp32")
     g32.set_state(u)
     d32 = g32.rhs()
