@@ -31,14 +31,38 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
           "-munsafe-fp-atomics"]
 
 
+# the compiler's per-kernel resource report (registers, spills, scratch,
+# LDS, occupancy) of every device function, kept beside the library
+RESOURCES = os.path.join(OUTDIR, "resource_usage.txt")
+
+
 def _compile(src: str, objdir: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(objdir, src + ".o")
-    cmd = [HIPCC] + COMMON + DEVICE + ["-x", "hip", "-c", path, "-o", obj]
+    cmd = [HIPCC] + COMMON + DEVICE + ["-Rpass-analysis=kernel-resource-usage", "-x", "hip", "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed on %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-6000:]))
+    with open(obj + ".resources", "w") as f:
+        f.write(r.stderr)
     return obj
+
+
+def resource_report(objs) -> dict:
+    """{kernel symbol: {field: value}} from the compiler remarks of the objects."""
+    import re
+    out, cur = {}, None
+    for obj in objs:
+        with open(obj + ".resources") as f:
+            for line in f:
+                m = re.search(r"remark: Function Name: (\S+)", line)
+                if m:
+                    cur = out.setdefault(m.group(1), {})
+                    continue
+                m = re.search(r"remark:\s+([A-Za-z][A-Za-z /\[\]]*?): (\S+) \[-Rpass-analysis", line)
+                if m and cur is not None:
+                    cur[m.group(1).strip()] = m.group(2)
+    return out
 
 
 def build(verbose: bool = False) -> str:
@@ -55,6 +79,12 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr[-4000:]))
     os.replace(tmp, LIB)
+    rep = resource_report(objs)
+    with open(RESOURCES + ".tmp", "w") as f:
+        for name in sorted(rep):
+            f.write(name + " " + " ".join("%s=%s" % (k.replace(" ", "_"), v) for k, v in sorted(rep[name].items()))
+                    + "\n")
+    os.replace(RESOURCES + ".tmp", RESOURCES)
     if verbose:
         print("built", LIB)
     return LIB

@@ -1,0 +1,72 @@
+"""Register spills of the stage kernels (host logic, no GPU), from the
+compiler's resource report that build() writes beside the library.
+
+Two wrong-result incidents in the development of the line-layout tiles came
+with spilled scalar operands (D~ held as 128 scalar registers in the FP64
+N = 8 tile; a spilling FP32 N = 8 tile).  Every N = 8 tile has read D~ from
+LDS since.  This test keeps spills from coming back unnoticed:
+  * the node and pair layouts (tile variants 3 and 4) spill nothing;
+  * no LGL tile at N = 8 spills scalar registers;
+  * any other spilling instantiation is listed in tests/data/spill_allowlist.txt
+    with its largest allowed scratch use and spill counts, which must not grow.
+"""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+REPORT = os.path.join(ROOT, "paper_2112_10517_amd", "lib", "resource_usage.txt")
+ALLOW = os.path.join(ROOT, "tests", "data", "spill_allowlist.txt")
+PAT = re.compile(r"stage_kernelILi(\d)ELi(\d)ELi(\d)ELi(\d)E([df])Li(\d+)ELi(\d)ELi(\d)E")
+
+
+@pytest.fixture(scope="module")
+def kernels():
+    if not os.path.exists(REPORT):
+        from paper_2112_10517_amd import build
+        build.build()
+    out = {}
+    with open(REPORT) as f:
+        for line in f:
+            name, *kv = line.split()
+            m = PAT.search(name)
+            if not m:
+                continue
+            d = dict(x.split("=", 1) for x in kv)
+            out[m.groups()] = (int(d["ScratchSize_[bytes/lane]"]), int(d["VGPRs_Spill"]), int(d["SGPRs_Spill"]))
+    assert len(out) > 400, "resource report incomplete: %d stage kernels" % len(out)
+    return out
+
+
+def allowlist():
+    out = {}
+    with open(ALLOW) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            f_ = line.split()
+            out[tuple(f_[:8])] = tuple(int(x) for x in f_[8:11])
+    return out
+
+
+def test_node_and_pair_layouts_do_not_spill(kernels):
+    for key, sp in kernels.items():
+        if key[7] in ("1", "2"):  # LAY_NODES, LAY_PAIRS
+            assert sp == (0, 0, 0), (key, sp)
+
+
+def test_no_scalar_spills_at_degree_seven(kernels):
+    for key, sp in kernels.items():
+        if key[1] == "8" and key[6] == "0":  # N = 8, LGL nodes
+            assert sp[2] == 0, (key, sp)
+
+
+def test_spills_only_where_allowed(kernels):
+    allow = allowlist()
+    for key, sp in kernels.items():
+        if sp == (0, 0, 0):
+            continue
+        assert key in allow, "stage kernel %s spills %s and is not in the allowlist" % (key, sp)
+        lim = allow[key]
+        assert all(a <= b for a, b in zip(sp, lim)), "stage kernel %s spills %s, more than %s" % (key, sp, lim)
