@@ -700,8 +700,8 @@ def main(argv=None):
     ap.add_argument("--serve-seed", type=int, default=5)
     ap.add_argument("--serve-t-end", type=float, default=0.5)
     ap.add_argument("--serve-tick", type=int, default=4, help="RK steps per server tick")
-    ap.add_argument("--serve-max-active", type=int, default=8,
-                    help="slots: jobs stepped together (admitted in arrival order as slots and memory free up)")
+    ap.add_argument("--serve-max-active", type=int, default=0,
+                    help="slots: most jobs stepped together (0: no cap; admission in arrival order as memory frees up)")
     ap.add_argument("--serve-hbm-gib", type=float, default=4.0,
                     help="HBM budget of the admitted jobs' footprints (GiB)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,

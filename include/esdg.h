@@ -248,14 +248,15 @@ esdg_status esdg_timing_reset(esdg_problem *prob);
  * line of an element (one wave per direction; the fewest elements filling
  * whole waves; twice the default); variant 3 gives one lane to each node,
  * which sweeps its partners along every direction (each pair evaluated from
- * both ends, fewer registers per lane); variant 4 (3D, p = 7 only) gives one
- * lane to each node and has the lanes of a line evaluate each pair once,
- * handing the flux to the partner lane.  Variants 0-3 compute bit-identical
+ * both ends, fewer registers per lane); variant 4 (3D) gives one lane to
+ * each node and has the lanes of a line evaluate each pair once, handing
+ * the flux to the partner lane.  Variants 0-3 compute bit-identical
  * results; variant 4 adds each node's terms in another order (the same
  * values up to rounding).  The variant in use is chosen per (dim, p, volume
  * flux, mesh kind, precision, node kind) in a process-wide table; until
- * changed, variant 4 for 3D LGL problems of degree 7, variant 3 for degrees
- * 4-6 (except p = 6 in FP32) and variant 0 otherwise.  2D and Gauss
+ * changed, for 3D LGL problems: variant 0 up to p = 3, variant 3 at p = 4,
+ * at p = 5 variant 4 except on curved FP32 meshes (3), at p = 6 variant 4
+ * except on curved FP64 meshes (3), variant 4 at p = 7.  2D and Gauss
  * problems have variant 0 only.
  *   esdg_autotune: times every variant on the problem's current state (reps
  *     right-hand-side launches each, written to internal scratch; the state

@@ -23,8 +23,8 @@ VolKernel vol_kernel() {
 
 template <int DIM, typename Real, int V, int N>
 VolKernel vol_pick_n(int vf, int mesh) {
-  if constexpr (V == 4 && (DIM != 3 || N != 8)) {
-    return VolKernel{};  // the pair layout exists for 3D N = 8 only
+  if constexpr (V == 4 && DIM != 3) {
+    return VolKernel{};  // the pair layout is 3D only
   } else {
   if (mesh == MESH_AFFINE) {
     if (vf == VF_RANOCHA) return vol_kernel<DIM, Real, N, VF_RANOCHA, MESH_AFFINE, V>();

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace esdg {
 
@@ -384,8 +385,14 @@ struct Tile {
   static constexpr int NFACE = 2 * DIM * NF;      // face nodes per element
   static constexpr int EPB = EPB_;                // elements per block
   static constexpr int LAY = LAY_;
-  // lanes per direction (line layout); the node layout has one group of lanes
-  static constexpr int LANES_DIR = LAY == LAY_LINES ? ((EPB * L + 63) / 64) * 64 : ((EPB * NN + 63) / 64) * 64;
+  // lanes per direction (line layout); the node and pair layouts have one
+  // group of lanes: one per node, and in the pair layout below N = 8 also
+  // enough for the lines of one direction packed floor(64/N) to a wave
+  static constexpr int NODE_LANES = ((EPB * NN + 63) / 64) * 64;
+  static constexpr int LPW = 64 / N;  // pair layout: whole lines per wave
+  static constexpr int PAIR_LANES = ((EPB * L + LPW - 1) / LPW) * 64;
+  static constexpr int LANES_DIR = LAY == LAY_LINES ? ((EPB * L + 63) / 64) * 64
+                                   : (LAY == LAY_PAIRS && PAIR_LANES > NODE_LANES ? PAIR_LANES : NODE_LANES);
   static constexpr int THREADS = LAY == LAY_LINES ? DIM * LANES_DIR : LANES_DIR;
   static constexpr int NPT = (EPB * NN + THREADS - 1) / THREADS;     // nodes per lane
   static constexpr int FPT = (EPB * NFACE + THREADS - 1) / THREADS;  // face nodes per lane
@@ -419,7 +426,10 @@ constexpr int tile_epb(int dim, int N, int np, int rbytes, int variant) {
     return epb0;
   }
   if (variant == 2) return 2 * epb0 * per <= kTileLdsCap ? 2 * epb0 : epb0;
-  if (variant == 4) return 1;  // pair layout: one element of N^3 = 512 nodes
+  // pair layout (3D): at N = 8 one element (a wave per z-plane); below, the
+  // elements that fill whole waves best with one lane per node and with
+  // floor(64/N) lines per wave
+  if (variant == 4) return N >= 6 ? 1 : (N == 5 ? 2 : (N == 4 ? 4 : (N == 3 ? 7 : 16)));
   if (variant == 3) {
     // node layout (LDS: primitives, two direction buffers of halved
     // contravariant vectors, face fluxes): the smallest tile of at least 128
@@ -724,7 +734,6 @@ __device__ __forceinline__ void pair_fluxes(const Real (*sp)[RL], const Real (*s
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int stride = Pow<N, DIR>::value;
   constexpr int H = N / 2;                 // rounds with exchange: 1 .. (N-1)/2; even N adds round H
-  static_assert((N & (N - 1)) == 0, "pair layout: N a power of two (positions wrap with a mask)");
   const int node0 = i - a * stride;        // node at line position 0
   const int lane0 = lane - a * LS;         // its lane
   const Real* rot_own = s_rot + a;         // D~_{a,a+d} at (d-1) N
@@ -733,7 +742,7 @@ __device__ __forceinline__ void pair_fluxes(const Real (*sp)[RL], const Real (*s
   for (int v = 0; v < NV; ++v) A[v] = Real(0);
 #pragma unroll 1
   for (int d = 1; d <= H; ++d) {
-    const int b = (a + d) & (N - 1);
+    const int b = a + d < N ? a + d : a + d - N;
     const int q = lds_node<PAD>(node0 + b * stride);
     Prim<Real> Pk;
     Pk.rho = sp[0][q];
@@ -756,7 +765,7 @@ __device__ __forceinline__ void pair_fluxes(const Real (*sp)[RL], const Real (*s
 #pragma unroll
     for (int v = 0; v < NV; ++v) A[v] = mad(dab, F[v], A[v]);
     if (2 * d < N) {  // uniform across the wave
-      const int src = lane0 + ((a - d) & (N - 1)) * LS;
+      const int src = lane0 + (a >= d ? a - d : a - d + N) * LS;
       const Real dac = rot_in[(d - 1) * N];
 #pragma unroll
       for (int v = 0; v < NV; ++v) A[v] = mad(dac, lane_pull(src, F[v]), A[v]);
@@ -782,19 +791,20 @@ __global__ void __launch_bounds__((Tile<DIM, N, EPB_, LAY>::THREADS))
 __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::value))) stage_kernel(StageArgs<Real> a) {
   static_assert(NODES == NODES_LGL || MESH == MESH_AFFINE, "Gauss collocation is built for affine meshes");
   static_assert(LAY == LAY_LINES || (NODES == NODES_LGL && DIM == 3), "node layout: 3D LGL");
-  static_assert(LAY != LAY_PAIRS || (N == 8 && EPB_ == 1), "pair layout: N = 8, one element (8 waves) per block");
+  static_assert(LAY != LAY_PAIRS || N != 8 || EPB_ == 1, "pair layout at N = 8: one element (8 waves) per block");
   using T = Tile<DIM, N, EPB_, LAY>;
   constexpr bool NODEL = LAY != LAY_LINES;  // one lane per node (node and pair layouts)
   constexpr bool PAIRS = LAY == LAY_PAIRS;
+  constexpr bool PG = PAIRS && N != 8;      // pair layout with lines packed per wave (N < 8)
   constexpr bool CNODE = NODEL && MESH == MESH_CURVED;
   constexpr int NN = T::NN, NF = T::NF, L = T::L, EPB = T::EPB, NV = T::NV, NFACE = T::NFACE;
   constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, LANES_DIR = T::LANES_DIR;
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int NM = DIM * DIM + 1;
-  // node-indexed LDS rows; the pair layout pads each 64-node z-plane by
+  // node-indexed LDS rows; the pair layout at N = 8 pads each 64-node z-plane by
   // LPAD entries, so that its z-lines (one node per plane, read by 8 lanes
   // at once) fall on different banks
-  constexpr int LPAD = PAIRS ? 8 : 0;
+  constexpr int LPAD = PAIRS && N == 8 ? 8 : 0;
   constexpr int NNL = NN + (NN / 64) * LPAD;
   __shared__ Real s_prim[EPB][NP][NNL];     // primitive variables (and logs)
   // volume term, summed over directions in order (line layout): reuses the
@@ -809,6 +819,9 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   // node layout, curved: halved contravariant vectors of two directions
   // (directions 0 and 1, then 2 in the first buffer)
   __shared__ Real s_nrm[CNODE ? EPB : 1][2][DIM][CNODE ? NNL : 1];
+  // pair layout below N = 8: the volume sums of the nodes, merged direction
+  // by direction (the lanes of a direction are not the nodes' own)
+  __shared__ Real s_vol[PG ? EPB : 1][NV][PG ? NN : 1];
 
   const int tid = threadIdx.x;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -1002,7 +1015,68 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   // ---- volume term, node layout: each lane sweeps the partners of its node,
   // direction by direction, and sums the directions in the line layout's order
   Real Sn[NV];
-  if constexpr (NODEL) {
+  if constexpr (PG) {
+    // pair layout, N < 8: lane x of a wave takes position x % N of line
+    // x / N (floor(64/N) whole lines per wave, element-major); per direction
+    // the lines' pairs are evaluated once (pair_fluxes, lanes of a line
+    // consecutive) and the sums are merged per node in LDS: direction 0
+    // writes, 1 adds, 2 adds, the order of the other layouts
+    const int lane = tid & 63, slot = lane / N, pos = lane - slot * N;
+    const int line = (tid >> 6) * T::LPW + slot;
+    const bool lok = slot < T::LPW && line < EPB * N * N && e0 + line / (N * N) < E;
+    const int lel = lok ? line / (N * N) : 0, lix = lok ? line - lel * N * N : 0;  // idle lanes: line 0
+    const int c1 = lix % N, c2 = lix / N;
+    const Real(*sp)[NNL] = s_prim[lel];
+    const Real(*sn0)[NNL] = reinterpret_cast<const Real(*)[NNL]>(&s_nrm[CNODE ? lel : 0][0][0][0]);
+    const Real(*sn1)[NNL] = reinterpret_cast<const Real(*)[NNL]>(&s_nrm[CNODE ? lel : 0][1][0][0]);
+    Real Ad[NV];
+    auto sweep = [&](auto dir_c, const Real(*sn)[NNL], int q, Real scale) {
+      constexpr int DIR = decltype(dir_c)::value;
+      Prim<Real> Pq;
+      Pq.rho = sp[0][q];
+      Pq.v0 = sp[1][q];
+      Pq.v1 = sp[2][q];
+      Pq.v2 = sp[3][q];
+      Pq.p = sp[4][q];
+      Pq.lr = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 2 : 0][q] : Real(0);
+      Pq.b = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 3 : 0][q] : Real(0);
+      Pq.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][q] : Real(0);
+      Real nq[3] = {Real(0), Real(0), Real(0)};
+      if constexpr (CNODE) { nq[0] = sn[0][q]; nq[1] = sn[1][q]; nq[2] = sn[2][q]; }
+      pair_fluxes<DIR, DIM, N, 1, VF, MESH, Real, NNL, 0>(sp, sn, Pq, nq, q, pos, lane, s_dts, scale, a.ops.inv_gm1,
+                                                           Ad);
+    };
+    const int q0 = pos + N * c1 + N * N * c2, q1 = c1 + N * pos + N * N * c2, q2 = c1 + N * c2 + N * N * pos;
+    sweep(std::integral_constant<int, 0>(), sn0, q0, P.scale[0]);
+    if (lok)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_vol[lel][v][q0] = Ad[v];
+    sweep(std::integral_constant<int, 1>(), sn1, q1, P.scale[1]);
+    __syncthreads();  // direction 0's sums written; its vectors (first buffer) read
+    if (lok)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_vol[lel][v][q1] += Ad[v];
+    if constexpr (CNODE) {
+      // direction 2 replaces direction 0 in the first buffer (node owners)
+      if (tid < EPB * NN && e0 + tid / NN < E) {
+        const int el = tid / NN, i = tid - el * NN;
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) s_nrm[el][0][m][i] = Real(0.5) * me_node[(2 * DIM + m) * NN];
+      }
+    }
+    __syncthreads();
+    sweep(std::integral_constant<int, 2>(), sn0, q2, P.scale[2]);
+    if (lok)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s_vol[lel][v][q2] += Ad[v];
+    __syncthreads();
+    if (tid < EPB * NN) {
+      const int el = tid / NN, i = tid - el * NN;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Sn[v] = s_vol[el][v][i];
+    }
+  }
+  if constexpr (NODEL && !PG) {
     const bool ok = tid < EPB * NN && e0 + tid / NN < E;
     const int el = ok ? tid / NN : 0, i = ok ? tid - el * NN : 0;  // idle lanes repeat node 0
     const Real(*sp)[NNL] = s_prim[el];

@@ -19,13 +19,14 @@ void one(const char* prec) {
   constexpr bool NODEL = LAY != LAY_LINES;
   constexpr bool CNODE = NODEL && MESH == MESH_CURVED;
   constexpr long rb = sizeof(Real);
-  constexpr long NNL = T::NN + (LAY == LAY_PAIRS ? (T::NN / 64) * 8 : 0);  // padded node rows (pair layout)
+  constexpr long NNL = T::NN + (LAY == LAY_PAIRS && N == 8 ? (T::NN / 64) * 8 : 0);  // padded rows (pairs, N = 8)
   constexpr long lds = (long)EPB * NP * NNL * rb                         // s_prim (s_acc aliases it)
                        + (long)EPB * T::NV * T::NFACE * rb               // s_face
                        + (long)EPB * 2 * DIM * 4                         // s_nbr
                        + (DtInLds<N, Real>::value ? N * N : 1) * rb      // s_dt
                        + (NODEL ? (LAY == LAY_PAIRS ? N * N : N * (N - 1)) : 1) * rb  // s_dts
-                       + (CNODE ? (long)EPB * 2 * DIM * NNL : 1) * rb;  // s_nrm
+                       + (CNODE ? (long)EPB * 2 * DIM * NNL : 1) * rb     // s_nrm
+                       + (LAY == LAY_PAIRS && N != 8 ? (long)EPB * T::NV * T::NN : 1) * rb;  // s_vol
   std::printf("N %d prec %s vf %d mesh %d variant %d epb %d epb0 %d threads %d npt %d fpt %d nn %d lds %ld waves %d\n", N,
               prec, VF, MESH, V, EPB, TileShape<DIM, N>::EPB0, T::THREADS, T::NPT, T::FPT, T::NN, lds,
               StageWaves<DIM, N, MESH, Real, EPB, LAY>::value);
@@ -37,7 +38,7 @@ void variants(const char* prec) {
   one<N, Real, VF, MESH, 1>(prec);
   one<N, Real, VF, MESH, 2>(prec);
   one<N, Real, VF, MESH, 3>(prec);
-  if constexpr (N == 8) one<N, Real, VF, MESH, 4>(prec);  // pair layout: N = 8 only
+  one<N, Real, VF, MESH, 4>(prec);
 }
 
 template <int N>

@@ -153,9 +153,9 @@ BITWISE_VARIANTS = (0, 1, 2, 3)
 @pytest.mark.parametrize("spec", CASES_VARIANT)
 def test_tile_variants_are_bit_identical(orc, esdg, spec):
     """The line layouts (0-2) and the node layout (3) give the same bits.
-    The pair layout (4, degree 7 only) sums each node's terms in another
-    order: it meets the parity bar against the oracle and differs from the
-    others by rounding only.  The autotuner picks one of them."""
+    The pair layout (4) sums each node's terms in another order: it meets
+    the parity bar against the oracle and differs from the others by
+    rounding only.  The autotuner picks one of them."""
     q, u = make(esdg, spec, 5)
     ref = None
     shapes = set()
@@ -169,12 +169,12 @@ def test_tile_variants_are_bit_identical(orc, esdg, spec):
                 ref = d
             assert np.array_equal(d, ref), "variant %d" % v
         dim, p, n, warp, vf, sf, prec = spec
-        if dim == 3 and p == 7:
+        if dim == 3:
             q.set_tile_variant(4)
             d4 = q.rhs()
             m = orc.Mesh(dim, p, n, warp=warp, vol_flux=vf, surf_flux=sf)
             o, sig = m.rhs(u), m.rhs_scale(u)
-            label = "pair layout p=7 %s %s warp %.1f" % (prec, vf, warp)
+            label = "pair layout p=%d %s %s warp %.1f" % (p, prec, vf, warp)
             if prec == "fp64":
                 assert parity.rhs64(d4, o, sig, label=label, u=u) <= 1.0
                 assert parity.rhs64(ref, o, sig, label=label + " (node layout)", u=u) <= 1.0

@@ -31,9 +31,8 @@ def shapes(tmp_path_factory):
     for line in out.stdout.splitlines():
         f = line.split()
         rows.append({f[i]: (f[i + 1] if f[i] == "prec" else int(f[i + 1])) for i in range(0, len(f), 2)})
-    # variants 0-3 for N = 2..8, and the pair layout (4) for N = 8; four
-    # (precision, flux, mesh) combinations each
-    assert len(rows) == (7 * 4 + 1) * 4
+    # variants 0-4 for N = 2..8; four (precision, flux, mesh) combinations each
+    assert len(rows) == 7 * 5 * 4
     return rows
 
 
@@ -55,14 +54,21 @@ def test_node_layout_one_node_per_lane(shapes):
 
 
 def test_pair_layout_shape(shapes):
-    """The pair layout: one element of 512 nodes, one lane per node, so each
-    64-lane wave is one z-plane (the x- and y-lines stay inside a wave), and
-    two workgroups (four waves per SIMD) fit a CU's LDS."""
+    """The pair layout: one lane per node; at N = 8 one element of 512 nodes,
+    so each 64-lane wave is one z-plane (the x- and y-lines stay inside a
+    wave); below N = 8 also enough lanes for the lines of one direction,
+    floor(64/N) whole lines per wave.  Two workgroups fit a CU's LDS."""
     pairs = [s for s in shapes if s["variant"] == 4]
-    assert len(pairs) == 4
+    assert len(pairs) == 7 * 4
     for s in pairs:
-        assert s["nn"] == 512 and s["epb"] == 1 and s["threads"] == 512 and s["npt"] == 1, s
-        assert 2 * s["lds"] <= 160 * 1024 and s["waves"] == 4, s
+        N = round(s["nn"] ** (1.0 / 3.0))
+        assert s["npt"] == 1 and s["threads"] >= s["epb"] * s["nn"], s
+        lines = s["epb"] * N * N
+        assert s["threads"] // 64 * (64 // N) >= lines, s
+        assert s["threads"] - s["epb"] * s["nn"] < 128, s  # at most one wave more than the nodes need
+        assert 2 * s["lds"] <= 160 * 1024, s
+        if N == 8:
+            assert s["epb"] == 1 and s["threads"] == 512 and s["waves"] == 4, s
 
 
 def test_lds_within_budget(shapes):
