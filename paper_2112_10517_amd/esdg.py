@@ -58,6 +58,7 @@ class JobDesc(C.Structure):
 
 
 _lib = None
+_lib_path = None
 _lock = threading.Lock()
 
 _vp, _dp, _i32, _i64, _d = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64, C.c_double
@@ -121,11 +122,16 @@ EXPORTS = list(SIGNATURES)
 
 
 def load_library(path: str | None = None):
-    """Load libesdg.so (raises if it has not been built)."""
-    global _lib
+    """Load libesdg.so (raises if it has not been built).  With a path, that
+    build becomes the library every later call of this module uses (Problem,
+    Batch, Server); a second, different path raises, since two builds of the
+    library in one process would share no state."""
+    global _lib, _lib_path
     with _lock:
-        if _lib is not None and path is None:
+        if _lib is not None and (path is None or os.path.realpath(path) == _lib_path):
             return _lib
+        if _lib is not None:
+            raise RuntimeError("libesdg is already loaded from %s; cannot load %s as well" % (_lib_path, path))
         p = path or LIB_PATH
         if not os.path.exists(p):
             raise RuntimeError("HIP library %s is not built: run __graft_entry__.build() or "
@@ -142,8 +148,7 @@ def load_library(path: str | None = None):
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
-        if path is None:
-            _lib = lib
+        _lib, _lib_path = lib, os.path.realpath(p)
         return lib
 
 

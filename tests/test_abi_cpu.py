@@ -135,3 +135,13 @@ def test_server_admission_rule(E):
     sizes = [E.footprint(3, p, (n, n, n), precision="fp32") for n, p in ((8, 3), (32, 5), (16, 4), (8, 5))]
     budget = sizes[0] + sizes[1] + sizes[2] // 2
     assert plan(sizes, used=0, budget=budget) == 2
+
+
+def test_load_library_path_selects_the_build(E):
+    """A library loaded by path is the one the module's classes use; a
+    second, different build in the same process is refused."""
+    lib = E.load_library(E.LIB_PATH)
+    assert E.load_library() is lib
+    assert E.load_library(E.LIB_PATH) is lib
+    with pytest.raises(RuntimeError):
+        E.load_library(os.path.join(os.path.dirname(E.LIB_PATH), "another", "libesdg.so"))
