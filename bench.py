@@ -276,12 +276,68 @@ def variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n):
     ctx["workload"] = ("isentropic vortex (strength 20) on [-5,5]^3, 8^3 elements (32,768 nodes), p = 3, FP64, "
                        "RK4 steps at CFL %.2f, 100 steps in one call" % args.cfl)
     out["paper_setup_vortex_8cubed"] = ctx
+    out["faces_once_fp64"] = faces_once_ab(args, esdg, torch, u0_dev, dim, p, n)
     out["gauss_vs_lgl_affine_fp64"] = {
         "lgl_pid_ns": round(res["lgl"] * 1e6 / (4 * nodes), 6),
         "gauss_pid_ns": round(res["gauss"] * 1e6 / (4 * nodes), 6),
         "gauss_over_lgl": round(res["gauss"] / res["lgl"], 3),
         "gauss_projection_share": round(pr_ms / (pr_ms + st_ms), 3),
     }
+    return out
+
+
+def faces_once_ab(args, esdg, torch, u0_dev, dim, p, n):
+    """Surface fluxes evaluated once per face (a face kernel before every
+    stage, Sec. 2.4) against the default fused evaluation (each element
+    evaluates its own faces inside the stage kernel), FP64, warped box: the
+    headline workload and 32^3 at p = 7.  Steps are timed alternately (best of
+    three); the two modes must give bitwise the same states."""
+    out = {}
+    for pp, nn, steps, warmup in ((p, n, max(10, args.steps // 2), 100), (7, 32, 10, 5)):
+        probs = []
+        for mode in (esdg.FACES_FUSED, esdg.FACES_ONCE):
+            g = esdg.Problem(dim, pp, (nn,) * 3, warp=0.1, volume_flux=args.flux, surface_flux="llf")
+            g.set_face_flux_mode(mode)
+            probs.append(g)
+        if pp == p and nn == n:
+            u = u0_dev
+        else:
+            u = random_fourier_device(torch.from_numpy(probs[0].coords()).to(u0_dev.device), 2, torch)
+        best = [float("inf"), float("inf")]
+        for _ in range(3):
+            for k, g in enumerate(probs):
+                g.set_state(u)
+                best[k] = min(best[k], time_steps(g, steps, warmup, args.cfl, torch))
+        states = []
+        for g in probs:
+            g.set_state(u)
+            g.step(dt=0.0, nsteps=3, cfl=args.cfl)
+            st = torch.empty(g.shape, dtype=torch.float64, device=u0_dev.device)
+            g.get_state(st)
+            states.append(st)
+        torch.cuda.synchronize()
+        once = probs[1]
+        once.timing(True)
+        once.timing_reset()
+        once.step(dt=0.0, nsteps=2, cfl=args.cfl)
+        fc_ms, _ = once.timing_read(esdg.KERNEL_FACE)
+        st_ms, _ = once.timing_read(esdg.KERNEL_STAGE)
+        once.timing(False)
+        nodes = probs[0].n_dof
+        out["%dcubed_p%d" % (nn, pp)] = {
+            "fused_ms_per_step": round(best[0], 6),
+            "once_ms_per_step": round(best[1], 6),
+            "once_over_fused": round(best[1] / best[0], 4),
+            "fused_pid_ns": round(best[0] * 1e6 / (4 * nodes), 6),
+            "once_pid_ns": round(best[1] * 1e6 / (4 * nodes), 6),
+            "once_face_kernel_us": round(1e3 * fc_ms / 8, 3),
+            "once_stage_kernel_us": round(1e3 * st_ms / 8, 3),
+            "bitwise_equal_after_3_steps": bool(torch.equal(states[0], states[1])),
+        }
+        for g in probs:
+            g.sync()
+            g.close()
+        del states
     return out
 
 
@@ -682,6 +738,8 @@ def main(argv=None):
                     help="steps with per-kernel hipEvent timing (after the timed region)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FP32-bulk and Shima variants of the workload")
+    ap.add_argument("--faces-ab-only", action="store_true",
+                    help="of the variants, run only the once-per-face vs fused surface-flux comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched FP32 workload")
     ap.add_argument("--batch-problems", type=int, default=256)
     ap.add_argument("--batch-seed", type=int, default=4)
@@ -853,7 +911,9 @@ def main(argv=None):
         "cpu_baseline": None,
     }
 
-    if not args.no_variants:
+    if args.faces_ab_only and not args.no_variants:
+        line["variants"] = {"faces_once_fp64": faces_once_ab(args, esdg, torch, u0_dev, dim, p, n)}
+    elif not args.no_variants:
         line["variants"] = variants(args, esdg, inputs, u0_dev, x, nodes, dim, p, n)
 
     if not args.no_sweep:

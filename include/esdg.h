@@ -236,8 +236,14 @@ esdg_status esdg_sync(esdg_problem *prob);
  * esdg_timing_read returns the summed duration (ms) and launch count since
  * the last reset, synchronising the stream.  STAGE is the fused
  * right-hand-side / RK-stage kernel, REDUCE the FP64 reductions, PROJECT the
- * entropy projection of Gauss problems. */
-typedef enum { ESDG_KERNEL_STAGE = 1, ESDG_KERNEL_REDUCE = 2, ESDG_KERNEL_PROJECT = 3 } esdg_kernel;
+ * entropy projection of Gauss problems, FACE the face kernel of the
+ * once-per-face mode (esdg_set_face_flux_mode). */
+typedef enum {
+  ESDG_KERNEL_STAGE = 1,
+  ESDG_KERNEL_REDUCE = 2,
+  ESDG_KERNEL_PROJECT = 3,
+  ESDG_KERNEL_FACE = 4
+} esdg_kernel;
 esdg_status esdg_timing_enable(esdg_problem *prob, int32_t enable);
 esdg_status esdg_timing_read(esdg_problem *prob, int32_t kernel, double *total_ms,
                              int64_t *launches);
@@ -270,6 +276,34 @@ esdg_status esdg_timing_reset(esdg_problem *prob);
 esdg_status esdg_autotune(esdg_problem *prob, int32_t reps, int32_t *best, double *us_per_variant);
 esdg_status esdg_set_tile_variant(esdg_problem *prob, int32_t variant);
 esdg_status esdg_get_tile_variant(const esdg_problem *prob, int32_t *variant, int32_t *elems_per_block);
+
+/* Where the surface fluxes are evaluated (Sec. 2.4 names evaluating them
+ * once per face and handing them to both elements as the usual efficient
+ * organisation on CPUs).
+ *   ESDG_FACES_FUSED (default): the stage kernel evaluates f* at every face
+ *     node of each element it updates, so every face is evaluated by both of
+ *     its elements, from the same inputs in the same order (the left
+ *     element's trace, the right one's, the left element's + face normal).
+ *   ESDG_FACES_ONCE: before every stage launch a face kernel evaluates f* once
+ *     per face node, for the + face of every element in every direction, into
+ *     a device buffer of E dim nv nf reals of the problem's precision (E nf
+ *     faces per direction), and the stage kernel reads it.  Bitwise the same
+ *     results as the fused mode; on MI355X slower at every measured size (the
+ *     face pass moves more data than the flux arithmetic it saves).
+ * 3D LGL problems only, with a stage kernel built for it: tile variants 3
+ * and 4, and the line tiles (0-2) up to p = 4 (in the line tiles above and
+ * in 2D the extra branch costs registers).  ESDG_EINVAL for an unknown mode,
+ * a 2D or Legendre-Gauss problem (which evaluates face fluxes per element),
+ * a tile variant in use without that build; in ONCE mode
+ * esdg_set_tile_variant refuses such a variant, esdg_autotune skips it, and
+ * a step finding one in the process-wide table fails.  Switching to ONCE
+ * allocates the buffer (ESDG_ENOMEM if that fails); switching back
+ * synchronises the handle's stream and frees it.  Batches evaluate faces
+ * fused: esdg_batch_create rejects a member in ONCE mode (ESDG_EINVAL). */
+#define ESDG_FACES_FUSED 0
+#define ESDG_FACES_ONCE 1
+esdg_status esdg_set_face_flux_mode(esdg_problem *prob, int32_t mode);
+esdg_status esdg_get_face_flux_mode(const esdg_problem *prob, int32_t *mode);
 
 /* Device memory (bytes) esdg_init_mesh would allocate for the descriptor:
  * five state-sized arrays (state, two stage states, accumulator, RHS), an

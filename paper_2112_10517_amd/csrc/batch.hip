@@ -300,6 +300,8 @@ static esdg_status batch_create_impl(esdg_problem* const* probs, int32_t count, 
     for (int j = 0; j < i; ++j)
       if (probs[j] == probs[i]) return report(nullptr, ESDG_EINVAL, "a problem appears twice in the batch");
     if (probs[i]->device != probs[0]->device) return report(nullptr, ESDG_EINVAL, "batch members on different devices");
+    if (probs[i]->FSTAR)
+      return report(nullptr, ESDG_EINVAL, "batch member %d is in once-per-face mode (batches evaluate faces fused)", i);
     if (t_end && std::isnan(t_end[i])) return report(nullptr, ESDG_EINVAL, "NaN end time");
   }
   esdg_batch* b = new esdg_batch();

@@ -253,7 +253,7 @@ esdg_status set_time(esdg_problem* P, double t) {
 
 void free_buffers(esdg_problem* P) {
   void* bufs[] = {P->U,     P->Y,       P->Y2,   P->R,   P->DU,   P->STAGE64, P->METRIC,
-                  P->NFACE, P->PARTIAL, P->SCAL, P->LAM, P->DESC, P->FACEB};
+                  P->NFACE, P->PARTIAL, P->SCAL, P->LAM, P->DESC, P->FACEB, P->FSTAR};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (P->FLAG_H) (void)hipHostFree(P->FLAG_H);
@@ -774,9 +774,41 @@ esdg_status esdg_get_tile_variant(const esdg_problem* P, int32_t* variant, int32
 
 esdg_status esdg_set_tile_variant(esdg_problem* P, int32_t variant) {
   if (!P) return fail(nullptr, ESDG_EINVAL, "NULL problem handle");
-  if (!kernel_of_variant(P, variant).fn)
-    return fail(P, ESDG_EINVAL, "tile variant %d does not exist for dim=%d p=%d", variant, P->dim, P->p);
+  const VolKernel k = kernel_of_variant(P, variant);
+  if (!k.fn) return fail(P, ESDG_EINVAL, "tile variant %d does not exist for dim=%d p=%d", variant, P->dim, P->p);
+  if (P->FSTAR && !k.faces_once)
+    return fail(P, ESDG_EINVAL, "tile variant %d has no once-per-face build at p=%d", variant, P->p);
   set_tile_variant(P, variant);
+  return ESDG_OK;
+}
+
+esdg_status esdg_set_face_flux_mode(esdg_problem* P, int32_t mode) {
+  ESDG_TRY(check_handle(P, false));
+  if (mode != ESDG_FACES_FUSED && mode != ESDG_FACES_ONCE) return fail(P, ESDG_EINVAL, "unknown face flux mode %d", mode);
+  if (mode == ESDG_FACES_ONCE && P->nodes != NODES_LGL)
+    return fail(P, ESDG_EINVAL, "Legendre-Gauss problems evaluate their face fluxes per element only");
+  if (mode == ESDG_FACES_ONCE && (P->dim != 3 || !pick_stage_kernel(P).faces_once))
+    return fail(P, ESDG_EINVAL,
+                "once-per-face mode needs a 3D problem whose tile variant is a node or pair tile, or a line tile "
+                "up to p = 4 (dim=%d p=%d)", P->dim, P->p);
+  if (mode == ESDG_FACES_ONCE && !P->FSTAR) {
+    const size_t bytes = (size_t)P->E * P->dim * P->nv * P->nf * P->rsize;
+    if (hipMalloc(&P->FSTAR, bytes) != hipSuccess) {
+      P->FSTAR = nullptr;
+      return fail(P, ESDG_ENOMEM, "device allocation of %zu bytes for the face fluxes failed", bytes);
+    }
+  }
+  if (mode == ESDG_FACES_FUSED && P->FSTAR) {
+    ESDG_HIP(&P->err, hipStreamSynchronize(P->stream));  // no launch in flight still reads it
+    ESDG_HIP(&P->err, hipFree(P->FSTAR));
+    P->FSTAR = nullptr;
+  }
+  return ESDG_OK;
+}
+
+esdg_status esdg_get_face_flux_mode(const esdg_problem* P, int32_t* mode) {
+  if (!P || !mode) return fail(nullptr, ESDG_EINVAL, "NULL argument");
+  *mode = P->FSTAR ? ESDG_FACES_ONCE : ESDG_FACES_FUSED;
   return ESDG_OK;
 }
 
@@ -801,7 +833,7 @@ esdg_status esdg_autotune(esdg_problem* P, int32_t reps, int32_t* best, double* 
     epb[v] = 0;
     fns[v] = nullptr;
     const VolKernel k = kernel_of_variant(P, v);
-    if (!k.fn) continue;
+    if (!k.fn || (P->FSTAR && !k.faces_once)) continue;
     epb[v] = k.epb;
     fns[v] = k.fn;
     int same = -1;

@@ -9,6 +9,7 @@ struct VolKernel {
   const void* fn = nullptr;  // __global__ stage_kernel<...>
   int epb = 0;               // elements per workgroup
   int threads = 0;           // lanes per workgroup
+  bool faces_once = false;   // reads f* written by the face kernel when given one
 };
 
 // number of tile variants of the 3D stage kernel (2D has one)
@@ -34,5 +35,7 @@ VolKernel gauss_kernel_f32(int dim, int N, int vf, bool project);
 const void* reduce_partial_for(int prec, int dim, int mesh, int op);
 const void* reduce_final_for(int op);
 const void* convert_kernel_for(int to_fp64);  // elementwise precision casts
+// face fluxes once per face (LGL): face_kernel<dim, N, mesh, precision>
+const void* face_kernel_for(int prec, int dim, int N, int mesh);
 
 }  // namespace esdg

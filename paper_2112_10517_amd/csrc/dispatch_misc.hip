@@ -34,7 +34,32 @@ __global__ void __launch_bounds__(256) to_fp32_kernel(const double* src, float* 
   if (i < n) dst[i] = (float)src[i];
 }
 
+template <int DIM, typename Real, int MESH>
+const void* face_pick(int N) {
+  switch (N) {
+    case 2: return (const void*)&face_kernel<DIM, 2, MESH, Real>;
+    case 3: return (const void*)&face_kernel<DIM, 3, MESH, Real>;
+    case 4: return (const void*)&face_kernel<DIM, 4, MESH, Real>;
+    case 5: return (const void*)&face_kernel<DIM, 5, MESH, Real>;
+    case 6: return (const void*)&face_kernel<DIM, 6, MESH, Real>;
+    case 7: return (const void*)&face_kernel<DIM, 7, MESH, Real>;
+    case 8: return (const void*)&face_kernel<DIM, 8, MESH, Real>;
+  }
+  return nullptr;
+}
+
+template <typename Real>
+const void* face_pick_dim(int dim, int N, int mesh) {
+  if (dim == 2) return mesh == MESH_AFFINE ? face_pick<2, Real, MESH_AFFINE>(N) : face_pick<2, Real, MESH_CURVED>(N);
+  if (dim == 3) return mesh == MESH_AFFINE ? face_pick<3, Real, MESH_AFFINE>(N) : face_pick<3, Real, MESH_CURVED>(N);
+  return nullptr;
+}
+
 }  // namespace
+
+const void* face_kernel_for(int prec, int dim, int N, int mesh) {
+  return prec == PREC_FP32 ? face_pick_dim<float>(dim, N, mesh) : face_pick_dim<double>(dim, N, mesh);
+}
 
 VolKernel stage_kernel_for(int prec, int dim, int N, int vf, int mesh, int variant) {
   if (variant < 0 || variant >= kTileVariants) return VolKernel{};

@@ -18,6 +18,7 @@ VolKernel vol_kernel() {
   k.fn = (const void*)&stage_kernel<DIM, N, VF, MESH, Real, EPB, NODES_LGL, LAY>;
   k.epb = T::EPB;
   k.threads = T::THREADS;
+  k.faces_once = FacesOnce<DIM, N, LAY>::value;
   return k;
 }
 

@@ -86,6 +86,10 @@ struct StageArgs {
   const ProbDesc<Real>* probs;  // problems of the launch, ordered by tile0
   const int* tile_prob;         // problem index of every tile; NULL for a single problem
   Real* out_ext;        // RHS mode of a single problem: output; else NULL (buf[out_idx])
+  // face fluxes evaluated once per face: f* of every element's + faces,
+  // [E][DIM][NV][NF], written by face_kernel before the stage launch; NULL:
+  // every element evaluates the fluxes of its own faces (both sides of a face)
+  Real* fstar;
   int in_idx, out_idx;  // ProbDesc::buf indices of the stage input and output
   int mode;             // StageMode
   int surf;             // SurfFlux
@@ -777,6 +781,13 @@ __device__ __forceinline__ void pair_fluxes(const Real (*sp)[RL], const Real (*s
   }
 }
 
+// Stage kernels built with the once-per-face reading of f* (a runtime
+// branch): 3D tiles whose register allocation it leaves unchanged, i.e. the
+// node and pair layouts and the line layout up to N = 5 (in the line tiles
+// above, and in 2D, it adds spills).
+template <int DIM, int N, int LAY>
+struct FacesOnce { static constexpr bool value = DIM == 3 && (LAY != LAY_LINES || N <= 5); };
+
 // Waves per SIMD the register allocation of a tile must allow: the tile's
 // default, except for the FP64 node tiles up to N = 5, whose prologue (two or
 // three face nodes per lane) spills at four waves (three measured 3% faster
@@ -797,6 +808,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   constexpr bool PAIRS = LAY == LAY_PAIRS;
   constexpr bool PG = PAIRS && N != 8;      // pair layout with lines packed per wave (N < 8)
   constexpr bool CNODE = NODEL && MESH == MESH_CURVED;
+  constexpr bool FONCE = FacesOnce<DIM, N, LAY>::value && NODES == NODES_LGL;  // may read f* (a.fstar)
   constexpr int NN = T::NN, NF = T::NF, L = T::L, EPB = T::EPB, NV = T::NV, NFACE = T::NFACE;
   constexpr int THREADS = T::THREADS, NPT = T::NPT, FPT = T::FPT, LANES_DIR = T::LANES_DIR;
   constexpr int NP = PrimCount<VF, DIM>::value;
@@ -946,6 +958,12 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     const int e = ok ? e0 + el : 0;
     const int en = ok ? s_nbr[el][fc] : 0;
     const int eL = side ? e : en, eR = side ? en : e;
+    if (FONCE && a.fstar) {  // the face's flux, from the + face of its left element
+      const auto fs = as_global((const Real*)a.fstar) + ((size_t)eL * DIM + dir) * (NV * NF) + f;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) tL[r][v] = fs[v * NF];
+      continue;
+    }
     const int qL = face_node<N>(dir, f, N - 1), qR = face_node<N>(dir, f, 0);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -1006,7 +1024,12 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     const int el = t / NFACE, rr = t - el * NFACE;
     if (!(t < EPB * NFACE && e0 + el < E)) continue;
     Real F[NV];
-    surface_flux<DIM>(a.surf, tL[r], tR[r], tn[r][0], tn[r][1], tn[r][2], a.ops.gamma, a.ops.inv_gm1, F);
+    if (FONCE && a.fstar) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) F[v] = tL[r][v];
+    } else {
+      surface_flux<DIM>(a.surf, tL[r], tR[r], tn[r][0], tn[r][1], tn[r][2], a.ops.gamma, a.ops.inv_gm1, F);
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) s_face[el][v][rr] = F[v];
   }
@@ -1536,6 +1559,62 @@ __global__ void __launch_bounds__(kRedThreads) reduce_final_kernel(const double*
       lam_slot[threadIdx.x] = threadIdx.x == 0 ? (unsigned long long)__double_as_longlong(sh[0]) : 0ull;
     __syncthreads();
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// face fluxes once per face (LGL, one problem): the organisation Sec. 2.4
+// names as the usual efficient one on CPUs (and Sec. 6 reports for the LGL
+// solver it times); an option beside the fused default, which evaluates each
+// face from both of its elements inside the stage kernel
+// ---------------------------------------------------------------------------
+
+constexpr int kFaceThreads = 256;
+
+// One lane per node of an element's + face in each direction: f*(u_L, u_R, n)
+// with u_L the element's trace at position N-1, u_R the + neighbour's at 0
+// and n the normal of the element's + face, the inputs (and so the bits) the
+// stage kernel uses when it evaluates the face from either side.  Writes
+// a.fstar[e][dir][v][f] from the stage input buf[in_idx] of a.probs[0].
+template <int DIM, int N, int MESH, typename Real>
+__global__ void __launch_bounds__(kFaceThreads) face_kernel(StageArgs<Real> a) {
+  constexpr int NV = DIM + 2, NF = Pow<N, DIM - 1>::value, NN = Pow<N, DIM>::value;
+  const ProbDesc<Real>& P = a.probs[0];
+  const int E = P.E, n0 = P.n0, n1 = P.n1, n2 = P.n2;
+  const int64_t g = (int64_t)blockIdx.x * kFaceThreads + threadIdx.x;
+  if (g >= (int64_t)E * DIM * NF) return;
+  const int e = (int)(g / (DIM * NF));
+  const int rem = (int)(g - (int64_t)e * (DIM * NF));
+  const int dir = rem / NF, f = rem - dir * NF;
+  const int ex = e % n0, ey = (e / n0) % n1, ez = e / (n0 * n1);
+  int en;
+  if (dir == 0) en = (ex == n0 - 1 ? 0 : ex + 1) + n0 * (ey + n1 * ez);
+  else if (dir == 1) en = ex + n0 * ((ey == n1 - 1 ? 0 : ey + 1) + n1 * ez);
+  else en = ex + n0 * (ey + n1 * (ez == n2 - 1 ? 0 : ez + 1));
+  const auto uin = as_global((const Real*)P.buf[a.in_idx]);
+  const int qL = face_node<N>(dir, f, N - 1), qR = face_node<N>(dir, f, 0);
+  Real tL[NV], tR[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    tL[v] = uin[(size_t)e * (NV * NN) + v * NN + qL];
+    tR[v] = uin[(size_t)en * (NV * NN) + v * NN + qR];
+  }
+  Real nx, ny, nz;
+  if (MESH == MESH_CURVED) {
+    const auto nf = as_global(P.nface) + ((size_t)dir * E + e) * (DIM * NF) + f;
+    nx = nf[0];
+    ny = DIM > 1 ? nf[NF] : Real(0);
+    nz = DIM > 2 ? nf[2 * NF] : Real(0);
+  } else {
+    nx = dir == 0 ? Real(1) : Real(0);
+    ny = dir == 1 ? Real(1) : Real(0);
+    nz = dir == 2 ? Real(1) : Real(0);
+  }
+  Real F[NV];
+  surface_flux<DIM>(a.surf, tL, tR, nx, ny, nz, a.ops.gamma, a.ops.inv_gm1, F);
+  const auto out = as_global(a.fstar) + ((size_t)e * DIM + dir) * (NV * NF) + f;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) out[v * NF] = F[v];
 }
 
 }  // namespace esdg

@@ -54,6 +54,7 @@ struct esdg_problem {
   int* FLAG = nullptr;                // non-physical flag: device address of FLAG_H
   int* FLAG_H = nullptr;              // the flag in host-mapped pinned memory (kernels store 1)
   void* FACEB = nullptr;              // Gauss: entropy-projected face states
+  void* FSTAR = nullptr;              // ESDG_FACES_ONCE: f* of every element's + faces [E][dim][nv][nf]
   int red_blocks = 1;
   int64_t red_per_block = 256;
 
@@ -192,7 +193,9 @@ VolKernel pick_projection_kernel(const esdg_problem* P);
 // descriptors (device memory) are `probs`, all with the parameters of `rep`:
 // right-hand side of buf[in_idx] (surface and volume terms) and, for the RK
 // modes, the stage update into buf[out_idx] / R; RHS mode writes buf[out_idx]
-// or out_ext.  Gauss problems first run the entropy projection of buf[in_idx].
+// or out_ext.  Gauss problems first run the entropy projection of buf[in_idx];
+// a problem in once-per-face mode stepped by itself first runs the face
+// kernel on buf[in_idx] (batch launches evaluate faces in the stage kernel).
 
 template <typename Real>
 esdg_status run_stage_on(const esdg_problem* rep, const Launcher& L, const VolKernel& k, const void* probs,
@@ -220,6 +223,19 @@ esdg_status run_stage_on(const esdg_problem* rep, const Launcher& L, const VolKe
   a.ops = stage_ops<Real>(rep);
   void* args[] = {&a};
   if (proj.fn) ESDG_TRY(launch_kernel(L, ESDG_KERNEL_PROJECT, proj.fn, dim3((unsigned)tiles), dim3(proj.threads), args));
+  if (rep->FSTAR && probs == rep->DESC) {
+    // once-per-face mode of a problem stepped by itself: the face kernel
+    // writes f* of every face, the stage kernel reads it
+    const void* fk = face_kernel_for(rep->prec, rep->dim, rep->N, rep->mesh);
+    if (!fk || !k.faces_once)
+      return report(L.err, ESDG_EINVAL,
+                    "once-per-face mode needs a 3D node or pair tile, or a line tile up to p = 4 (dim=%d p=%d)",
+                    rep->dim, rep->p);
+    a.fstar = (Real*)rep->FSTAR;
+    const int64_t lanes = rep->E * rep->dim * rep->nf;
+    ESDG_TRY(launch_kernel(L, ESDG_KERNEL_FACE, fk, dim3((unsigned)((lanes + kFaceThreads - 1) / kFaceThreads)),
+                           dim3(kFaceThreads), args));
+  }
   return launch_kernel(L, ESDG_KERNEL_STAGE, k.fn, dim3((unsigned)tiles), dim3(k.threads), args);
 }
 

@@ -21,7 +21,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONPHYSICAL, ESTATE = 0, -1, -2, -3, -4, -5
 FLUX = {"ranocha": 0, "shima": 1, "llf": 2, "central": 3}
 PRECISION = {"fp64": 0, "fp32": 1}
 HOST, DEVICE = 0, 1
-KERNEL_STAGE, KERNEL_REDUCE, KERNEL_PROJECT = 1, 2, 3
+KERNEL_STAGE, KERNEL_REDUCE, KERNEL_PROJECT, KERNEL_FACE = 1, 2, 3, 4
+FACES_FUSED, FACES_ONCE = 0, 1
 NODES = {"lgl": 0, "gauss": 1}
 INTEGRATORS = {"rk4": 0, "ck45": 1}
 PMAX = 7
@@ -92,6 +93,8 @@ SIGNATURES = {
     "esdg_autotune": (_st, [_vp, _i32, _pi32, _dp]),
     "esdg_set_tile_variant": (_st, [_vp, _i32]),
     "esdg_get_tile_variant": (_st, [_vp, _pi32, _pi32]),
+    "esdg_set_face_flux_mode": (_st, [_vp, _i32]),
+    "esdg_get_face_flux_mode": (_st, [_vp, _pi32]),
     "esdg_footprint": (_st, [C.POINTER(MeshDesc), _pi64]),
     "esdg_batch_create": (_st, [C.POINTER(_vp), _i32, _dp, _vp, _i32, C.POINTER(_vp)]),
     "esdg_batch_destroy": (None, [_vp]),
@@ -360,6 +363,15 @@ class Problem:
 
     def set_tile_variant(self, variant: int):
         self._call(self._lib.esdg_set_tile_variant, int(variant))
+
+    def face_flux_mode(self) -> int:
+        """FACES_FUSED (each element evaluates its faces) or FACES_ONCE."""
+        m = C.c_int32()
+        self._call(self._lib.esdg_get_face_flux_mode, C.byref(m))
+        return m.value
+
+    def set_face_flux_mode(self, mode: int):
+        self._call(self._lib.esdg_set_face_flux_mode, int(mode))
 
     def entropy_rate(self) -> float:
         r = C.c_double()
