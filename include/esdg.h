@@ -356,7 +356,13 @@ esdg_status esdg_batch_times(esdg_batch *batch, double *t);
  * so a further call reports the next one), else *bad = -1. */
 esdg_status esdg_batch_sync(esdg_batch *batch, int32_t *bad);
 
-/* Tune the tile variant of every group on its largest member (esdg_autotune). */
+/* Tune the tile variant of every 3D LGL group on its own launch: each variant
+ * is timed over reps right-hand-side launches of all the group's tiles (after
+ * one untimed launch; written to the members' internal RHS buffers, states
+ * unchanged) and the fastest is stored in the process-wide table for the
+ * group's parameters, as esdg_set_tile_variant does.  Synchronises the batch's
+ * and the members' streams; ESDG_EINVAL for reps < 1, ESDG_ESTATE if a member
+ * has no state. */
 esdg_status esdg_batch_autotune(esdg_batch *batch, int32_t reps);
 
 /* Groups (launches per stage) and total element tiles of the batch. */

@@ -288,6 +288,57 @@ void destroy_batch(esdg_batch* b) {
 
 }  // namespace
 
+namespace {
+
+// Time every tile variant of group g on its own launch shape: reps
+// right-hand-side launches over all of its members' tiles (into the members'
+// RHS buffers; states unchanged) after one untimed launch; us per launch in
+// us[v], -1 for a variant without a kernel.
+template <typename Real>
+esdg_status time_group_variants(esdg_batch* b, const BatchGroup& g, int32_t reps, hipEvent_t e0, hipEvent_t e1,
+                                double* us) {
+  const Launcher L = launcher_on(b, b->stream);
+  const void* fns[ESDG_TILE_VARIANTS];
+  for (int v = 0; v < ESDG_TILE_VARIANTS; ++v) {
+    us[v] = -1.0;
+    fns[v] = nullptr;
+    BatchGroup t;
+    t.rep = g.rep;
+    t.members = g.members;
+    t.integrator = g.integrator;
+    t.k = kernel_of_variant(g.rep, v);
+    if (!t.k.fn) continue;
+    fns[v] = t.k.fn;
+    int same = -1;
+    for (int w = 0; w < v; ++w)
+      if (fns[w] == t.k.fn) same = w;
+    if (same >= 0) {
+      us[v] = us[same];
+      continue;
+    }
+    esdg_status st = upload_group<Real>(b, t);
+    auto one = [&]() {
+      return run_stage_on<Real>(t.rep, L, t.k, t.desc, t.tile_prob, t.tiles, BUF_U, BUF_DU, nullptr, MODE_RHS, 0, 0,
+                                StepCtl());
+    };
+    if (st == ESDG_OK) st = one();
+    if (st == ESDG_OK && hipEventRecord(e0, b->stream) != hipSuccess) st = bfail(b, ESDG_EDEVICE, "hipEventRecord failed");
+    for (int r = 0; r < reps && st == ESDG_OK; ++r) st = one();
+    float ms = 0.0f;
+    if (st == ESDG_OK && (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = bfail(b, ESDG_EDEVICE, "event timing failed");
+    (void)hipStreamSynchronize(b->stream);
+    if (t.desc) (void)hipFree(t.desc);
+    if (t.tile_prob) (void)hipFree(t.tile_prob);
+    ESDG_TRY(st);
+    us[v] = 1000.0 * ms / reps;
+  }
+  return ESDG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 static esdg_status batch_create_impl(esdg_problem* const* probs, int32_t count, const double* t_end, void* stream,
@@ -502,14 +553,32 @@ static esdg_status batch_sync_impl(esdg_batch* b, int32_t* bad) {
 
 static esdg_status batch_autotune_impl(esdg_batch* b, int32_t reps) {
   ESDG_TRY(check_batch(b));
+  if (reps < 1) return bfail(b, ESDG_EINVAL, "reps must be >= 1");
   ESDG_HIP(&b->err, hipStreamSynchronize(b->stream));
-  for (auto& g : b->groups) {
-    esdg_problem* big = b->probs[g.members[0]];
-    for (int i : g.members)
-      if (b->probs[i]->E > big->E) big = b->probs[i];
-    esdg_status st = esdg_autotune(big, reps, nullptr, nullptr);
-    if (st != ESDG_OK) return report(&b->err, st, "autotune: %s", big->err.c_str());
+  // the members' own streams may still hold work on their states
+  for (hipStream_t s : b->mstreams) ESDG_HIP(&b->err, hipStreamSynchronize(s));
+  ESDG_TRY(refresh_groups(b));
+  hipEvent_t e0, e1;
+  ESDG_HIP(&b->err, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(b, ESDG_EDEVICE, "hipEventCreate failed");
   }
+  esdg_status st = ESDG_OK;
+  for (size_t gi = 0; gi < b->groups.size() && st == ESDG_OK; ++gi) {
+    const BatchGroup& g = b->groups[gi];
+    if (g.rep->nodes != NODES_LGL || g.rep->dim != 3) continue;  // one variant only
+    double us[ESDG_TILE_VARIANTS];
+    st = g.rep->prec == PREC_FP32 ? time_group_variants<float>(b, g, reps, e0, e1, us)
+                                  : time_group_variants<double>(b, g, reps, e0, e1, us);
+    int pick = -1;
+    for (int v = 0; v < ESDG_TILE_VARIANTS && st == ESDG_OK; ++v)
+      if (us[v] >= 0.0 && (pick < 0 || us[v] < us[pick])) pick = v;
+    if (st == ESDG_OK && pick >= 0) set_tile_variant(g.rep, pick);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ESDG_TRY(st);
   return refresh_groups(b);
 }
 

@@ -112,7 +112,7 @@ int tile_table_version() {
   return g_tune_version;
 }
 
-static void set_tile_variant(const esdg_problem* P, int v) {
+void set_tile_variant(const esdg_problem* P, int v) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   auto it = g_tune.find(tune_key(P));
   const int cur = it == g_tune.end() ? default_tile_variant(P) : it->second;
@@ -121,7 +121,7 @@ static void set_tile_variant(const esdg_problem* P, int v) {
 }
 
 // stage kernel of tile variant v for P (Gauss collocation has variant 0 only)
-static VolKernel kernel_of_variant(const esdg_problem* P, int v) {
+VolKernel kernel_of_variant(const esdg_problem* P, int v) {
   if (P->nodes == NODES_GAUSS) return v == 0 ? gauss_kernel_for(P->prec, P->dim, P->N, P->vf, false) : VolKernel{};
   return stage_kernel_for(P->prec, P->dim, P->N, P->vf, P->mesh, v);
 }

@@ -140,6 +140,10 @@ inline void flag_clear(esdg_problem* P) { __atomic_store_n(P->FLAG_H, 0, __ATOMI
 int tile_variant_of(const esdg_problem* P);
 int tile_table_version();
 VolKernel pick_stage_kernel(const esdg_problem* P);
+// stage kernel of tile variant v for P's parameters (fn == NULL if none) and
+// the table update that makes v the variant in use for them
+VolKernel kernel_of_variant(const esdg_problem* P, int v);
+void set_tile_variant(const esdg_problem* P, int v);
 
 template <typename Real>
 StageOps<Real> stage_ops(const esdg_problem* P) {

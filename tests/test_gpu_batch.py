@@ -73,6 +73,34 @@ def test_batch_cfl_steps_match_alone(esdg, graphs, concurrent):
         assert q.get_time() == t
 
 
+def test_batch_autotune_times_whole_groups(esdg):
+    # the batch autotuner times every variant of a group on the group's own
+    # launch (RHS mode into the members' RHS buffers): states unchanged, a
+    # variant stored for each 3D group, and the tuned batch still steps
+    # exactly as its members alone (which use the same process-wide table)
+    batched, alone = pair(esdg, MIX, seed0=70)
+    before = [r.tile_variant()[0] for r in alone]
+    try:
+        u0 = [q.get_state() for q in batched]
+        with esdg.Batch(batched, graphs=True) as B:
+            B.autotune(reps=2)
+            for q, u in zip(batched, u0):
+                assert np.array_equal(q.get_state(), u)
+            for q in batched:
+                v, epb = q.tile_variant()
+                assert 0 <= v < esdg.TILE_VARIANTS and epb >= 1
+            B.step(nsteps=2, cfl=0.4)
+            tb = B.times()
+            B.sync()
+        for q, r, t in zip(batched, alone, tb):
+            tr = r.step(nsteps=2, cfl=0.4, t=0.0)
+            assert t == tr
+            assert np.array_equal(q.get_state(), r.get_state())
+    finally:
+        for r, v in zip(alone, before):
+            r.set_tile_variant(v)
+
+
 def test_batch_fixed_dt_and_rhs_match_alone(esdg):
     batched, alone = pair(esdg, MIX, seed0=30)
     with esdg.Batch(batched, graphs=True) as B:
