@@ -101,10 +101,18 @@ def recorded_valu(kernel_source: str, profile: str, launch_s: float):
     try:
         flops = 64.0 * (rec["fp64_add"] + rec["fp64_mul"] + rec["fp64_trans"] + 2.0 * rec["fp64_fma"])
         tflops = flops / launch_s / 1e12
-        return {"fp64_tflops": round(tflops, 3), "fp64_frac_of_peak": round(tflops / FP64_VALU_PEAK_TF, 4),
-                "valu_issue_frac": round(rec["valu_insts"] * 4.0 / (1024 * 2.4e9 * launch_s), 4)}
+        out = {"fp64_tflops": round(tflops, 3), "fp64_frac_of_peak": round(tflops / FP64_VALU_PEAK_TF, 4),
+               "valu_issue_frac": round(rec["valu_insts"] * 4.0 / (1024 * 2.4e9 * launch_s), 4)}
     except KeyError:
         return None
+    # the combined roofline: hardware flops per measured HBM byte, and the
+    # achieved rate over min(FP64 peak, intensity x HBM peak)
+    traffic = recorded_traffic(kernel_source, profile)
+    if traffic:
+        oi = flops / traffic
+        out["flop_per_hbm_byte"] = round(oi, 3)
+        out["roofline_frac"] = round(tflops / min(FP64_VALU_PEAK_TF, oi * HBM_PEAK_GBS / 1e3), 4)
+    return out
 
 
 def time_steps(g, steps, warmup, cfl, torch):
