@@ -256,13 +256,15 @@ esdg_status esdg_timing_reset(esdg_problem *prob);
  * which sweeps its partners along every direction (each pair evaluated from
  * both ends, fewer registers per lane); variant 4 (3D) gives one lane to
  * each node and has the lanes of a line evaluate each pair once, handing
- * the flux to the partner lane.  Variants 0-3 compute bit-identical
+ * the flux to the partner lane (one wave per z-plane of the element at
+ * p = 7, and at p = 6 for FP64 curved meshes; lines of one direction packed
+ * into waves otherwise).  Variants 0-3 compute bit-identical
  * results; variant 4 adds each node's terms in another order (the same
  * values up to rounding).  The variant in use is chosen per (dim, p, volume
  * flux, mesh kind, precision, node kind) in a process-wide table; until
  * changed, for 3D LGL problems: variant 0 up to p = 3, variant 3 at p = 4,
- * at p = 5 variant 4 except on curved FP32 meshes (3), at p = 6 variant 4
- * except on curved FP64 meshes (3), variant 4 at p = 7.  2D and Gauss
+ * at p = 5 variant 4 except on curved FP32 meshes (3), variant 4 at p = 6
+ * and 7.  2D and Gauss
  * problems have variant 0 only.
  *   esdg_autotune: times every variant on the problem's current state (reps
  *     right-hand-side launches each, written to internal scratch; the state

@@ -87,18 +87,14 @@ std::tuple<int, int, int, int, int, int> tune_key(const esdg_problem* P) {
 // nodes): the line layout (0) up to p = 3, where the kernel is bound by
 // memory and the line's single pass over its pairs wins; the node layout (3)
 // at p = 4; at p = 5 the pair layout (4) in FP64 and on affine FP32 meshes,
-// the node layout on curved FP32 meshes; at p = 6 the pair layout except on
-// curved FP64 meshes (its 64 KB of LDS per 6-wave workgroup leaves 3 waves
-// per SIMD); the pair layout at p = 7.
+// the node layout on curved FP32 meshes; the pair layout at p = 6 (on curved
+// FP64 meshes its one-z-plane-per-wave form) and p = 7.
 static int default_tile_variant(const esdg_problem* P) {
   if (P->dim != 3 || P->nodes != NODES_LGL || P->N < 5) return 0;
   const bool fp64 = P->prec == PREC_FP64, curved = P->mesh == MESH_CURVED;
-  switch (P->N) {
-    case 5: return 3;
-    case 6: return (!fp64 && curved) ? 3 : 4;
-    case 7: return (fp64 && curved) ? 3 : 4;
-    default: return 4;
-  }
+  if (P->N == 5) return 3;
+  if (P->N == 6) return (!fp64 && curved) ? 3 : 4;
+  return 4;
 }
 
 int tile_variant_of(const esdg_problem* P) {

@@ -11,8 +11,10 @@ namespace esdg {
 template <int DIM, typename Real, int N, int VF, int MESH, int V>
 VolKernel vol_kernel() {
   constexpr int EPB = tile_epb(DIM, N, PrimCount<VF, DIM>::value, (int)sizeof(Real), V);
-  // variant 3: node layout; variant 4: pair layout
-  constexpr int LAY = V == 4 ? LAY_PAIRS : (V == 3 ? LAY_NODES : LAY_LINES);
+  // variant 3: node layout; variant 4: pair layout (at N = 7 one z-plane per
+  // wave for the FP64 curved tiles, where it measured fastest)
+  constexpr int LAY = V == 4 ? ((N == 7 && sizeof(Real) == 8 && MESH == MESH_CURVED) ? LAY_PLANES : LAY_PAIRS)
+                             : (V == 3 ? LAY_NODES : LAY_LINES);
   using T = Tile<DIM, N, EPB, LAY>;
   VolKernel k;
   k.fn = (const void*)&stage_kernel<DIM, N, VF, MESH, Real, EPB, NODES_LGL, LAY>;

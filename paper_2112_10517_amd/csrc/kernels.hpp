@@ -382,12 +382,17 @@ struct TileShape {
 // evaluated from both ends (twice the flux evaluations), in exchange for a
 // register footprint of one node instead of one line, hence more waves per
 // SIMD at high degree.  Both layouts add the same terms in the same order, so
-// they give the same bits.  LAY_PAIRS (3D, N = 8): one lane per node as in
+// they give the same bits.  LAY_PAIRS (3D): one lane per node as in
 // LAY_NODES, but the lanes of a line evaluate each pair once in a rotation
 // schedule and hand the flux to the partner lane with a cross-lane permute
 // (pair_fluxes); half the flux evaluations of LAY_NODES, the same values up to
-// the order of the sums.
-enum Layout { LAY_LINES = 0, LAY_NODES = 1, LAY_PAIRS = 2 };
+// the order of the sums.  At N = 8 a wave holds one z-plane of the element,
+// so the x- and y-lines lie in one wave; below, floor(64/N) whole lines of
+// one direction are packed per wave and the directions' sums merged in LDS.
+// LAY_PLANES (N = 7): the pair layout with one z-plane (49 nodes) per wave
+// and lanes 49 .. 63 idle, no merge buffer; faster than packed lines for the
+// FP64 curved tiles only.
+enum Layout { LAY_LINES = 0, LAY_NODES = 1, LAY_PAIRS = 2, LAY_PLANES = 3 };
 
 template <int DIM, int N, int EPB_ = TileShape<DIM, N>::EPB0, int LAY_ = LAY_LINES>
 struct Tile {
@@ -403,8 +408,12 @@ struct Tile {
   static constexpr int NODE_LANES = ((EPB * NN + 63) / 64) * 64;
   static constexpr int LPW = 64 / N;  // pair layout: whole lines per wave
   static constexpr int PAIR_LANES = ((EPB * L + LPW - 1) / LPW) * 64;
+  // pair layout, one element per workgroup, wave w = z-plane w (lanes
+  // 0 .. N^2-1 of each wave hold the plane's nodes)
+  static constexpr bool PLANE = DIM == 3 && ((LAY == LAY_PAIRS && N == 8) || (LAY == LAY_PLANES && N * N <= 64));
   static constexpr int LANES_DIR = LAY == LAY_LINES ? ((EPB * L + 63) / 64) * 64
-                                   : (LAY == LAY_PAIRS && PAIR_LANES > NODE_LANES ? PAIR_LANES : NODE_LANES);
+                                   : (PLANE ? N * 64
+                                            : (LAY != LAY_NODES && PAIR_LANES > NODE_LANES ? PAIR_LANES : NODE_LANES));
   static constexpr int THREADS = LAY == LAY_LINES ? DIM * LANES_DIR : LANES_DIR;
   static constexpr int NPT = (EPB * NN + THREADS - 1) / THREADS;     // nodes per lane
   static constexpr int FPT = (EPB * NFACE + THREADS - 1) / THREADS;  // face nodes per lane
@@ -414,7 +423,19 @@ struct Tile {
   // node layout: two workgroups of up to 8 waves per CU
   static constexpr int WPE = LAY != LAY_LINES ? 4 : (N <= 4 ? 3 : (N <= 6 ? 2 : 1));
   static_assert(LAY == LAY_LINES || NPT == 1, "node layout: one node per lane");
+  static_assert(!PLANE || EPB == 1, "plane layout: one element (N waves) per block");
+  static_assert(LAY != LAY_PLANES || PLANE, "LAY_PLANES: 3D, N = 7 or 8");
 };
+
+// Lane slot q (= tid + r THREADS) holds node q of the tile (element-major),
+// except in the plane layout: there lane l of wave w holds node l + N^2 w of
+// the one element and the lanes l >= N^2 hold none (false).
+template <int N>
+__device__ __forceinline__ bool plane_node(int q, int& i) {
+  const int w = q >> 6, l = q & 63;
+  i = l + w * (N * N);
+  return l < N * N && w < N;
+}
 
 // LDS budget of one workgroup of a tile variant (two workgroups fit a CU)
 constexpr int kTileLdsCap = 80 * 1024;
@@ -816,11 +837,14 @@ __global__ void __launch_bounds__((Tile<DIM, N, EPB_, LAY>::THREADS))
 __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::value))) stage_kernel(StageArgs<Real> a) {
   static_assert(NODES == NODES_LGL || MESH == MESH_AFFINE, "Gauss collocation is built for affine meshes");
   static_assert(LAY == LAY_LINES || (NODES == NODES_LGL && DIM == 3), "node layout: 3D LGL");
-  static_assert(LAY != LAY_PAIRS || N != 8 || EPB_ == 1, "pair layout at N = 8: one element (8 waves) per block");
+  static_assert(!Tile<DIM, N, EPB_, LAY>::PLANE || EPB_ == 1, "plane layouts: one element per block");
   using T = Tile<DIM, N, EPB_, LAY>;
   constexpr bool NODEL = LAY != LAY_LINES;  // one lane per node (node and pair layouts)
-  constexpr bool PAIRS = LAY == LAY_PAIRS;
-  constexpr bool PG = PAIRS && N != 8;      // pair layout with lines packed per wave (N < 8)
+  constexpr bool PAIRS = LAY == LAY_PAIRS || LAY == LAY_PLANES;
+  constexpr bool PG = PAIRS && !T::PLANE;   // pair layout with lines packed per wave (N < 7)
+  // plane layout with idle lanes (N = 7: lane l of wave w holds node l + N^2 w);
+  // at N = 8 the plane layout's node of lane slot q is q itself
+  constexpr bool PMAP = T::PLANE && N * N < 64;
   constexpr bool CNODE = NODEL && MESH == MESH_CURVED;
   constexpr bool FONCE = FacesOnce<DIM, N, LAY>::value && NODES == NODES_LGL;  // may read f* (a.fstar)
   constexpr int NN = T::NN, NF = T::NF, L = T::L, EPB = T::EPB, NV = T::NV, NFACE = T::NFACE;
@@ -903,8 +927,12 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
-    const int el = q / NN, i = q - el * NN;
-    const bool ok = q < EPB * NN && e0 + el < E;
+    int el = q / NN, i = q - el * NN;
+    bool ok = q < EPB * NN && e0 + el < E;
+    if constexpr (PMAP) {
+      el = 0;
+      ok = plane_node<N>(q, i) && e0 < E;
+    }
     const size_t o = ok ? (size_t)(e0 + el) * (NV * NN) + i : 0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) uo[r][v] = uin[o + (size_t)v * NN];
@@ -915,9 +943,13 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   // node layout, curved: the node's halved contravariant vectors of
   // directions 0 and 1 (direction 2 is loaded after their sweeps)
   Real hm[2][DIM];
-  const auto me_node = metric + ((CNODE && tid < EPB * NN && e0 + tid / NN < E)
-                                     ? (size_t)(e0 + tid / NN) * (NM * NN) + (tid - (tid / NN) * NN)
-                                     : 0);
+  int pnode = 0;
+  const bool pok = PMAP && plane_node<N>(tid, pnode) && e0 < E;  // plane layout: the lane's node
+  const auto me_node =
+      metric + (PMAP ? (CNODE && pok ? (size_t)e0 * (NM * NN) + pnode : 0)
+                         : ((CNODE && tid < EPB * NN && e0 + tid / NN < E)
+                                ? (size_t)(e0 + tid / NN) * (NM * NN) + (tid - (tid / NN) * NN)
+                                : 0));
   if constexpr (CNODE) {
 #pragma unroll
     for (int n = 0; n < 2; ++n)
@@ -1000,8 +1032,13 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
-    const int el = q / NN, i = q - el * NN;
-    if (!(q < EPB * NN && e0 + el < E)) continue;
+    int el = q / NN, i = q - el * NN;
+    if constexpr (PMAP) {
+      el = 0;
+      if (!(plane_node<N>(q, i) && e0 < E)) continue;
+    } else if (!(q < EPB * NN && e0 + el < E)) {
+      continue;
+    }
     const Real rho = uo[r][0];
     const Real inv_rho = dev_rcp(rho);
     const Real m0 = uo[r][1];
@@ -1114,8 +1151,9 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     }
   }
   if constexpr (NODEL && !PG) {
-    const bool ok = tid < EPB * NN && e0 + tid / NN < E;
-    const int el = ok ? tid / NN : 0, i = ok ? tid - el * NN : 0;  // idle lanes repeat node 0
+    const bool ok = PMAP ? pok : (tid < EPB * NN && e0 + tid / NN < E);
+    const int el = (ok && !PMAP) ? tid / NN : 0;
+    const int i = ok ? (PMAP ? pnode : tid - el * NN) : 0;  // idle lanes repeat node 0
     const Real(*sp)[NNL] = s_prim[el];
     const int ix = i % N, iy = (i / N) % N, iz = i / (N * N);
     const int li = lds_node<LPAD>(i);
@@ -1136,8 +1174,8 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     const Real(*sn1)[NNL] = reinterpret_cast<const Real(*)[NNL]>(&s_nrm[CNODE ? el : 0][1][0][0]);
     if constexpr (CNODE) { no[0] = sn0[0][li]; no[1] = sn0[1][li]; no[2] = sn0[2][li]; }
     const int lane = tid & 63;
-    // pair layout: a wave is one z-plane of the element, so the lines of
-    // directions 0 and 1 lie in one wave (lane strides 1 and N)
+    // pair layout: a wave is one z-plane of the element (lanes x + N y), so
+    // the lines of directions 0 and 1 lie in one wave (lane strides 1 and N)
     if constexpr (PAIRS)
       pair_fluxes<0, DIM, N, 1, VF, MESH, Real, NNL, LPAD>(sp, sn0, Po, no, i, ix, lane, s_dts, P.scale[0],
                                                            a.ops.inv_gm1, Ad);
@@ -1158,7 +1196,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
 #pragma unroll
       for (int m = 0; m < DIM; ++m) no[m] = Real(0.5) * me_node[(2 * DIM + m) * NN];
       __syncthreads();
-      if (tid < EPB * NN && e0 + tid / NN < E)
+      if (ok)
 #pragma unroll
         for (int m = 0; m < DIM; ++m) s_nrm[el][0][m][li] = no[m];
       __syncthreads();
@@ -1167,8 +1205,11 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
       // direction 2: the lanes are re-mapped so that a wave holds one
       // y-plane (lane x + N z of wave y takes node (x, y, z)), which puts
       // each z-line in one wave at lane stride N; the sums go back to the
-      // nodes' own lanes through the primitives' LDS
-      const int i2 = (lane % N) + N * (tid / 64) + N * N * (lane / N);
+      // nodes' own lanes through the primitives' LDS.  Lanes N^2 .. 63 (N = 7)
+      // take node (x, y, 0) and store nothing.
+      const bool ok2 = lane < N * N;
+      const int z2 = ok2 ? lane / N : 0;
+      const int i2 = (lane % N) + N * (tid / 64) + N * N * z2;
       const int l2 = lds_node<LPAD>(i2);
       Prim<Real> P2;
       P2.rho = sp[0][l2];
@@ -1181,11 +1222,12 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
       P2.lb = NP > DIM + 2 ? sp[(NP > DIM + 2) ? DIM + 4 : 0][l2] : Real(0);
       Real n2[3] = {Real(0), Real(0), Real(0)};
       if constexpr (CNODE) { n2[0] = sn0[0][l2]; n2[1] = sn0[1][l2]; n2[2] = sn0[2][l2]; }
-      pair_fluxes<2, DIM, N, N, VF, MESH, Real, NNL, LPAD>(sp, sn0, P2, n2, i2, lane / N, lane, s_dts, P.scale[2],
+      pair_fluxes<2, DIM, N, N, VF, MESH, Real, NNL, LPAD>(sp, sn0, P2, n2, i2, z2, lane, s_dts, P.scale[2],
                                                            a.ops.inv_gm1, Ad);
       __syncthreads();  // every lane has read the primitives
+      if (ok2)
 #pragma unroll
-      for (int v = 0; v < NV; ++v) s_acc[0][v][l2] = Ad[v];
+        for (int v = 0; v < NV; ++v) s_acc[0][v][l2] = Ad[v];
       __syncthreads();
 #pragma unroll
       for (int v = 0; v < NV; ++v) Sn[v] += s_acc[0][v][li];
@@ -1215,8 +1257,12 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
-    const int el = q / NN, i = q - el * NN;
-    const bool ok = q < EPB * NN && e0 + el < E;
+    int el = q / NN, i = q - el * NN;
+    bool ok = q < EPB * NN && e0 + el < E;
+    if constexpr (PMAP) {
+      el = 0;
+      ok = plane_node<N>(q, i) && e0 < E;
+    }
     const size_t o = ok ? (size_t)(e0 + el) * (NV * NN) + i : 0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -1267,8 +1313,13 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
     const int q = tid + r * THREADS;
-    const int el = q / NN, i = q - el * NN;
-    if (!(q < EPB * NN && e0 + el < E)) continue;
+    int el = q / NN, i = q - el * NN;
+    if constexpr (PMAP) {
+      el = 0;
+      if (!(plane_node<N>(q, i) && e0 < E)) continue;
+    } else if (!(q < EPB * NN && e0 + el < E)) {
+      continue;
+    }
     const int ee = e0 + el;
     const int ix = i % N;
     const int iy = DIM > 1 ? (i / N) % N : 0;

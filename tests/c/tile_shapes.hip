@@ -14,7 +14,8 @@ void one(const char* prec) {
   constexpr int DIM = 3;
   constexpr int NP = PrimCount<VF, DIM>::value;
   constexpr int EPB = tile_epb(DIM, N, NP, (int)sizeof(Real), V);
-  constexpr int LAY = V == 4 ? LAY_PAIRS : (V == 3 ? LAY_NODES : LAY_LINES);
+  constexpr int LAY = V == 4 ? ((N == 7 && sizeof(Real) == 8 && MESH == MESH_CURVED) ? LAY_PLANES : LAY_PAIRS)
+                             : (V == 3 ? LAY_NODES : LAY_LINES);
   using T = Tile<DIM, N, EPB, LAY>;
   constexpr bool NODEL = LAY != LAY_LINES;
   constexpr bool CNODE = NODEL && MESH == MESH_CURVED;
@@ -24,9 +25,9 @@ void one(const char* prec) {
                        + (long)EPB * T::NV * T::NFACE * rb               // s_face
                        + (long)EPB * 2 * DIM * 4                         // s_nbr
                        + (DtInLds<N, Real>::value ? N * N : 1) * rb      // s_dt
-                       + (NODEL ? (LAY == LAY_PAIRS ? N * N : N * (N - 1)) : 1) * rb  // s_dts
+                       + (NODEL ? (LAY != LAY_NODES ? N * N : N * (N - 1)) : 1) * rb  // s_dts
                        + (CNODE ? (long)EPB * 2 * DIM * NNL : 1) * rb     // s_nrm
-                       + (LAY == LAY_PAIRS && N != 8 ? (long)EPB * T::NV * T::NN : 1) * rb;  // s_vol
+                       + (LAY == LAY_PAIRS && !T::PLANE ? (long)EPB * T::NV * T::NN : 1) * rb;  // s_vol (packed lines)
   std::printf("N %d prec %s vf %d mesh %d variant %d epb %d epb0 %d threads %d npt %d fpt %d nn %d lds %ld waves %d\n", N,
               prec, VF, MESH, V, EPB, TileShape<DIM, N>::EPB0, T::THREADS, T::NPT, T::FPT, T::NN, lds,
               StageWaves<DIM, N, MESH, Real, EPB, LAY>::value);

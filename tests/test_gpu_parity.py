@@ -291,7 +291,7 @@ def test_isentropic_vortex_parity(orc, esdg, dim, warp, vol):
 
 @pytest.mark.parametrize("p,n,warp,variant", [(5, (2, 3, 2), 0.1, 3), (7, (2, 2, 2), 0.0, 3), (7, (2, 1, 2), 0.1, 3),
                                                (7, (2, 2, 2), 0.0, 4), (7, (2, 1, 2), 0.1, 4), (4, (3, 2, 1), 0.1, 4),
-                                               (5, (1, 2, 3), 0.1, 4), (6, (2, 1, 2), 0.0, 4)])
+                                               (5, (1, 2, 3), 0.1, 4), (6, (2, 1, 2), 0.0, 4), (6, (1, 2, 2), 0.1, 4)])
 def test_entropy_conservation_node_layout(orc, esdg, p, n, warp, variant):
     """Entropy-conservative volume and surface fluxes in the node layout
     (tile variant 3, one lane per node; every pair evaluated from both of its
@@ -328,7 +328,8 @@ PAIR_CASES = [
     (4, (3, 1, 1), 0.1, "ranocha", "llf"),
     (5, (2, 1, 2), 0.1, "ranocha", "ranocha"),
     (6, (1, 2, 2), 0.0, "central", "llf"),
-    (6, (2, 1, 1), 0.1, "ranocha", "llf"),
+    (6, (2, 1, 1), 0.1, "ranocha", "llf"),     # FP64 curved at p = 6: one z-plane per wave
+    (6, (1, 1, 3), 0.1, "shima", "ranocha"),
     (7, (2, 1, 2), 0.1, "ranocha", "llf"),
     (7, (2, 2, 1), 0.0, "ranocha", "ranocha"),
     (7, (1, 2, 2), 0.1, "central", "central"),

@@ -52,7 +52,7 @@ def allowlist():
 
 def test_node_and_pair_layouts_do_not_spill(kernels):
     for key, sp in kernels.items():
-        if key[7] in ("1", "2"):  # LAY_NODES, LAY_PAIRS
+        if key[7] in ("1", "2", "3"):  # LAY_NODES, LAY_PAIRS, LAY_PLANES
             assert sp == (0, 0, 0), (key, sp)
 
 

@@ -54,10 +54,11 @@ def test_node_layout_one_node_per_lane(shapes):
 
 
 def test_pair_layout_shape(shapes):
-    """The pair layout: one lane per node; at N = 8 one element of 512 nodes,
-    so each 64-lane wave is one z-plane (the x- and y-lines stay inside a
-    wave); below N = 8 also enough lanes for the lines of one direction,
-    floor(64/N) whole lines per wave.  Two workgroups fit a CU's LDS."""
+    """The pair layout: one lane per node; at N = 8 (and at N = 7 for FP64
+    curved tiles) one element per workgroup and one wave per z-plane (N^2 of
+    its lanes; the x- and y-lines stay inside a wave); otherwise also enough
+    lanes for the lines of one direction, floor(64/N) whole lines per wave.
+    Two workgroups fit a CU's LDS."""
     pairs = [s for s in shapes if s["variant"] == 4]
     assert len(pairs) == 7 * 4
     for s in pairs:
@@ -67,8 +68,8 @@ def test_pair_layout_shape(shapes):
         assert s["threads"] // 64 * (64 // N) >= lines, s
         assert s["threads"] - s["epb"] * s["nn"] < 128, s  # at most one wave more than the nodes need
         assert 2 * s["lds"] <= 160 * 1024, s
-        if N == 8:
-            assert s["epb"] == 1 and s["threads"] == 512 and s["waves"] == 4, s
+        if N == 8 or (N == 7 and s["prec"] == "fp64" and s["mesh"] == 1):  # one z-plane per wave
+            assert s["epb"] == 1 and s["threads"] == 64 * N and s["waves"] == 4, s
 
 
 def test_lds_within_budget(shapes):
