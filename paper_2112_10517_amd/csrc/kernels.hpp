@@ -403,8 +403,9 @@ struct Tile {
   static constexpr int EPB = EPB_;                // elements per block
   static constexpr int LAY = LAY_;
   // lanes per direction (line layout); the node and pair layouts have one
-  // group of lanes: one per node, and in the pair layout below N = 8 also
-  // enough for the lines of one direction packed floor(64/N) to a wave
+  // group of lanes: one per node, in the pair layout with packed lines also
+  // enough for the lines of one direction packed floor(64/N) to a wave, and
+  // in the plane layouts N waves of 64 lanes
   static constexpr int NODE_LANES = ((EPB * NN + 63) / 64) * 64;
   static constexpr int LPW = 64 / N;  // pair layout: whole lines per wave
   static constexpr int PAIR_LANES = ((EPB * L + LPW - 1) / LPW) * 64;
@@ -459,9 +460,10 @@ constexpr int tile_epb(int dim, int N, int np, int rbytes, int variant) {
     return epb0;
   }
   if (variant == 2) return 2 * epb0 * per <= kTileLdsCap ? 2 * epb0 : epb0;
-  // pair layout (3D): at N = 8 one element (a wave per z-plane); below, the
-  // elements that fill whole waves best with one lane per node and with
-  // floor(64/N) lines per wave
+  // pair layout (3D): from N = 6 one element (at N = 8, and at N = 7 in the
+  // LAY_PLANES tiles, a wave per z-plane); below, the elements that fill
+  // whole waves best with one lane per node and with floor(64/N) lines per
+  // wave
   if (variant == 4) return N >= 6 ? 1 : (N == 5 ? 2 : (N == 4 ? 4 : (N == 3 ? 7 : 16)));
   if (variant == 3) {
     // node layout (LDS: primitives, two direction buffers of halved
@@ -869,8 +871,8 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   // node layout, curved: halved contravariant vectors of two directions
   // (directions 0 and 1, then 2 in the first buffer)
   __shared__ Real s_nrm[CNODE ? EPB : 1][2][DIM][CNODE ? NNL : 1];
-  // pair layout below N = 8: the volume sums of the nodes, merged direction
-  // by direction (the lanes of a direction are not the nodes' own)
+  // pair layout with packed lines: the volume sums of the nodes, merged
+  // direction by direction (the lanes of a direction are not the nodes' own)
   __shared__ Real s_vol[PG ? EPB : 1][NV][PG ? NN : 1];
 
   const int tid = threadIdx.x;
@@ -1090,7 +1092,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
   // direction by direction, and sums the directions in the line layout's order
   Real Sn[NV];
   if constexpr (PG) {
-    // pair layout, N < 8: lane x of a wave takes position x % N of line
+    // pair layout with packed lines: lane x of a wave takes position x % N of line
     // x / N (floor(64/N) whole lines per wave, element-major); per direction
     // the lines' pairs are evaluated once (pair_fluxes, lanes of a line
     // consecutive) and the sums are merged per node in LDS: direction 0
