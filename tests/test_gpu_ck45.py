@@ -32,7 +32,8 @@ def noisy(u, seed, rel=0.01):
     return u * (1 + rel * rng.standard_normal(u.shape))
 
 
-@pytest.mark.parametrize("dim,p,n,warp", [(3, 3, (3, 4, 2), 0.1), (2, 5, (4, 3), 0.0), (3, 7, (2, 1, 2), 0.1)])
+@pytest.mark.parametrize("dim,p,n,warp", [(3, 3, (3, 4, 2), 0.1), (2, 5, (4, 3), 0.0), (3, 7, (2, 1, 2), 0.1),
+                                          (3, 6, (2, 2, 1), 0.1)])
 def test_ck45_steps_vs_oracle(orc, esdg, dim, p, n, warp):
     m = orc.Mesh(dim, p, n, warp=warp, vol_flux="ranocha", surf_flux="llf")
     g = esdg.Problem(dim, p, n, warp=warp, volume_flux="ranocha", surface_flux="llf", integrator="ck45")
