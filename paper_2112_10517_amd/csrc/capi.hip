@@ -13,6 +13,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "problem.hpp"
@@ -124,6 +125,30 @@ VolKernel kernel_of_variant(const esdg_problem* P, int v) {
 
 VolKernel pick_stage_kernel(const esdg_problem* P) {
   return kernel_of_variant(P, P->nodes == NODES_GAUSS ? 0 : tile_variant_of(P));
+}
+
+bool one_generation(const void* fn, int threads, int64_t blocks) {
+  static std::mutex mu;
+  // (device, kernel) -> (compute units, workgroups resident at once)
+  static std::map<std::pair<int, const void*>, std::pair<int64_t, int64_t>> sizes;
+  int dev = 0;
+  if (!fn || hipGetDevice(&dev) != hipSuccess) return false;
+  try {
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_pair(dev, fn);
+    auto it = sizes.find(key);
+    if (it == sizes.end()) {
+      int per_cu = 0, cus = 0;
+      std::pair<int64_t, int64_t> v(0, 0);
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+        v = std::make_pair((int64_t)cus, (int64_t)per_cu * cus);
+      it = sizes.emplace(key, v).first;
+    }
+    return blocks > it->second.first && blocks <= it->second.second;
+  } catch (...) {
+    return false;
+  }
 }
 
 VolKernel pick_projection_kernel(const esdg_problem* P) {

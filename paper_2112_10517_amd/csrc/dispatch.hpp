@@ -10,6 +10,10 @@ struct VolKernel {
   int epb = 0;               // elements per workgroup
   int threads = 0;           // lanes per workgroup
   bool faces_once = false;   // reads f* written by the face kernel when given one
+  // the same stage with the prologue at raised wave priority (stage_kernel
+  // with PRIO), for launches whose workgroups are all resident at once; NULL
+  // if not built for this tile
+  const void* fn_prio = nullptr;
 };
 
 // number of tile variants of the 3D stage kernel (2D has one)

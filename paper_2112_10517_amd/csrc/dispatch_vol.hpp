@@ -21,6 +21,10 @@ VolKernel vol_kernel() {
   k.epb = T::EPB;
   k.threads = T::THREADS;
   k.faces_once = FacesOnce<DIM, N, LAY>::value;
+  // the priority twin of the default 3D line tiles (p <= 3, where launches of
+  // one generation are common)
+  if constexpr (DIM == 3 && N <= 4 && V == 0)
+    k.fn_prio = (const void*)&stage_kernel<DIM, N, VF, MESH, Real, EPB, NODES_LGL, LAY, true>;
   return k;
 }
 

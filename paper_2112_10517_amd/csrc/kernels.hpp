@@ -834,7 +834,15 @@ struct StageWaves {
   static constexpr int value = (LAY != LAY_LINES && sizeof(Real) == 8 && N <= 5) ? 3 : Tile<DIM, N, EPB_, LAY>::WPE;
 };
 
-template <int DIM, int N, int VF, int MESH, typename Real, int EPB_, int NODES = NODES_LGL, int LAY = LAY_LINES>
+// PRIO: the prologue and the surface fluxes run at raised wave priority.  The
+// host launches this form only where all the launch's workgroups are resident
+// at once (one generation, more than one workgroup per compute unit): the
+// workgroups dispatched last then set up their tiles ahead of the volume
+// work of those dispatched first, which shortens the launch's tail.  With
+// workgroups queued behind the resident ones, or one per compute unit, the
+// same priority measured slower.
+template <int DIM, int N, int VF, int MESH, typename Real, int EPB_, int NODES = NODES_LGL, int LAY = LAY_LINES,
+          bool PRIO = false>
 __global__ void __launch_bounds__((Tile<DIM, N, EPB_, LAY>::THREADS))
 __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::value))) stage_kernel(StageArgs<Real> a) {
   static_assert(NODES == NODES_LGL || MESH == MESH_AFFINE, "Gauss collocation is built for affine meshes");
@@ -1030,6 +1038,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     }
   }
 
+  if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
   // ---- prologue: primitive variables and logs once per node into LDS
 #pragma unroll
   for (int r = 0; r < NPT; ++r) {
@@ -1087,6 +1096,7 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
     for (int v = 0; v < NV; ++v) s_face[el][v][rr] = F[v];
   }
   __syncthreads();
+  if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
 
   // ---- volume term, node layout: each lane sweeps the partners of its node,
   // direction by direction, and sums the directions in the line layout's order

@@ -189,6 +189,12 @@ ProbDesc<Real> prob_desc(const esdg_problem* P, int tile0, double t_end) {
   return d;
 }
 
+// Whether a launch of `blocks` workgroups of kernel fn (`threads` lanes each)
+// is one generation of more than one workgroup per compute unit on the
+// current device: all resident at once, by the runtime's occupancy query
+// (cached per device and kernel).  False if the query fails.
+bool one_generation(const void* fn, int threads, int64_t blocks);
+
 // Legendre-Gauss problems: the entropy-projection kernel that must precede
 // every stage launch (same tiles and descriptors); fn == NULL for LGL
 VolKernel pick_projection_kernel(const esdg_problem* P);
@@ -240,7 +246,8 @@ esdg_status run_stage_on(const esdg_problem* rep, const Launcher& L, const VolKe
     ESDG_TRY(launch_kernel(L, ESDG_KERNEL_FACE, fk, dim3((unsigned)((lanes + kFaceThreads - 1) / kFaceThreads)),
                            dim3(kFaceThreads), args));
   }
-  return launch_kernel(L, ESDG_KERNEL_STAGE, k.fn, dim3((unsigned)tiles), dim3(k.threads), args);
+  const void* fn = k.fn_prio && one_generation(k.fn_prio, k.threads, tiles) ? k.fn_prio : k.fn;
+  return launch_kernel(L, ESDG_KERNEL_STAGE, fn, dim3((unsigned)tiles), dim3(k.threads), args);
 }
 
 // FP64 reduction of op over P's state (and DU for the entropy rate) on L's

@@ -8,7 +8,8 @@ LDS since.  This test keeps spills from coming back unnoticed:
   * the node and pair layouts (tile variants 3 and 4) spill nothing;
   * no LGL tile at N = 8 spills scalar registers;
   * any other spilling instantiation is listed in tests/data/spill_allowlist.txt
-    with its largest allowed scratch use and spill counts, which must not grow.
+    with its largest allowed scratch use and spill counts, which must not grow;
+  * the raised-priority form of a tile (PRIO) spills no more than the tile.
 """
 import os
 import re
@@ -18,15 +19,16 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 REPORT = os.path.join(ROOT, "paper_2112_10517_amd", "lib", "resource_usage.txt")
 ALLOW = os.path.join(ROOT, "tests", "data", "spill_allowlist.txt")
-PAT = re.compile(r"stage_kernelILi(\d)ELi(\d)ELi(\d)ELi(\d)E([df])Li(\d+)ELi(\d)ELi(\d)E")
+PAT = re.compile(r"stage_kernelILi(\d)ELi(\d)ELi(\d)ELi(\d)E([df])Li(\d+)ELi(\d)ELi(\d)ELb([01])E")
 
 
-@pytest.fixture(scope="module")
-def kernels():
+def read_report():
+    """({8 template arguments: spills} of the stage kernels, the same of their
+    raised-priority forms (PRIO = true)); spills = (scratch, VGPR, SGPR)."""
     if not os.path.exists(REPORT):
         from paper_2112_10517_amd import build
         build.build()
-    out = {}
+    plain, prio = {}, {}
     with open(REPORT) as f:
         for line in f:
             name, *kv = line.split()
@@ -34,9 +36,15 @@ def kernels():
             if not m:
                 continue
             d = dict(x.split("=", 1) for x in kv)
-            out[m.groups()] = (int(d["ScratchSize_[bytes/lane]"]), int(d["VGPRs_Spill"]), int(d["SGPRs_Spill"]))
-    assert len(out) > 400, "resource report incomplete: %d stage kernels" % len(out)
-    return out
+            sp = (int(d["ScratchSize_[bytes/lane]"]), int(d["VGPRs_Spill"]), int(d["SGPRs_Spill"]))
+            (prio if m.group(9) == "1" else plain)[m.groups()[:8]] = sp
+    assert len(plain) > 400, "resource report incomplete: %d stage kernels" % len(plain)
+    return plain, prio
+
+
+@pytest.fixture(scope="module")
+def kernels():
+    return read_report()[0]
 
 
 def allowlist():
@@ -70,3 +78,14 @@ def test_spills_only_where_allowed(kernels):
         assert key in allow, "stage kernel %s spills %s and is not in the allowlist" % (key, sp)
         lim = allow[key]
         assert all(a <= b for a, b in zip(sp, lim)), "stage kernel %s spills %s, more than %s" % (key, sp, lim)
+
+
+def test_priority_forms_match_their_tiles():
+    # the raised-priority form exists for the default 3D LGL line tiles up to
+    # N = 4 only, and spills no more than the plain kernel of its tile
+    plain, prio = read_report()
+    assert prio, "no raised-priority stage kernels in the report"
+    for key, sp in prio.items():
+        assert key[0] == "3" and int(key[1]) <= 4 and key[6] == "0" and key[7] == "0", key
+        assert key in plain, key
+        assert all(a <= b for a, b in zip(sp, plain[key])), (key, sp, plain[key])
