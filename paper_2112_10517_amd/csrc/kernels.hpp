@@ -834,13 +834,16 @@ struct StageWaves {
   static constexpr int value = (LAY != LAY_LINES && sizeof(Real) == 8 && N <= 5) ? 3 : Tile<DIM, N, EPB_, LAY>::WPE;
 };
 
-// PRIO: the prologue and the surface fluxes run at raised wave priority.  The
-// host launches this form only where all the launch's workgroups are resident
-// at once (one generation, more than one workgroup per compute unit): the
-// workgroups dispatched last then set up their tiles ahead of the volume
-// work of those dispatched first, which shortens the launch's tail.  With
-// workgroups queued behind the resident ones, or one per compute unit, the
-// same priority measured slower.
+// PRIO, the one-generation form: the prologue and the surface fluxes run at
+// raised wave priority, and the RK4 stage results are stored with the
+// nontemporal hint.  The host launches this form only where all the
+// launch's workgroups are resident at once (one generation, more than one
+// workgroup per compute unit): the workgroups dispatched last then set up
+// their tiles ahead of the volume work of those dispatched first, which
+// shortens the launch's tail, and the results stream out without displacing
+// the inputs from the caches.  With workgroups queued behind the resident
+// ones, or one per compute unit, the same priority measured slower and the
+// hint gained nothing or lost.
 template <int DIM, int N, int VF, int MESH, typename Real, int EPB_, int NODES = NODES_LGL, int LAY = LAY_LINES,
           bool PRIO = false>
 __global__ void __launch_bounds__((Tile<DIM, N, EPB_, LAY>::THREADS))
@@ -1369,11 +1372,21 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
         // the stage input is read again (an L2 hit) rather than kept live in
         // registers through the line phase
         const Real u_in = uin[o];
-        racc_buf[o] = u_in + a.coef_b * (Real)dt * k;
-        out[o] = u_in + a.coef_a * (Real)dt * k;
+        if constexpr (PRIO) {
+          __builtin_nontemporal_store(u_in + a.coef_b * (Real)dt * k, racc_buf + o);
+          __builtin_nontemporal_store(u_in + a.coef_a * (Real)dt * k, out + o);
+        } else {
+          racc_buf[o] = u_in + a.coef_b * (Real)dt * k;
+          out[o] = u_in + a.coef_a * (Real)dt * k;
+        }
       } else if (a.mode == MODE_RK_MID) {
-        racc_buf[o] = racc[r][v] + a.coef_b * (Real)dt * k;
-        out[o] = ru0[r][v] + a.coef_a * (Real)dt * k;
+        if constexpr (PRIO) {
+          __builtin_nontemporal_store(racc[r][v] + a.coef_b * (Real)dt * k, racc_buf + o);
+          __builtin_nontemporal_store(ru0[r][v] + a.coef_a * (Real)dt * k, out + o);
+        } else {
+          racc_buf[o] = racc[r][v] + a.coef_b * (Real)dt * k;
+          out[o] = ru0[r][v] + a.coef_a * (Real)dt * k;
+        }
       } else if (a.mode >= MODE_LS_FIRST) {
         // 2N storage: the accumulator holds du
         const Real d = a.mode == MODE_LS_FIRST ? (Real)dt * k : a.coef_a * racc[r][v] + (Real)dt * k;
@@ -1382,7 +1395,8 @@ __attribute__((amdgpu_waves_per_eu(StageWaves<DIM, N, MESH, Real, EPB_, LAY>::va
         out[o] = unew[v];
       } else {
         unew[v] = racc[r][v] + a.coef_b * (Real)dt * k;
-        out[o] = unew[v];
+        if constexpr (PRIO) __builtin_nontemporal_store(unew[v], out + o);
+        else out[o] = unew[v];
       }
     }
     if (lam_out) {
