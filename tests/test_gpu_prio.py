@@ -1,12 +1,13 @@
-"""The raised-priority form of the line tiles gives the bits of the plain kernel.
+"""The one-generation form of the line tiles gives the bits of the plain kernel.
 
 A launch whose workgroups are all resident at once (one generation, more
 than one workgroup per compute unit) runs the form of tile variant 0 whose
-prologue and surface fluxes execute at raised wave priority.  On a 256-CU
+prologue and surface fluxes execute at raised wave priority and whose RK
+stage results are stored with the nontemporal hint.  On a 256-CU
 MI355X the 16^3 p = 3 launches (1,024 workgroups of 4 elements, four
 resident per CU), the 12^3 p = 3 launches (432) and the 16^3 p = 2 launches
 (586 workgroups of 7 elements) are such launches.  Tile variant 2 (twice the
-elements per workgroup) has no raised-priority form and adds the same terms
+elements per workgroup) has no one-generation form and adds the same terms
 in the same order, so right-hand sides, states and CFL times must agree bit
 for bit.  Inputs are seeded and synthetic.
 """

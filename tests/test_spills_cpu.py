@@ -9,7 +9,7 @@ LDS since.  This test keeps spills from coming back unnoticed:
   * no LGL tile at N = 8 spills scalar registers;
   * any other spilling instantiation is listed in tests/data/spill_allowlist.txt
     with its largest allowed scratch use and spill counts, which must not grow;
-  * the raised-priority form of a tile (PRIO) spills no more than the tile.
+  * the one-generation form of a tile (PRIO) spills no more than the tile.
 """
 import os
 import re
@@ -24,7 +24,7 @@ PAT = re.compile(r"stage_kernelILi(\d)ELi(\d)ELi(\d)ELi(\d)E([df])Li(\d+)ELi(\d)
 
 def read_report():
     """({8 template arguments: spills} of the stage kernels, the same of their
-    raised-priority forms (PRIO = true)); spills = (scratch, VGPR, SGPR)."""
+    one-generation forms (PRIO = true)); spills = (scratch, VGPR, SGPR)."""
     if not os.path.exists(REPORT):
         from paper_2112_10517_amd import build
         build.build()
@@ -81,10 +81,10 @@ def test_spills_only_where_allowed(kernels):
 
 
 def test_priority_forms_match_their_tiles():
-    # the raised-priority form exists for the default 3D LGL line tiles up to
+    # the one-generation form exists for the default 3D LGL line tiles up to
     # N = 4 only, and spills no more than the plain kernel of its tile
     plain, prio = read_report()
-    assert prio, "no raised-priority stage kernels in the report"
+    assert prio, "no one-generation stage kernels in the report"
     for key, sp in prio.items():
         assert key[0] == "3" and int(key[1]) <= 4 and key[6] == "0" and key[7] == "0", key
         assert key in plain, key
