@@ -29,20 +29,22 @@ def esdg():
 
 
 CASES = [
-    # p, n, warp, precision
-    (3, (16, 16, 16), 0.1, "fp64"),
-    (3, (16, 16, 16), 0.0, "fp64"),
-    (3, (16, 16, 16), 0.1, "fp32"),
-    (3, (12, 12, 12), 0.1, "fp64"),
-    (2, (16, 16, 16), 0.1, "fp64"),
+    # p, n, warp, precision, integrator
+    (3, (16, 16, 16), 0.1, "fp64", "rk4"),
+    (3, (16, 16, 16), 0.0, "fp64", "rk4"),
+    (3, (16, 16, 16), 0.1, "fp32", "rk4"),
+    (3, (12, 12, 12), 0.1, "fp64", "rk4"),
+    (2, (16, 16, 16), 0.1, "fp64", "rk4"),
+    (3, (16, 16, 16), 0.1, "fp64", "ck45"),  # 2N-storage stages (plain stores in both forms)
 ]
 
 
-@pytest.mark.parametrize("p,n,warp,prec", CASES)
-def test_priority_form_equals_plain_tile(esdg, p, n, warp, prec):
-    label = "priority form p=%d %s warp %.1f %s" % (p, n, warp, prec)
+@pytest.mark.parametrize("p,n,warp,prec,integrator", CASES)
+def test_priority_form_equals_plain_tile(esdg, p, n, warp, prec, integrator):
+    label = "one-generation form p=%d %s warp %.1f %s %s" % (p, n, warp, prec, integrator)
     print(label, flush=True)
-    g = esdg.Problem(3, p, n, warp=warp, volume_flux="ranocha", surface_flux="llf", precision=prec)
+    g = esdg.Problem(3, p, n, warp=warp, volume_flux="ranocha", surface_flux="llf", precision=prec,
+                     integrator=integrator)
     u = inputs.random_fourier(g.coords(), 7)
     v_before = g.tile_variant()[0]
     out = {}
